@@ -1,0 +1,278 @@
+"""CPU reference of the spectrum sweeping method (SS-DGC) in float64.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  The HIP library never
+calls it and shares no code with it.
+
+Paper: L. Lin, "Randomized estimation of spectral densities of large matrices
+made accurate" (arXiv:1504.07690).  Every function follows one passage of the
+paper, in its order and notation; numpy/scipy routines serve only as library
+primitives (FFT, dense symmetric eigensolver, sparse matrix times block, erf).
+
+Units.  The paper assumes spec(A) in (-1, 1).  For a general matrix it applies
+the affine map A~ = (2A - (lo+hi)I)/(hi-lo) (Section 2).  Here A, the sweep
+points t and the smearing sigma stay in A's units; the Chebyshev expansion is
+taken in the rescaled variable, i.e. the expanded function is
+s -> g_sigma(t - x(s)) with x(s) = c0 + hw*s, c0 = (lo+hi)/2, hw = (hi-lo)/2.
+
+Readings where the paper is silent (each also listed in the design notes):
+* N_theta of Algorithm 1: 2*N_theta is the least power of two >= 4(M+1).
+* Algorithm 5 applies A once more after the last accumulation (l = M); that
+  product is never used and is not computed.
+* W^* Z is symmetric in exact arithmetic (Section 3.1); it is symmetrised as
+  (W^T Z + Z^T W)/2 before the eigen-decomposition of Algorithm 4.
+* Algorithm 4, step 2 keeps s_j >= tau * max_i s_i (inclusive); if
+  max_i s_i <= 0 nothing is kept and the estimate is 0.
+* Algorithm 4, step 4 keeps xi in [0, (1 + rho) / (N sqrt(2 pi sigma^2))]
+  (closed interval, relative slack rho, default 1e-3).
+* Algorithm 8 deconvolves with the unit-mass Gaussian (N times g_sigma),
+  periodically on [-1, 1] in the rescaled variable, dropping wavenumbers k
+  with exp(-(sigma^ pi k)^2 / 2) < eta (eta = 1e-10).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.special as sps
+
+
+# ----------------------------------------------------------------------------
+# Section 2: Gaussian regularisation and the exact regularised DOS
+# ----------------------------------------------------------------------------
+def g_sigma(s, sigma: float, n: int):
+    """Eq. (gaussian): g_sigma(s) = exp(-s^2 / (2 sigma^2)) / (N sqrt(2 pi sigma^2))."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.exp(-s * s / (2.0 * sigma * sigma)) / (n * math.sqrt(2.0 * math.pi * sigma * sigma))
+
+
+def exact_dos(eigenvalues, t, sigma: float, n: int | None = None):
+    """phi_sigma(t) = sum_i g_sigma(t - lambda_i) (Section 2), from eigenvalues."""
+    lam = np.asarray(eigenvalues, dtype=np.float64)
+    n = lam.size if n is None else n
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    out = np.empty(t.shape)
+    for k in range(0, t.size, 256):
+        out[k:k + 256] = g_sigma(t[k:k + 256, None] - lam[None, :], sigma, n).sum(axis=1)
+    return out
+
+
+def range_bound(sigma: float, n: int) -> float:
+    """Largest value of g_sigma: 1 / (N sqrt(2 pi sigma^2)) (Section 3.2)."""
+    return 1.0 / (n * math.sqrt(2.0 * math.pi * sigma * sigma))
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1: Delta-Gauss-Chebyshev coefficients
+# ----------------------------------------------------------------------------
+def n_theta_for(degree: int) -> int:
+    """N_theta > M (Algorithm 1); taken so that 2 N_theta = 2^ceil(log2(4(M+1)))."""
+    two_nt = 1
+    while two_nt < 4 * (degree + 1):
+        two_nt *= 2
+    return two_nt // 2
+
+
+def dgc_coefficients(t, degree: int, sigma: float, n: int, lo: float, hi: float,
+                     n_theta: int | None = None) -> np.ndarray:
+    """mu_l(t_i), l = 0..M, for every sweep point (Algorithm 1, Eq. mucoef2).
+
+    theta_j = j pi / N_theta (j < 2 N_theta); g_j = g_sigma(t - x(cos theta_j));
+    g^ = DFT(g); mu_l = (2 - delta_l0) / (2 N_theta) Re g^_l.
+    Returns an array of shape (M + 1, N_t).
+    """
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    n_theta = n_theta_for(degree) if n_theta is None else n_theta
+    assert n_theta > degree
+    c0, hw = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    theta = np.arange(2 * n_theta) * math.pi / n_theta
+    x = c0 + hw * np.cos(theta)
+    g = g_sigma(t[None, :] - x[:, None], sigma, n)          # (2 N_theta, N_t)
+    ghat = np.fft.fft(g, axis=0)                             # sum_j e^{-i 2 pi j l / 2N_theta} g_j
+    mu = ghat[: degree + 1].real / (2 * n_theta)
+    mu[1:] *= 2.0
+    return mu
+
+
+def chebyshev_eval(mu: np.ndarray, s) -> np.ndarray:
+    """sum_l mu_l T_l(s) by the three-term recurrence (Eq. gcheb) at scalar points s."""
+    s = np.asarray(s, dtype=np.float64)
+    t_prev, t_cur = np.ones_like(s), s.copy()
+    out = mu[0] * t_prev
+    if mu.shape[0] > 1:
+        out = out + mu[1] * t_cur
+    for l in range(2, mu.shape[0]):
+        t_prev, t_cur = t_cur, 2.0 * s * t_cur - t_prev
+        out = out + mu[l] * t_cur
+    return out
+
+
+# ----------------------------------------------------------------------------
+# The three-term recurrence of Algorithms 2 and 5 on one block W
+# ----------------------------------------------------------------------------
+def _as_scipy(a):
+    if sp.issparse(a):
+        return a.tocsr()
+    if hasattr(a, "to_scipy"):
+        return a.to_scipy()
+    return sp.csr_matrix(np.asarray(a, dtype=np.float64))
+
+
+def chebyshev_blocks(a, w: np.ndarray, degree: int, lo: float, hi: float):
+    """Yield (l, V_c) with V_c = T_l(A~) W for l = 0..M (Algorithm 5, steps 3-11).
+
+    V_m, V_c <- 0, W; after the accumulations of step l:
+    V_p <- (2 - delta_l0) A~ V_c - V_m; V_m <- V_c; V_c <- V_p,
+    where A~ = (2A - (lo+hi) I)/(hi - lo) (Section 2).  The product that would
+    follow the last accumulation (l = M) is not computed.
+    """
+    a = _as_scipy(a)
+    alpha = 2.0 / (hi - lo)
+    beta = -(hi + lo) / (hi - lo)
+    v_m = np.zeros_like(w, dtype=np.float64)
+    v_c = np.asarray(w, dtype=np.float64).copy()
+    for l in range(degree + 1):
+        yield l, v_c
+        if l == degree:
+            break
+        a_vc = alpha * (a @ v_c) + beta * v_c
+        v_p = (2.0 if l > 0 else 1.0) * a_vc - v_m
+        v_m, v_c = v_c, v_p
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2: DGC (Hutchinson-type) estimate, for comparison
+# ----------------------------------------------------------------------------
+def dgc_dos(a, w, t, degree, sigma, lo, hi):
+    """zeta_l = Tr[W^* T_l(A~) W] / N_v; phi~(t_i) = sum_l mu_l(t_i) zeta_l (Algorithm 2)."""
+    n, nv = w.shape
+    mu = dgc_coefficients(t, degree, sigma, n, lo, hi)
+    zeta = np.zeros(degree + 1)
+    for l, v_c in chebyshev_blocks(a, w, degree, lo, hi):
+        zeta[l] = np.sum(w * v_c) / nv
+    return mu.T @ zeta
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 4: generalised eigenvalue problem, truncated
+# ----------------------------------------------------------------------------
+def geneig_trace(k_w: np.ndarray, k_z: np.ndarray, g_max: float, tau: float = 1e-7,
+                 rho: float = 1e-3, return_parts: bool = False):
+    """Tr Xi~ for the pencil (Z^*Z, W^*Z) of one sweep point (Algorithm 4).
+
+    1. W^*Z = U S U^*.
+    2. keep s_j >= tau max_i s_i  (S~, U~).
+    3. eig of S~^{-1/2} U~^* Z^*Z U~ S~^{-1/2}  -> xi.
+    4. keep xi in [0, (1 + rho) g_max].
+    Returns the sum of kept xi and the two kept counts (r1, r2).
+    """
+    k_w = 0.5 * (k_w + k_w.T)
+    s, u = np.linalg.eigh(k_w)
+    smax = s.max() if s.size else 0.0
+    if not smax > 0.0:
+        out = (0.0, 0, 0)
+        return out + ({"s": s, "xi": np.zeros(0)},) if return_parts else out
+    keep = s >= tau * smax
+    u_t = u[:, keep] / np.sqrt(s[keep])[None, :]
+    b = u_t.T @ k_z @ u_t
+    xi = np.linalg.eigvalsh(0.5 * (b + b.T))
+    in_range = (xi >= 0.0) & (xi <= (1.0 + rho) * g_max)
+    out = (float(xi[in_range].sum()), int(keep.sum()), int(in_range.sum()))
+    return out + ({"s": s, "xi": xi},) if return_parts else out
+
+
+def gram(w: np.ndarray, z: np.ndarray):
+    """K_W = (W^T Z + Z^T W)/2 and K_Z = Z^T Z for one sweep point (Eq. tracelr)."""
+    wz = w.T @ z
+    return 0.5 * (wz + wz.T), z.T @ z
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 5: SS-DGC
+# ----------------------------------------------------------------------------
+def ss_dgc(a, w, t, degree: int, sigma: float, lo: float, hi: float, tau: float = 1e-7,
+           rho: float = 1e-3, points=None, keep=False, mu=None):
+    """Spectrum sweeping estimate of phi_sigma at the sweep points (Algorithm 5).
+
+    ``points`` selects a subset of the sweep points (the points are
+    independent once the T_l(A~) W are known).  Returns a dict with the DOS
+    estimate ``dos`` (A's units), the kept counts ``r1``, ``r2`` and, if
+    ``keep``, the blocks Z(t_i) and the Gram matrices.
+    """
+    w = np.asarray(w, dtype=np.float64)
+    n, nv = w.shape
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    sel = np.arange(t.size) if points is None else np.asarray(points)
+    if mu is None:
+        mu = dgc_coefficients(t[sel], degree, sigma, n, lo, hi)          # step 1
+    else:
+        mu = np.asarray(mu)[:, sel]
+    z = np.zeros((sel.size, n, nv))                                      # step 4
+    for l, v_c in chebyshev_blocks(a, w, degree, lo, hi):                # steps 3, 5-11
+        for i in range(sel.size):
+            z[i] += mu[l, i] * v_c
+    g_max = range_bound(sigma, n)
+    dos = np.zeros(sel.size)
+    r1 = np.zeros(sel.size, dtype=np.int64)
+    r2 = np.zeros(sel.size, dtype=np.int64)
+    kws, kzs = [], []
+    for i in range(sel.size):                                            # steps 12-14
+        k_w, k_z = gram(w, z[i])
+        dos[i], r1[i], r2[i] = geneig_trace(k_w, k_z, g_max, tau, rho)
+        if keep:
+            kws.append(k_w)
+            kzs.append(k_z)
+    out = {"dos": dos, "r1": r1, "r2": r2, "mu": mu, "points": sel}
+    if keep:
+        out.update(z=z, k_w=np.array(kws), k_z=np.array(kzs))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Section 5, Algorithm 8: trace of a matrix function from the DOS
+# ----------------------------------------------------------------------------
+def window(t, a: float, sigma_tilde: float):
+    """pi(t) of Eq. (pifunc): 1 on (-a, a), smoothly 0 near +-1."""
+    t = np.asarray(t, dtype=np.float64)
+    return 0.5 * (sps.erf((1.0 + a - 2.0 * t) / sigma_tilde)
+                  - sps.erf((-1.0 - a - 2.0 * t) / sigma_tilde))
+
+
+def periodic_extension(f, t_hat, lo: float, hi: float, a: float, sigma_tilde: float):
+    """h(t) = f(t) pi(t) + c (1 - pi(t)) (Eq. hform), in the rescaled variable.
+
+    c is taken as (f(x(-a)) + f(x(a)))/2: the paper notes the constant is
+    arbitrary, and f need not be defined at the ends of [lo, hi].  f is only
+    evaluated where pi(t) > 1e-300.
+    """
+    c0, hw = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    pi_t = window(t_hat, a, sigma_tilde)
+    c = 0.5 * (f(c0 - hw * a) + f(c0 + hw * a))
+    h = np.full(t_hat.shape, c, dtype=np.float64)
+    m = pi_t > 1e-300
+    h[m] = f(c0 + hw * t_hat[m]) * pi_t[m] + c * (1.0 - pi_t[m])
+    return h
+
+
+def trace_weights(f, n: int, lo: float, hi: float, nt: int, sigma: float, a: float = 0.9,
+                  sigma_tilde: float = 0.016, eta: float = 1e-10):
+    """Weights w_i with Tr f(A) ~= sum_i w_i phi~(t_i) (Algorithm 8).
+
+    Grid: the nt midpoints t^_i of [-1, 1] (rescaled), t_i = c0 + hw t^_i.
+    f~ solves (f~ * G) = h periodically on [-1, 1], G the unit-mass Gaussian
+    of width sigma^ = sigma/hw (the deconvolution of Eq. deconvolv by Fourier
+    transform); Tr f(A) ~= N dt^ sum_i f~(t^_i) phi^(t^_i), and phi^ = hw phi
+    in A's units, so w_i = N dt^ hw f~_i.
+    """
+    hw = 0.5 * (hi - lo)
+    sh = sigma / hw
+    t_hat = -1.0 + (2.0 * np.arange(nt) + 1.0) / nt
+    h = periodic_extension(f, t_hat, lo, hi, a, sigma_tilde)
+    k = np.fft.fftfreq(nt, d=1.0 / nt)                  # integer wavenumbers, period 2
+    gk = np.exp(-0.5 * (sh * math.pi * k) ** 2)
+    k_c = math.floor(math.sqrt(2.0 * math.log(1.0 / eta)) / (math.pi * sh))
+    hk = np.fft.fft(h)
+    fk = np.where(np.abs(k) <= k_c, hk / gk, 0.0)
+    f_tilde = np.fft.ifft(fk).real
+    return n * (2.0 / nt) * hw * f_tilde
