@@ -1,0 +1,187 @@
+"""Benchmark of the spectrum sweeping DOS (Algorithm 5) on one MI355X.
+
+Workload: the 3D Anderson model on a 64^3 periodic lattice (N = 262144, hopping -1,
+disorder uniform in [-2, 2]), N_v = 80, Chebyshev degree M = 1000, N_t = 1000
+midpoint sweep points, sigma = 0.01 in the rescaled variable; FP32 recurrence and
+sweep, FP64 Gram / Algorithm 4.  One step = one full ssm_dos (coefficients and W
+are set up once, outside the timed region).
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16|fp64]
+                    [--no-fp64] [--no-bf16] [--no-cpu-baseline]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Cheb block-SpMM GB/s (% HBM peak); SSM DOS time at fixed L1 error"
+HBM_PEAK_GBPS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, sample_steps=30, sample_points=2):
+    """The oracle, as it stands, on a bounded sample of the same workload, one thread;
+    extrapolated to the full DOS (seconds per DOS)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ssm_oracle as O
+    with threadpool_limits(1):
+        w = wl.w()
+        pts = np.linspace(0, wl.nt - 1, sample_points).astype(int)
+        t0 = time.perf_counter()
+        mu = O.dgc_coefficients(wl.t[pts], wl.degree, wl.sigma, wl.a.n, wl.lo, wl.hi)
+        t_coef = (time.perf_counter() - t0) / sample_points
+        blocks = []
+        t0 = time.perf_counter()
+        for l, v in O.chebyshev_blocks(wl.a, w, sample_steps, wl.lo, wl.hi):
+            blocks.append(v)
+        t_step = (time.perf_counter() - t0) / sample_steps
+        t0 = time.perf_counter()
+        z = O.sweep(mu[: sample_steps + 1], iter(blocks))
+        t_axpy = (time.perf_counter() - t0) / ((sample_steps + 1) * sample_points)
+        t0 = time.perf_counter()
+        g_max = O.range_bound(wl.sigma, wl.a.n)
+        for i in range(sample_points):
+            kw, kz = O.gram(w, z[i])
+            O.geneig_trace(kw, kz, g_max)
+        t_point = (time.perf_counter() - t0) / sample_points
+    m1 = wl.degree + 1
+    total = t_coef * wl.nt + t_step * wl.degree + t_axpy * m1 * wl.nt + t_point * wl.nt
+    return {
+        "value": total, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"{sample_steps} Chebyshev steps, the sweep of {sample_points} points over them, "
+                   f"Gram + Algorithm 4 for {sample_points} points; extrapolated to M={wl.degree}, "
+                   f"N_t={wl.nt}: coeff {t_coef:.3g} s/point, step {t_step:.3g} s, axpy {t_axpy:.3g} s, "
+                   f"Gram+eig {t_point:.3g} s/point"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the sweep-point batches would shard across GPUs with no "
+              "communication until a final gather, and that path is not built; use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1504_07690_amd import ssm as S
+    from paper_1504_07690_amd import workloads as WL
+
+    dev = "cuda:0"
+    t0 = time.time()
+    wl = WL.make_workload(2)
+    log(f"workload {wl.name}: n={wl.a.n} nnz={wl.a.nnz} nv={wl.nv} M={wl.degree} nt={wl.nt} "
+        f"[{wl.lo:.4f}, {wl.hi:.4f}] ({time.time() - t0:.1f} s)")
+    n, nv, m = wl.a.n, wl.nv, wl.degree
+    e = n * nv
+
+    def run(precision, steps, warmup, budget=0):
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=dev)
+        ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=wl.t, precision=precision,
+                    seed=wl.seed, budget=budget, device=dev)
+        for _ in range(warmup):
+            ctx.dos()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            dos, r1, r2 = ctx.dos()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t_start) * 1e3 / max(steps, 1)
+        st = ctx.stats()
+        ctx.close()
+        del ctx, csr
+        torch.cuda.empty_cache()
+        log(f"{precision}: {ms:.1f} ms/DOS  phases {st}")
+        return ms, dos, r1, r2, st
+
+    def budget_left():
+        free, _ = torch.cuda.mem_get_info()
+        return int(free - 6 * (1 << 30))
+
+    ms, dos, r1, r2, st = run(args.precision, args.steps, args.warmup, budget=0)
+    es = 8 if args.precision == "fp64" else 4
+
+    # Chebyshev block-SpMM: compulsory bytes per launch = Y_k, Y_{k-1} read, Y_{k+1}
+    # written, CSR read once
+    spmm_bytes = 3 * e * es + wl.a.nnz * (4 + es) + (n + 1) * 4
+    spmm_us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
+    spmm_gbps = spmm_bytes / (spmm_us * 1e-6) / 1e9
+    # sweep GEMM: 2 e (M+1) N_t flops
+    sweep_flops = 2.0 * e * (m + 1) * wl.nt
+    sweep_tflops = sweep_flops / (st["ms_sweep"] * 1e-3) / 1e12
+    gram_flops = 3.0 * n * nv * nv * wl.nt  # W^T Z (2 n nv^2) + the symmetric Z^T Z (n nv^2), per point
+    phases = {k: st[k] for k in ("ms_total", "ms_recurrence", "ms_sweep", "ms_gram", "ms_geneig")}
+    dom = max(("sweep", st["ms_sweep"]), ("spmm", st["ms_recurrence"]), ("gram", st["ms_gram"]),
+              key=lambda kv: kv[1])[0]
+    if dom == "sweep":
+        per_launch_ms = st["ms_sweep"] / st["sweep_launches"]
+        roof = {"kernel": f"sweep_{args.precision}_kernel", "bound": "mfma",
+                "achieved": sweep_flops / st["sweep_launches"] / (per_launch_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TFLOPS[args.precision], "unit": "TFLOP/s", "traffic": None}
+    elif dom == "spmm":
+        roof = {"kernel": "cheb_step_kernel", "bound": "hbm", "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "traffic": None}
+    else:
+        roof = {"kernel": "gram_kernel", "bound": "mfma",
+                "achieved": gram_flops / (st["ms_gram"] * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["fp64"],
+                "unit": "TFLOP/s", "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+
+    out = {
+        "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "nnz": wl.a.nnz, "nv": nv, "degree": m, "nt": wl.nt,
+                   "sigma_hat": wl.sigma_hat, "recurrence_sweep": args.precision, "gram_eig": "fp64",
+                   "plan": {"passes": st["passes"], "chunk": st["chunk"], "batch": st["batch"]}},
+        "spmm": {"GBps": spmm_gbps, "frac_hbm": spmm_gbps / HBM_PEAK_GBPS, "bytes_per_launch": spmm_bytes,
+                 "us_per_launch": spmm_us, "launches": st["spmm_launches"]},
+        "sweep": {"TFLOPs": sweep_tflops, "frac_mfma": sweep_tflops / MFMA_PEAK_TFLOPS[args.precision]},
+        "phases_ms": phases,
+        "roofline": roof,
+    }
+
+    comparisons = {}
+    if not args.no_fp64 and args.precision != "fp64":
+        ms64, dos64, *_ = run("fp64", 1, 1, budget=budget_left())
+        l1 = float(np.abs(dos - dos64).sum() / np.abs(dos64).sum())
+        comparisons["fp64"] = {"s_per_dos": ms64 / 1e3, "speedup_of_measured_path": ms64 / ms,
+                               "dos_l1_measured_vs_fp64": l1}
+        if not args.no_bf16 and args.precision != "bf16":
+            msb, dosb, *_ = run("bf16", 1, 1, budget=0)
+            comparisons["bf16"] = {"s_per_dos": msb / 1e3,
+                                   "dos_l1_vs_fp64": float(np.abs(dosb - dos64).sum() / np.abs(dos64).sum())}
+    out["comparisons"] = comparisons
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

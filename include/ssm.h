@@ -1,0 +1,221 @@
+/*
+ * ssm.h -- C ABI of libssm: the spectrum sweeping method (SS-DGC) for the
+ * Gaussian-regularised density of states of a sparse real symmetric matrix,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: L. Lin, "Randomized estimation of spectral densities of large
+ * matrices made accurate", arXiv:1504.07690.  Algorithm numbers below refer to
+ * that paper.
+ *
+ * Conventions shared by every call
+ *  - Every call returns an ssm_status; nothing is thrown across the ABI.  On
+ *    error the outputs are left untouched and ssm_last_error() returns a
+ *    message for the calling thread.
+ *  - "device" pointers are HIP device memory owned by the caller (for example
+ *    torch tensors); "host" pointers are ordinary host memory.  The library
+ *    never frees or keeps caller memory beyond the documented lifetime.
+ *  - The library allocates no device memory: every device buffer it needs is
+ *    carved out of the workspace the caller passes to ssm_create, or is a
+ *    caller buffer of a stage call.
+ *  - stream is a hipStream_t (NULL = the null stream).  Stage calls only
+ *    enqueue work and return; context calls that return host results
+ *    synchronise the stream before returning.
+ *  - Units: the matrix A, the interval [lo, hi], the sweep points t_i and the
+ *    smearing sigma are all in A's own units.  The Chebyshev expansion is
+ *    taken in the rescaled variable of Section 2,
+ *    A~ = (2A - (lo+hi) I) / (hi - lo), whose spectrum must lie in [-1, 1].
+ *  - Dense blocks are row-major: a block X of N rows and N_v columns stores
+ *    X[r][j] at r*N_v + j.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef SSM_H
+#define SSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ssm_status {
+  SSM_OK = 0,
+  SSM_ERR_ARG = 1,         /* invalid argument: null pointer, bad size, bad enum, non-finite scalar */
+  SSM_ERR_WORKSPACE = 2,   /* workspace too small for any plan, or not 256-byte aligned */
+  SSM_ERR_HIP = 3,         /* a HIP runtime call failed (message in ssm_last_error) */
+  SSM_ERR_BOUNDS = 4,      /* ||T_M(A~)W||_F > (1 + 1e-3)||W||_F: spec(A) is not inside [lo, hi] */
+  SSM_ERR_NONFINITE = 5,   /* NaN or Inf in the Gram matrices or in the DOS */
+  SSM_ERR_STATE = 6,       /* call order violated (e.g. ssm_trace before ssm_dos) */
+  SSM_ERR_UNSUPPORTED = 7  /* a size outside what this build implements (see each call) */
+} ssm_status;
+
+/* Arithmetic of the hot path.  In every mode the Gram matrices, the two
+ * eigen-decompositions of Algorithm 4 and the trace are FP64. */
+typedef enum ssm_precision {
+  SSM_FP64 = 0,            /* recurrence and sweep in FP64 (CSR values double) */
+  SSM_FP32 = 1,            /* recurrence and sweep in FP32 (CSR values float), FP32 MFMA sweep */
+  SSM_FP32_BF16SWEEP = 2   /* FP32 recurrence; sweep with BF16 inputs (round to nearest even)
+                              and FP32 accumulation on MFMA (CSR values float) */
+} ssm_precision;
+
+/* Sparse real symmetric matrix in CSR form, all arrays on the device and
+ * borrowed for the lifetime of the context (or of the stage call). */
+typedef struct ssm_csr {
+  int64_t n;               /* dimension N >= 1 */
+  int64_t nnz;             /* stored entries, 1 <= nnz < 2^31 */
+  const int32_t* row_ptr;  /* n+1 offsets, row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz */
+  const int32_t* col_idx;  /* nnz column indices in [0, n) */
+  const void* values;      /* nnz values: double for SSM_FP64, float for the FP32 modes */
+} ssm_csr;
+
+/* Parameters of Algorithm 5 (with Algorithm 4's tau). */
+typedef struct ssm_params {
+  double lo, hi;           /* lo < hi, interval containing spec(A) (Section 2) */
+  double sigma;            /* smearing sigma > 0 of g_sigma, Eq. (gaussian), A's units */
+  double tau;              /* Algorithm 4 step 2 truncation, keep s_j >= tau max s; <= 0 selects 1e-7 */
+  double range_slack;      /* rho: Algorithm 4 step 4 keeps xi in [0, (1+rho) g_max]; < 0 selects 1e-3 */
+  int32_t nv;              /* N_v random vectors: 4 <= nv <= 96 and nv % 4 == 0 in this build */
+  int32_t degree;          /* Chebyshev degree M >= 1 (T_0..T_M); M <= 4095 in this build */
+  int32_t nt;              /* number of sweep points N_t >= 1 */
+  int32_t precision;       /* an ssm_precision */
+  uint64_t seed;           /* key of the Philox generator for W when ssm_create gets no W */
+} ssm_params;
+
+/* Per-phase device times (milliseconds, HIP events on the context's stream)
+ * of the last ssm_dos, and the plan it ran. */
+typedef struct ssm_stats {
+  double ms_total;         /* whole ssm_dos, first launch to last kernel end */
+  double ms_recurrence;    /* all Chebyshev block-SpMM launches (summed over passes) */
+  double ms_sweep;         /* all sweep GEMM launches */
+  double ms_gram;          /* Gram kernels incl. partial-sum reduction */
+  double ms_geneig;        /* Algorithm 4 kernel */
+  int64_t spmm_launches;   /* number of block-SpMM launches */
+  int64_t sweep_launches;  /* number of sweep GEMM launches */
+  int32_t passes;          /* recurrence passes (sweep-point batches) */
+  int32_t chunk;           /* K_c: Chebyshev blocks held at once */
+  int32_t batch;           /* N_t^b: sweep points per batch */
+  int32_t gram_segments;   /* row segments of the Gram partial sums */
+} ssm_stats;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ssm_last_error(void);
+const char* ssm_status_str(ssm_status s);
+
+/* ------------------------------------------------------------------------
+ * Context calls: the whole hot path of Algorithm 5.
+ * ---------------------------------------------------------------------- */
+typedef struct ssm_ctx ssm_ctx;
+
+/* Bytes of device workspace for a plan that fits in `budget` bytes
+ * (budget == 0: no limit, i.e. one recurrence pass holding every T_k(A~)W and
+ * every Z(t_i)).  The plan minimises recurrence passes first, then sweep
+ * read-modify-write passes.  SSM_ERR_WORKSPACE if no plan fits. */
+ssm_status ssm_workspace_size(const ssm_csr* a, const ssm_params* p, size_t budget, size_t* bytes);
+
+/* Validate, plan within ws_bytes, copy the nt sweep points t_host (A's units),
+ * compute the coefficients mu_l(t_i) of Algorithm 1 on the device and, if
+ * w_dev is NULL, draw W (N x N_v, entries N(0,1), Philox4x32-10 keyed by
+ * p->seed, Box-Muller) into the workspace.  A non-NULL w_dev (double for
+ * SSM_FP64, float otherwise) is borrowed for the context's lifetime.
+ * `workspace` must be 256-byte aligned and stay valid until ssm_destroy. */
+ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_host, const void* w_dev,
+                      void* workspace, size_t ws_bytes, void* stream, ssm_ctx** out);
+
+/* Algorithm 5: dos_host[i] = Tr Xi~(t_i), the SS-DGC estimate of phi_sigma(t_i)
+ * (A's units).  ranks_host, if not NULL, receives 2*nt ints: r1 (eigenvalues of
+ * W^T Z kept by the tau test) then r2 (generalised eigenvalues kept by the
+ * range test).  Synchronises the stream. */
+ssm_status ssm_dos(ssm_ctx* ctx, double* dos_host, int32_t* ranks_host);
+
+/* Sum_i w[i] * dos[i] over the DOS of the last ssm_dos (Algorithm 8, step 4).
+ * SSM_ERR_STATE before the first ssm_dos. */
+ssm_status ssm_trace(ssm_ctx* ctx, const double* w_host, double* tr);
+
+ssm_status ssm_get_stats(const ssm_ctx* ctx, ssm_stats* out);
+
+/* Device views of the context's buffers (valid until ssm_destroy; contents as
+ * left by the last ssm_dos).  y: K_c blocks T_k(A~)W (block k at slot k mod K_c
+ * of the last pass); z: the last batch's Z(t_i) blocks; k_w, k_z: nt Gram
+ * matrices N_v x N_v (double); coeff: (M+1) x nt coefficients (double,
+ * row-major, mu_l(t_i) at l*nt + i); w: the block W. */
+typedef struct ssm_views {
+  void* w; void* y; void* z; double* k_w; double* k_z; double* coeff;
+  int32_t chunk; int32_t batch; int32_t first_point_of_last_batch; int32_t elem_bytes;
+} ssm_views;
+ssm_status ssm_get_views(const ssm_ctx* ctx, ssm_views* out);
+
+ssm_status ssm_destroy(ssm_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Algorithm 8 (host only): weights w_i with Tr f(A) ~= sum_i w_i phi~(t_i),
+ * for the nt midpoints t_i = c0 + hw(-1 + (2i+1)/nt) of [lo, hi].
+ * h(t) = f(t) pi(t) + c (1 - pi(t)) (Eq. hform, pi of Eq. pifunc with
+ * parameters a and sigma_tilde in the rescaled variable, c = (f(x(-a)) +
+ * f(x(a)))/2); f~ solves f~ * G = h periodically on the rescaled [-1, 1] with
+ * G the unit-mass Gaussian of width sigma/hw, by DFT, keeping the wavenumbers
+ * k with exp(-(pi k sigma/hw)^2/2) >= 1e-10; w_i = N (hi - lo)/nt f~(t_i).
+ * f is called only at points where pi(t) > 1e-300, plus x(+-a).
+ * Requires 0 < a < 1, sigma_tilde > 0, nt >= 2. */
+typedef double (*ssm_scalar_fn)(double x, void* user);
+ssm_status ssm_trace_weights(double lo, double hi, int32_t nt, int64_t n, double sigma, double a,
+                             double sigma_tilde, ssm_scalar_fn f, void* user, double* w_host);
+
+/* ------------------------------------------------------------------------
+ * Stage calls: one step of the hot path each, on caller device buffers.
+ * They enqueue on `stream` and return without synchronising.
+ * ---------------------------------------------------------------------- */
+
+/* Algorithm 1 for nt points at once: c[l*nt + i] = mu_l(t_i), l = 0..M, with
+ * theta_j = j pi / N_theta, 2 N_theta = least power of two >= 4(M+1), and
+ * g_j = g_sigma(t_i - x(cos theta_j)), x(s) = (lo+hi)/2 + s (hi-lo)/2,
+ * g_sigma of Eq. (gaussian) with its 1/N.  t_dev: nt doubles.  c32, if not
+ * NULL, receives the same values rounded to float. */
+ssm_status ssm_coefficients(double lo, double hi, double sigma, int64_t n, const double* t_dev,
+                            int32_t nt, int32_t degree, double* c_dev, float* c32_dev, void* stream);
+
+/* W (n x nv): element (r, j), j = 4g + m, is normal m of Philox4x32-10 with
+ * counter (g, 0, r mod 2^32, r div 2^32) and key (seed mod 2^32, seed div
+ * 2^32); Box-Muller with u = (x0+1) 2^-32, v = x1 2^-32 (normals 0, 1 =
+ * sqrt(-2 ln u) cos/sin(2 pi v)) and likewise (x2, x3) for normals 2, 3.
+ * Computed in double; dtype 0 stores double, 1 stores float. */
+ssm_status ssm_gaussian_block(uint64_t seed, int64_t n, int32_t nv, int32_t dtype, void* w_dev,
+                              void* stream);
+
+/* The three-term recurrence of Algorithm 5 (steps 3, 9, 10):
+ * y holds M+1 consecutive blocks (n x nv each); block 0 <- w,
+ * block 1 <- A~ w, block k+1 <- 2 A~ block k - block k-1, with
+ * A~ = (2A - (lo+hi) I)/(hi-lo).  FP64 when precision == SSM_FP64, else FP32. */
+ssm_status ssm_chebyshev(const ssm_csr* a, double lo, double hi, int32_t precision, int32_t nv,
+                         int32_t degree, const void* w, void* y, void* stream);
+
+/* The sweep (Algorithm 5, steps 6-8) over a chunk of kc blocks and ntb points:
+ * z[i*e + q] (+)= sum_{k<kc} c[k*ldc + i] * y[k*e + q],  i < ntb, q < e,
+ * with e = N * N_v elements per block.  accumulate = 0 overwrites z.
+ * SSM_FP64: c, y, z double (FP64 MFMA).  SSM_FP32: c, y, z float (FP32 MFMA).
+ * SSM_FP32_BF16SWEEP: c, y, z float; c and y rounded to bfloat16 (nearest
+ * even) before the products, FP32 accumulation (BF16 MFMA). */
+ssm_status ssm_sweep(int32_t precision, int64_t e, int32_t kc, int32_t ntb, const void* c, int64_t ldc,
+                     const void* y, void* z, int32_t accumulate, void* stream);
+
+/* Gram matrices of ntb sweep points (Eq. tracelr, Algorithm 5 step 13):
+ * k_w[i] = (W^T Z_i + Z_i^T W)/2,  k_z[i] = Z_i^T Z_i  (nv x nv doubles each),
+ * Z_i = z + i*n*nv.  Products and sums in FP64 (FP32 inputs widened exactly).
+ * w, z: double for SSM_FP64, float otherwise.  The rows are split in nseg
+ * segments whose partial sums go to `scratch` (nseg*ntb*2*nv*nv doubles)
+ * and are then added in a fixed order (deterministic). */
+ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
+                    double* k_w, double* k_z, int32_t nseg, double* scratch, void* stream);
+
+/* Algorithm 4 and the trace, for ntb points: for point i, eig(k_w[i]) = U S U^T,
+ * keep s_j >= tau max_j s_j (nothing if max s <= 0), B = S~^-1/2 U~^T k_z[i]
+ * U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi in [0, (1 + rho) g_max];
+ * ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).  Cyclic Jacobi in
+ * FP64.  scratch: ntb*nv*nv doubles. */
+ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max,
+                            double tau, double rho, double* dos_dev, int32_t* ranks_dev, double* scratch,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSM_H */

@@ -182,6 +182,19 @@ def geneig_trace(k_w: np.ndarray, k_z: np.ndarray, g_max: float, tau: float = 1e
     return out + ({"s": s, "xi": xi},) if return_parts else out
 
 
+def sweep(mu: np.ndarray, blocks) -> np.ndarray:
+    """Z(t_i) = sum_l mu_l(t_i) V_l accumulated block by block (Algorithm 5, steps 6-8).
+
+    ``mu`` has shape (L, N_t) and ``blocks`` yields the L blocks V_l in order."""
+    z = None
+    for l, v in enumerate(blocks):
+        if z is None:
+            z = np.zeros((mu.shape[1],) + v.shape)
+        for i in range(mu.shape[1]):
+            z[i] += mu[l, i] * v
+    return z
+
+
 def gram(w: np.ndarray, z: np.ndarray):
     """K_W = (W^T Z + Z^T W)/2 and K_Z = Z^T Z for one sweep point (Eq. tracelr)."""
     wz = w.T @ z
@@ -208,10 +221,7 @@ def ss_dgc(a, w, t, degree: int, sigma: float, lo: float, hi: float, tau: float 
         mu = dgc_coefficients(t[sel], degree, sigma, n, lo, hi)          # step 1
     else:
         mu = np.asarray(mu)[:, sel]
-    z = np.zeros((sel.size, n, nv))                                      # step 4
-    for l, v_c in chebyshev_blocks(a, w, degree, lo, hi):                # steps 3, 5-11
-        for i in range(sel.size):
-            z[i] += mu[l, i] * v_c
+    z = sweep(mu, (v for _, v in chebyshev_blocks(a, w, degree, lo, hi)))   # steps 3-11
     g_max = range_bound(sigma, n)
     dos = np.zeros(sel.size)
     r1 = np.zeros(sel.size, dtype=np.int64)

@@ -1,0 +1,66 @@
+// Algorithm 1 (Delta-Gauss-Chebyshev coefficients) for all sweep points at once.
+//
+// mu_l(t) = (2 - delta_l0) / (2 N_theta) * Re sum_{j<2N_theta} exp(-i 2 pi j l / 2N_theta) g_j,
+// g_j = g_sigma(t - x(cos theta_j)), theta_j = j pi / N_theta   (Eq. mucoef2 discretised).
+// Because cos(theta_{2N_theta - j}) = cos(theta_j), g is even in j and the DFT is a
+// cosine sum over j = 0..N_theta (a DCT-I):
+//   Re g^_l = g_0 + (-1)^l g_{N_theta} + 2 sum_{0<j<N_theta} g_j cos(pi j l / N_theta).
+// One workgroup per sweep point: g_j and the table cos(pi m / N_theta), m = 0..N_theta,
+// sit in LDS; the index j*l is reduced modulo 2 N_theta exactly, in integers.
+#include "ssm_kernels.h"
+
+namespace ssm {
+namespace {
+
+__global__ void __launch_bounds__(256) dgc_coefficients_kernel(double c0, double hw, double sigma,
+                                                               double inv_norm, const double* __restrict__ t,
+                                                               int nt, int degree, int n_theta,
+                                                               double* __restrict__ c,
+                                                               float* __restrict__ c32, int64_t ldc) {
+  extern __shared__ double lds[];
+  double* g = lds;                 // n_theta + 1
+  double* cs = lds + n_theta + 1;  // n_theta + 1
+  const int i = blockIdx.x;
+  const double ti = t[i];
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  for (int j = threadIdx.x; j <= n_theta; j += blockDim.x) {
+    const double ct = cospi((double)j / (double)n_theta);
+    cs[j] = ct;
+    const double s = ti - (c0 + hw * ct);
+    g[j] = inv_norm * exp(-s * s * inv2s2);
+  }
+  __syncthreads();
+  const int two = 2 * n_theta;
+  for (int l = threadIdx.x; l <= degree; l += blockDim.x) {
+    double acc = 0.0;
+    int m = 0;
+    for (int j = 1; j < n_theta; ++j) {
+      m += l;
+      if (m >= two) m -= two;  // l < 2 N_theta, so one subtraction keeps m = (j l) mod 2N_theta
+      const int idx = (m <= n_theta) ? m : two - m;
+      acc += g[j] * cs[idx];
+    }
+    const double re = g[0] + ((l & 1) ? -g[n_theta] : g[n_theta]) + 2.0 * acc;
+    const double mu = re / (double)two * (l == 0 ? 1.0 : 2.0);
+    c[(int64_t)l * ldc + i] = mu;
+    if (c32) c32[(int64_t)l * ldc + i] = (float)mu;
+  }
+}
+
+}  // namespace
+
+size_t coefficient_lds_bytes(int n_theta) { return 2 * (size_t)(n_theta + 1) * sizeof(double); }
+
+hipError_t launch_coefficients(double c0, double hw, double sigma, double inv_norm, const double* t, int nt,
+                               int degree, int n_theta, double* c, float* c32, int64_t ldc,
+                               hipStream_t stream) {
+  const size_t lds = coefficient_lds_bytes(n_theta);
+  hipError_t err = hipFuncSetAttribute((const void*)dgc_coefficients_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(dgc_coefficients_kernel, dim3(nt), dim3(256), lds, stream, c0, hw, sigma, inv_norm, t,
+                     nt, degree, n_theta, c, c32, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace ssm

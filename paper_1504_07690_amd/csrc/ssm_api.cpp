@@ -1,0 +1,637 @@
+// libssm host side: argument validation, workspace planning, the driver of
+// Algorithm 5 on the device, the stage calls, and the weights of Algorithm 8.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ssm.h"
+#include "ssm_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ssm_status fail(ssm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+ssm_status hip_fail(hipError_t e, const char* what) {
+  return fail(SSM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SSM_HIP(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kMaxNv = 96;
+constexpr int kMaxDegree = 4095;
+constexpr int kMinChunk = 16;
+
+int n_theta_for(int degree) {
+  int two = 1;
+  while (two < 4 * (degree + 1)) two *= 2;
+  return two / 2;
+}
+
+size_t elem_bytes(int precision) { return precision == SSM_FP64 ? 8 : 4; }
+
+ssm_status check_csr(const ssm_csr* a) {
+  if (!a) return fail(SSM_ERR_ARG, "csr is NULL");
+  if (a->n < 1) return fail(SSM_ERR_ARG, "csr.n must be >= 1 (got %lld)", (long long)a->n);
+  if (a->nnz < 1 || a->nnz >= 0x7FFFFFFFLL) return fail(SSM_ERR_ARG, "csr.nnz must be in [1, 2^31)");
+  if (a->n > (int64_t)1 << 31) return fail(SSM_ERR_UNSUPPORTED, "csr.n above 2^31");
+  if (!a->row_ptr || !a->col_idx || !a->values) return fail(SSM_ERR_ARG, "csr arrays must be non-NULL");
+  return SSM_OK;
+}
+
+ssm_status check_params(const ssm_params* p) {
+  if (!p) return fail(SSM_ERR_ARG, "params is NULL");
+  if (!std::isfinite(p->lo) || !std::isfinite(p->hi) || !(p->lo < p->hi))
+    return fail(SSM_ERR_ARG, "need finite lo < hi (got %g, %g)", p->lo, p->hi);
+  if (!std::isfinite(p->sigma) || !(p->sigma > 0)) return fail(SSM_ERR_ARG, "sigma must be finite and > 0");
+  if (!std::isfinite(p->tau) || !std::isfinite(p->range_slack)) return fail(SSM_ERR_ARG, "tau, rho must be finite");
+  if (p->tau >= 1.0) return fail(SSM_ERR_ARG, "tau must be < 1");
+  if (p->nv < 4 || p->nv % 4 != 0) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4 (got %d)", p->nv);
+  if (p->nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d is not implemented in this build", kMaxNv);
+  if (p->degree < 1) return fail(SSM_ERR_ARG, "degree must be >= 1");
+  if (p->degree > kMaxDegree) return fail(SSM_ERR_UNSUPPORTED, "degree > %d is not implemented", kMaxDegree);
+  if (p->nt < 1) return fail(SSM_ERR_ARG, "nt must be >= 1");
+  if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16SWEEP)
+    return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
+  return SSM_OK;
+}
+
+double eff_tau(const ssm_params* p) { return p->tau > 0 ? p->tau : 1e-7; }
+double eff_rho(const ssm_params* p) { return p->range_slack >= 0 ? p->range_slack : 1e-3; }
+
+struct Plan {
+  int passes = 1, chunk = 1, batch = 1, nseg = 1;
+  int64_t ldc = 4;
+  size_t off_t = 0, off_c64 = 0, off_c32 = 0, off_w = 0, off_y = 0, off_z = 0, off_kw = 0, off_kz = 0,
+         off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, total = 0;
+};
+
+int gram_segments(int64_t n, int batch) {
+  int s = (int)std::min<int64_t>(64, std::max<int64_t>(1, (2048 + batch - 1) / batch));
+  while (s > 1 && n / s < 256) --s;
+  return s;
+}
+
+void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
+  const size_t es = elem_bytes(p->precision);
+  const size_t e = (size_t)a->n * p->nv;
+  const size_t nn = (size_t)p->nv * p->nv;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  pl.off_t = take(p->nt * 8);
+  pl.off_c64 = take((size_t)(p->degree + 1) * pl.ldc * 8);
+  pl.off_c32 = take(p->precision == SSM_FP64 ? 0 : (size_t)(p->degree + 1) * pl.ldc * 4);
+  pl.off_w = take(own_w ? e * es : 0);
+  pl.off_kw = take((size_t)p->nt * nn * 8);
+  pl.off_kz = take((size_t)p->nt * nn * 8);
+  pl.off_escr = take((size_t)p->nt * nn * 8);
+  pl.off_dos = take(p->nt * 8);
+  pl.off_ranks = take(2 * (size_t)p->nt * 4);
+  pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
+  pl.off_gpart = take((size_t)pl.nseg * pl.batch * 2 * nn * 8);
+  pl.off_z = take((size_t)pl.batch * e * es);
+  pl.off_y = take((size_t)pl.chunk * e * es);
+  pl.total = o;
+}
+
+// Minimise modelled bytes: recurrence replays (one per pass) against read-modify-write
+// of the Z batch for every extra chunk.
+ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t budget, Plan& out) {
+  const size_t es = elem_bytes(p->precision);
+  const double e = (double)a->n * p->nv;
+  const double spmm_bytes = 3.0 * e * es + (double)a->nnz * (4.0 + es);
+  Plan best;
+  double best_cost = -1.0;
+  const int m1 = p->degree + 1;
+  for (int passes = 1; passes <= p->nt; ++passes) {
+    int batch = (p->nt + passes - 1) / passes;
+    if (passes > 1) batch = (batch + 3) / 4 * 4;  // batch starts stay 16-byte aligned in the coefficient table
+    if ((p->nt + batch - 1) / batch != passes) continue;  // same batch as a smaller pass count
+    Plan pl;
+    pl.ldc = (p->nt + 3) / 4 * 4;
+    pl.passes = passes;
+    pl.batch = batch;
+    pl.nseg = gram_segments(a->n, batch);
+    pl.chunk = 0;
+    layout(pl, a, p, own_w);
+    const size_t fixed = pl.total;
+    int chunk = m1;
+    if (budget) {
+      const double room = (double)budget - (double)fixed;
+      const double per = (double)align_up((size_t)e * es) + 0.0;
+      chunk = room > 0 ? (int)std::min<double>(m1, std::floor(room / ((double)e * es)) - 1) : 0;
+      (void)per;
+      if (chunk < std::min(m1, kMinChunk)) continue;
+    }
+    pl.chunk = chunk;
+    layout(pl, a, p, own_w);
+    if (budget && pl.total > budget) continue;
+    const int nchunks = (m1 + chunk - 1) / chunk;
+    const double cost = passes * (p->degree * spmm_bytes) + passes * (2.0 * nchunks - 1.0) * batch * e * es;
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = pl;
+    }
+    if (!budget) break;
+    if (passes > 4096) break;
+  }
+  if (best_cost < 0) return fail(SSM_ERR_WORKSPACE, "no plan fits in %zu bytes of workspace", budget);
+  out = best;
+  return SSM_OK;
+}
+
+}  // namespace
+
+struct ssm_ctx {
+  ssm_csr a{};
+  ssm_params p{};
+  hipStream_t stream = nullptr;
+  Plan pl;
+  char* ws = nullptr;
+  double* t = nullptr;
+  double* c64 = nullptr;
+  float* c32 = nullptr;
+  void* w = nullptr;
+  void* y = nullptr;
+  void* z = nullptr;
+  double* kw = nullptr;
+  double* kz = nullptr;
+  double* gpart = nullptr;
+  double* escr = nullptr;
+  double* dos = nullptr;
+  int32_t* ranks = nullptr;
+  double* norm = nullptr;
+  std::vector<double> dos_host;
+  bool have_dos = false;
+  ssm_stats stats{};
+  std::vector<hipEvent_t> events;
+  int last_batch_start = 0;
+};
+
+extern "C" {
+
+const char* ssm_last_error(void) { return g_last_error.c_str(); }
+
+const char* ssm_status_str(ssm_status s) {
+  switch (s) {
+    case SSM_OK: return "ok";
+    case SSM_ERR_ARG: return "invalid argument";
+    case SSM_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case SSM_ERR_HIP: return "HIP runtime error";
+    case SSM_ERR_BOUNDS: return "spectrum not inside [lo, hi]";
+    case SSM_ERR_NONFINITE: return "non-finite value";
+    case SSM_ERR_STATE: return "call order violated";
+    case SSM_ERR_UNSUPPORTED: return "size not supported by this build";
+  }
+  return "unknown status";
+}
+
+ssm_status ssm_workspace_size(const ssm_csr* a, const ssm_params* p, size_t budget, size_t* bytes) {
+  ssm_status s = check_csr(a);
+  if (s != SSM_OK) return s;
+  if ((s = check_params(p)) != SSM_OK) return s;
+  if (!bytes) return fail(SSM_ERR_ARG, "bytes is NULL");
+  Plan pl;
+  if ((s = make_plan(a, p, true, budget, pl)) != SSM_OK) return s;
+  *bytes = pl.total;
+  return SSM_OK;
+}
+
+ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_host, const void* w_dev,
+                      void* workspace, size_t ws_bytes, void* stream, ssm_ctx** out) {
+  ssm_status s = check_csr(a);
+  if (s != SSM_OK) return s;
+  if ((s = check_params(p)) != SSM_OK) return s;
+  if (!t_host || !out) return fail(SSM_ERR_ARG, "t_host and out must be non-NULL");
+  for (int i = 0; i < p->nt; ++i)
+    if (!std::isfinite(t_host[i])) return fail(SSM_ERR_ARG, "t[%d] is not finite", i);
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SSM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  const bool own_w = (w_dev == nullptr);
+  Plan pl;
+  if ((s = make_plan(a, p, own_w, ws_bytes, pl)) != SSM_OK) return s;
+  if (pl.total > ws_bytes) return fail(SSM_ERR_WORKSPACE, "plan needs %zu bytes, got %zu", pl.total, ws_bytes);
+
+  ssm_ctx* c = new ssm_ctx();
+  c->a = *a;
+  c->p = *p;
+  c->p.tau = eff_tau(p);
+  c->p.range_slack = eff_rho(p);
+  c->stream = (hipStream_t)stream;
+  c->pl = pl;
+  c->ws = (char*)workspace;
+  c->t = (double*)(c->ws + pl.off_t);
+  c->c64 = (double*)(c->ws + pl.off_c64);
+  c->c32 = p->precision == SSM_FP64 ? nullptr : (float*)(c->ws + pl.off_c32);
+  c->w = own_w ? (void*)(c->ws + pl.off_w) : const_cast<void*>(w_dev);
+  c->y = c->ws + pl.off_y;
+  c->z = c->ws + pl.off_z;
+  c->kw = (double*)(c->ws + pl.off_kw);
+  c->kz = (double*)(c->ws + pl.off_kz);
+  c->gpart = (double*)(c->ws + pl.off_gpart);
+  c->escr = (double*)(c->ws + pl.off_escr);
+  c->dos = (double*)(c->ws + pl.off_dos);
+  c->ranks = (int32_t*)(c->ws + pl.off_ranks);
+  c->norm = (double*)(c->ws + pl.off_norm);
+  c->dos_host.assign(p->nt, 0.0);
+
+  auto bail = [&](ssm_status st) {
+    delete c;
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(c->t, t_host, sizeof(double) * p->nt, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "copy of sweep points"));
+  if (pl.ldc != p->nt) {  // padding columns of the coefficient table are read by the sweep: make them 0
+    if ((e = hipMemsetAsync(c->c64, 0, (size_t)(p->degree + 1) * pl.ldc * 8, c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "clear coefficients"));
+    if (c->c32 && (e = hipMemsetAsync(c->c32, 0, (size_t)(p->degree + 1) * pl.ldc * 4, c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "clear coefficients"));
+  }
+  const double c0 = 0.5 * (p->lo + p->hi), hw = 0.5 * (p->hi - p->lo);
+  const double inv_norm = 1.0 / ((double)a->n * std::sqrt(2.0 * M_PI) * p->sigma);
+  if ((e = ssm::launch_coefficients(c0, hw, p->sigma, inv_norm, c->t, p->nt, p->degree, n_theta_for(p->degree),
+                                    c->c64, c->c32, pl.ldc, c->stream)) != hipSuccess)
+    return bail(hip_fail(e, "coefficient kernel"));
+  if (own_w) {
+    if ((e = ssm::launch_gaussian_block(p->seed, a->n, p->nv, p->precision == SSM_FP64 ? 0 : 1, c->w,
+                                        c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "W generator"));
+  }
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(hip_fail(e, "ssm_create sync"));
+  c->stats.passes = pl.passes;
+  c->stats.chunk = pl.chunk;
+  c->stats.batch = pl.batch;
+  c->stats.gram_segments = pl.nseg;
+  *out = c;
+  return SSM_OK;
+}
+
+ssm_status ssm_destroy(ssm_ctx* c) {
+  if (!c) return fail(SSM_ERR_ARG, "ctx is NULL");
+  for (auto ev : c->events) (void)hipEventDestroy(ev);
+  delete c;
+  return SSM_OK;
+}
+
+ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
+  if (!c || !dos_host) return fail(SSM_ERR_ARG, "ctx and dos_host must be non-NULL");
+  const ssm_params& p = c->p;
+  const Plan& pl = c->pl;
+  const int64_t n = c->a.n;
+  const int nv = p.nv;
+  const int64_t e = n * nv;
+  const size_t es = elem_bytes(p.precision);
+  const bool f64 = p.precision == SSM_FP64;
+  const double alpha = 2.0 / (p.hi - p.lo);
+  const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
+  const int m = p.degree;
+  hipStream_t st = c->stream;
+
+  // events: [0] start, then (begin, end) pairs per timed launch group
+  const int nchunks = (m + 1 + pl.chunk - 1) / pl.chunk;
+  const size_t need = 2 + (size_t)pl.passes * (2 * nchunks + 2) * 2 + 4;
+  while (c->events.size() < need) {
+    hipEvent_t ev;
+    SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
+    c->events.push_back(ev);
+  }
+  size_t evi = 0;
+  struct Span { size_t b, en; int kind; };  // kind 0 rec, 1 sweep, 2 gram, 3 eig
+  std::vector<Span> spans;
+  auto mark = [&]() -> size_t { return evi++; };
+  const size_t ev_start = mark();
+  SSM_HIP(hipEventRecord(c->events[ev_start], st), "hipEventRecord");
+  int64_t spmm_launches = 0, sweep_launches = 0;
+
+  auto y_slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % pl.chunk) * e * es; };
+  for (int pass = 0; pass < pl.passes; ++pass) {
+    const int p0 = pass * pl.batch;
+    const int nb = std::min(pl.batch, p.nt - p0);
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int k_first = ch * pl.chunk;
+      const int k_last = std::min(m, k_first + pl.chunk - 1);
+      Span rs{mark(), 0, 0};
+      SSM_HIP(hipEventRecord(c->events[rs.b], st), "hipEventRecord");
+      for (int k = k_first; k <= k_last; ++k) {
+        char* out = y_slot(k);
+        hipError_t err;
+        if (k == 0) {
+          err = hipMemcpyAsync(out, c->w, e * es, hipMemcpyDeviceToDevice, st);
+        } else {
+          const void* x = (k == 1) ? c->w : (const void*)y_slot(k - 1);
+          const void* xp = (k == 1) ? nullptr : (const void*)y_slot(k - 2);
+          const double a = (k == 1) ? alpha : 2.0 * alpha;
+          const double b = (k == 1) ? beta : 2.0 * beta;
+          const double cc = (k == 1) ? 0.0 : -1.0;
+          if (f64)
+            err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
+                                            (const double*)x, (const double*)xp, (double*)out, st);
+          else
+            err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
+                                            (float)b, (float)cc, (const float*)x, (const float*)xp, (float*)out, st);
+          ++spmm_launches;
+        }
+        if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
+      }
+      rs.en = mark();
+      SSM_HIP(hipEventRecord(c->events[rs.en], st), "hipEventRecord");
+      spans.push_back(rs);
+      // sweep over this chunk
+      Span ss{rs.en, mark(), 1};
+      const int kc = k_last - k_first + 1;
+      hipError_t err;
+      if (f64)
+        err = ssm::launch_sweep_f64(e, kc, nb, c->c64 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0, (const double*)c->y,
+                                    (double*)c->z, ch > 0, st);
+      else if (p.precision == SSM_FP32)
+        err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
+                                    (const float*)c->y, (float*)c->z, ch > 0, st);
+      else
+        err = ssm::launch_sweep_bf16(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
+                                     (const float*)c->y, (float*)c->z, ch > 0, st);
+      if (err != hipSuccess) return hip_fail(err, "sweep GEMM");
+      ++sweep_launches;
+      SSM_HIP(hipEventRecord(c->events[ss.en], st), "hipEventRecord");
+      spans.push_back(ss);
+    }
+    if (pass == 0) {  // bound check inputs: ||W||_F^2 and ||T_M(A~) W||_F^2
+      hipError_t err = ssm::launch_sumsq(c->w, e, !f64, c->norm + 8, c->norm + 0, st);
+      if (err == hipSuccess) err = ssm::launch_sumsq(y_slot(m), e, !f64, c->norm + 8, c->norm + 1, st);
+      if (err != hipSuccess) return hip_fail(err, "norm kernel");
+    }
+    Span gs{mark(), mark(), 2};
+    SSM_HIP(hipEventRecord(c->events[gs.b], st), "hipEventRecord");
+    hipError_t err = ssm::launch_gram(!f64, n, nv, nb, c->w, c->z, c->kw + (int64_t)p0 * nv * nv,
+                                      c->kz + (int64_t)p0 * nv * nv, pl.nseg, c->gpart, st);
+    if (err != hipSuccess) return hip_fail(err, "Gram kernel");
+    SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
+    spans.push_back(gs);
+    c->last_batch_start = p0;
+  }
+  const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
+  Span es_{mark(), mark(), 3};
+  SSM_HIP(hipEventRecord(c->events[es_.b], st), "hipEventRecord");
+  hipError_t err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks,
+                                            c->escr, st);
+  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
+  SSM_HIP(hipEventRecord(c->events[es_.en], st), "hipEventRecord");
+  spans.push_back(es_);
+
+  std::vector<double> dos(p.nt);
+  std::vector<int32_t> ranks(2 * (size_t)p.nt);
+  double norms[2];
+  SSM_HIP(hipMemcpyAsync(dos.data(), c->dos, sizeof(double) * p.nt, hipMemcpyDeviceToHost, st), "copy DOS");
+  SSM_HIP(hipMemcpyAsync(ranks.data(), c->ranks, sizeof(int32_t) * 2 * p.nt, hipMemcpyDeviceToHost, st), "copy ranks");
+  SSM_HIP(hipMemcpyAsync(norms, c->norm, sizeof(norms), hipMemcpyDeviceToHost, st), "copy norms");
+  SSM_HIP(hipStreamSynchronize(st), "ssm_dos sync");
+
+  ssm_stats& S = c->stats;
+  S.ms_recurrence = S.ms_sweep = S.ms_gram = S.ms_geneig = 0.0;
+  for (const Span& sp : spans) {
+    float ms = 0.f;
+    SSM_HIP(hipEventElapsedTime(&ms, c->events[sp.b], c->events[sp.en]), "hipEventElapsedTime");
+    double* dst = sp.kind == 0 ? &S.ms_recurrence : sp.kind == 1 ? &S.ms_sweep : sp.kind == 2 ? &S.ms_gram : &S.ms_geneig;
+    *dst += ms;
+  }
+  float tot = 0.f;
+  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[es_.en]), "hipEventElapsedTime");
+  S.ms_total = tot;
+  S.spmm_launches = spmm_launches;
+  S.sweep_launches = sweep_launches;
+
+  if (std::isnan(norms[0]) || std::isnan(norms[1]))
+    return fail(SSM_ERR_NONFINITE, "NaN in W or T_M(A~)W: non-finite values, or [lo, hi] far from enclosing spec(A)");
+  if (!std::isfinite(norms[0]) || !std::isfinite(norms[1]) || norms[1] > (1.0 + 1e-3) * (1.0 + 1e-3) * norms[0])
+    return fail(SSM_ERR_BOUNDS, "||T_M(A~)W||_F^2 = %g exceeds ||W||_F^2 = %g: spectrum not inside [lo, hi]",
+                norms[1], norms[0]);
+  for (int i = 0; i < p.nt; ++i)
+    if (!std::isfinite(dos[i])) return fail(SSM_ERR_NONFINITE, "DOS at point %d is not finite", i);
+  std::copy(dos.begin(), dos.end(), dos_host);
+  if (ranks_host) std::copy(ranks.begin(), ranks.end(), ranks_host);
+  c->dos_host = dos;
+  c->have_dos = true;
+  return SSM_OK;
+}
+
+ssm_status ssm_trace(ssm_ctx* c, const double* w_host, double* tr) {
+  if (!c || !w_host || !tr) return fail(SSM_ERR_ARG, "ctx, w and tr must be non-NULL");
+  if (!c->have_dos) return fail(SSM_ERR_STATE, "ssm_trace before ssm_dos");
+  double acc = 0.0;
+  for (int i = 0; i < c->p.nt; ++i) acc += w_host[i] * c->dos_host[i];
+  *tr = acc;
+  return SSM_OK;
+}
+
+ssm_status ssm_get_stats(const ssm_ctx* c, ssm_stats* out) {
+  if (!c || !out) return fail(SSM_ERR_ARG, "ctx and out must be non-NULL");
+  *out = c->stats;
+  return SSM_OK;
+}
+
+ssm_status ssm_get_views(const ssm_ctx* c, ssm_views* out) {
+  if (!c || !out) return fail(SSM_ERR_ARG, "ctx and out must be non-NULL");
+  out->w = c->w;
+  out->y = c->y;
+  out->z = c->z;
+  out->k_w = c->kw;
+  out->k_z = c->kz;
+  out->coeff = c->c64;
+  out->chunk = c->pl.chunk;
+  out->batch = c->pl.batch;
+  out->first_point_of_last_batch = c->last_batch_start;
+  out->elem_bytes = (int32_t)elem_bytes(c->p.precision);
+  return SSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 8 weights (host).  h is sampled on the nt midpoints of the rescaled
+// [-1, 1] (period 2).  Forward transform C_k - i S_k = sum_j h_j e^{-2 pi i k j/nt},
+// division by G^_k = exp(-(pi k sigma^)^2 / 2) (unit-mass Gaussian) for
+// |k| <= k_c, and the inverse transform back to the grid; both transforms are
+// direct sums (O(nt k_c)) with the angle index reduced exactly modulo nt.  The
+// division happens in the wavenumber domain so that rounding of h is amplified
+// only at the wavenumbers where the Gaussian-damped DOS is itself negligible.
+// ---------------------------------------------------------------------------
+ssm_status ssm_trace_weights(double lo, double hi, int32_t nt, int64_t n, double sigma, double a, double sigma_tilde,
+                             ssm_scalar_fn f, void* user, double* w_host) {
+  if (!f || !w_host) return fail(SSM_ERR_ARG, "f and w must be non-NULL");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(SSM_ERR_ARG, "need finite lo < hi");
+  if (nt < 2) return fail(SSM_ERR_ARG, "nt must be >= 2");
+  if (n < 1) return fail(SSM_ERR_ARG, "n must be >= 1");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(SSM_ERR_ARG, "sigma must be > 0");
+  if (!(a > 0 && a < 1)) return fail(SSM_ERR_ARG, "a must be in (0, 1)");
+  if (!(sigma_tilde > 0) || !std::isfinite(sigma_tilde)) return fail(SSM_ERR_ARG, "sigma_tilde must be > 0");
+  const double c0 = 0.5 * (lo + hi), hw = 0.5 * (hi - lo);
+  const double sh = sigma / hw;
+  const double cst = 0.5 * (f(c0 - hw * a, user) + f(c0 + hw * a, user));
+  if (!std::isfinite(cst)) return fail(SSM_ERR_NONFINITE, "f(x(+-a)) is not finite");
+  std::vector<double> h(nt);
+  for (int i = 0; i < nt; ++i) {
+    const double th = -1.0 + (2.0 * i + 1.0) / nt;
+    const double pi_t = 0.5 * (std::erf((1.0 + a - 2.0 * th) / sigma_tilde) - std::erf((-1.0 - a - 2.0 * th) / sigma_tilde));
+    if (pi_t > 1e-300) {
+      const double fv = f(c0 + hw * th, user);
+      h[i] = fv * pi_t + cst * (1.0 - pi_t);
+    } else {
+      h[i] = cst;
+    }
+    if (!std::isfinite(h[i])) return fail(SSM_ERR_NONFINITE, "h(t_%d) is not finite", i);
+  }
+  const double eta = 1e-10;
+  const double kc_real = std::floor(std::sqrt(2.0 * std::log(1.0 / eta)) / (M_PI * sh));
+  const int kmax = (int)std::min<double>(nt / 2, kc_real);  // k in [0, kmax]; -k handled by symmetry
+  std::vector<double> cosv(nt), sinv(nt);
+  for (int m = 0; m < nt; ++m) {
+    cosv[m] = std::cos(2.0 * M_PI * (double)m / nt);
+    sinv[m] = std::sin(2.0 * M_PI * (double)m / nt);
+  }
+  // coefficients of the inverse transform: f~_i = (1/nt) sum_k (P_k cos + Q_k sin)(2 pi k i / nt)
+  std::vector<double> pk(kmax + 1), qk(kmax + 1);
+  for (int k = 0; k <= kmax; ++k) {
+    double ck = 0.0, sk = 0.0;
+    long long idx = 0;
+    for (int j = 0; j < nt; ++j) {
+      ck += h[j] * cosv[idx];
+      sk += h[j] * sinv[idx];
+      idx += k;
+      if (idx >= nt) idx -= nt;
+    }
+    const double gk = std::exp(-0.5 * (M_PI * k * sh) * (M_PI * k * sh));
+    // +k and -k together; k = 0 and the Nyquist wavenumber k = nt/2 appear once
+    const double mult = (k == 0 || 2 * k == nt) ? 1.0 : 2.0;
+    pk[k] = mult * ck / gk;
+    qk[k] = mult * sk / gk;
+  }
+  const double scale = (double)n * (hi - lo) / nt;  // N * dt_A
+  for (int i = 0; i < nt; ++i) {
+    double acc = 0.0;
+    long long idx = 0;
+    for (int k = 0; k <= kmax; ++k) {
+      acc += pk[k] * cosv[idx] + qk[k] * sinv[idx];
+      idx += i;
+      if (idx >= nt) idx %= nt;
+    }
+    w_host[i] = scale * acc / nt;
+  }
+  return SSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stage calls
+// ---------------------------------------------------------------------------
+ssm_status ssm_coefficients(double lo, double hi, double sigma, int64_t n, const double* t_dev, int32_t nt,
+                            int32_t degree, double* c_dev, float* c32_dev, void* stream) {
+  if (!t_dev || !c_dev) return fail(SSM_ERR_ARG, "t and c must be non-NULL");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(SSM_ERR_ARG, "need finite lo < hi");
+  if (!(sigma > 0) || n < 1 || nt < 1 || degree < 1) return fail(SSM_ERR_ARG, "need sigma > 0, n, nt, degree >= 1");
+  if (degree > kMaxDegree) return fail(SSM_ERR_UNSUPPORTED, "degree > %d", kMaxDegree);
+  const double inv_norm = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * sigma);
+  hipError_t e = ssm::launch_coefficients(0.5 * (lo + hi), 0.5 * (hi - lo), sigma, inv_norm, t_dev, nt, degree,
+                                          n_theta_for(degree), c_dev, c32_dev, nt, (hipStream_t)stream);
+  return e == hipSuccess ? SSM_OK : hip_fail(e, "coefficient kernel");
+}
+
+ssm_status ssm_gaussian_block(uint64_t seed, int64_t n, int32_t nv, int32_t dtype, void* w_dev, void* stream) {
+  if (!w_dev || n < 1 || nv < 1 || (dtype != 0 && dtype != 1)) return fail(SSM_ERR_ARG, "bad arguments");
+  hipError_t e = ssm::launch_gaussian_block(seed, n, nv, dtype, w_dev, (hipStream_t)stream);
+  return e == hipSuccess ? SSM_OK : hip_fail(e, "W generator");
+}
+
+ssm_status ssm_chebyshev(const ssm_csr* a, double lo, double hi, int32_t precision, int32_t nv, int32_t degree,
+                         const void* w, void* y, void* stream) {
+  ssm_status s = check_csr(a);
+  if (s != SSM_OK) return s;
+  if (!w || !y) return fail(SSM_ERR_ARG, "w and y must be non-NULL");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(SSM_ERR_ARG, "need finite lo < hi");
+  if (nv < 4 || nv % 4 != 0) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4");
+  if (degree < 0) return fail(SSM_ERR_ARG, "degree must be >= 0");
+  if (precision < SSM_FP64 || precision > SSM_FP32_BF16SWEEP) return fail(SSM_ERR_ARG, "bad precision");
+  const bool f64 = precision == SSM_FP64;
+  const size_t es = f64 ? 8 : 4;
+  const int64_t e = a->n * nv;
+  hipStream_t st = (hipStream_t)stream;
+  const double alpha = 2.0 / (hi - lo), beta = -(hi + lo) / (hi - lo);
+  SSM_HIP(hipMemcpyAsync(y, w, e * es, hipMemcpyDeviceToDevice, st), "copy W");
+  for (int k = 1; k <= degree; ++k) {
+    char* out = (char*)y + (size_t)k * e * es;
+    const char* x = (char*)y + (size_t)(k - 1) * e * es;
+    const char* xp = k >= 2 ? (char*)y + (size_t)(k - 2) * e * es : nullptr;
+    const double aa = k == 1 ? alpha : 2 * alpha, bb = k == 1 ? beta : 2 * beta, cc = k == 1 ? 0.0 : -1.0;
+    hipError_t err = f64 ? ssm::launch_cheb_step_f64(a->n, nv, a->row_ptr, a->col_idx, (const double*)a->values, aa, bb,
+                                                     cc, (const double*)x, (const double*)xp, (double*)out, st)
+                         : ssm::launch_cheb_step_f32(a->n, nv, a->row_ptr, a->col_idx, (const float*)a->values,
+                                                     (float)aa, (float)bb, (float)cc, (const float*)x,
+                                                     (const float*)xp, (float*)out, st);
+    if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
+  }
+  return SSM_OK;
+}
+
+ssm_status ssm_sweep(int32_t precision, int64_t e, int32_t kc, int32_t ntb, const void* c, int64_t ldc,
+                     const void* y, void* z, int32_t accumulate, void* stream) {
+  if (!c || !y || !z) return fail(SSM_ERR_ARG, "c, y, z must be non-NULL");
+  if (e < 1 || kc < 1 || ntb < 1 || ldc < ntb) return fail(SSM_ERR_ARG, "need e, kc, ntb >= 1 and ldc >= ntb");
+  const int vec = precision == SSM_FP64 ? 2 : 4;
+  if (ldc % vec || e % vec) return fail(SSM_ERR_ARG, "ldc and e must be multiples of %d", vec);
+  hipError_t err;
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == SSM_FP64)
+    err = ssm::launch_sweep_f64(e, kc, ntb, (const double*)c, ldc, ldc, (const double*)y, (double*)z, accumulate, st);
+  else if (precision == SSM_FP32)
+    err = ssm::launch_sweep_f32(e, kc, ntb, (const float*)c, ldc, ldc, (const float*)y, (float*)z, accumulate, st);
+  else if (precision == SSM_FP32_BF16SWEEP)
+    err = ssm::launch_sweep_bf16(e, kc, ntb, (const float*)c, ldc, ldc, (const float*)y, (float*)z, accumulate, st);
+  else
+    return fail(SSM_ERR_ARG, "bad precision");
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "sweep GEMM");
+}
+
+ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z, double* k_w,
+                    double* k_z, int32_t nseg, double* scratch, void* stream) {
+  if (!w || !z || !k_w || !k_z || !scratch) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+  if (n < 1 || ntb < 1 || nseg < 1) return fail(SSM_ERR_ARG, "need n, ntb, nseg >= 1");
+  if (nv < 4 || nv % 4) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4");
+  if (nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d", kMaxNv);
+  if (precision < SSM_FP64 || precision > SSM_FP32_BF16SWEEP) return fail(SSM_ERR_ARG, "bad precision");
+  hipError_t err = ssm::launch_gram(precision != SSM_FP64, n, nv, ntb, w, z, k_w, k_z, nseg, scratch, (hipStream_t)stream);
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "Gram kernel");
+}
+
+ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                            double rho, double* dos_dev, int32_t* ranks_dev, double* scratch, void* stream) {
+  if (!k_w || !k_z || !dos_dev || !scratch) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+  if (nv < 1 || ntb < 1) return fail(SSM_ERR_ARG, "need nv, ntb >= 1");
+  if (nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d", kMaxNv);
+  if (!(g_max > 0) || !std::isfinite(tau) || !std::isfinite(rho)) return fail(SSM_ERR_ARG, "bad g_max/tau/rho");
+  hipError_t err = ssm::launch_geneig_trace(nv, ntb, k_w, k_z, g_max, tau, rho, dos_dev, ranks_dev, scratch,
+                                            (hipStream_t)stream);
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "Algorithm 4 kernel");
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Host-side launchers of the libssm kernels (internal to the library).
+// Every launcher only enqueues on `stream` and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ssm {
+
+// Algorithm 1 on the device (coeffs.hip).  c: (degree+1) x ldc doubles.
+hipError_t launch_coefficients(double c0, double hw, double sigma, double inv_norm, const double* t, int nt,
+                               int degree, int n_theta, double* c, float* c32, int64_t ldc, hipStream_t stream);
+size_t coefficient_lds_bytes(int n_theta);
+
+// Philox4x32-10 + Box-Muller block (philox.hip).
+hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, void* w, hipStream_t stream);
+
+// One Chebyshev step (cheb_spmm.hip):
+//   out = a * (A x) + b * x + c * xprev   (xprev may be null when c == 0)
+hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                const double* val, double a, double b, double c, const double* x,
+                                const double* xprev, double* out, hipStream_t stream);
+hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                const float* val, float a, float b, float c, const float* x,
+                                const float* xprev, float* out, hipStream_t stream);
+
+// Sum of squares of `count` elements, two deterministic stages (reduce.hip).
+// partial must hold reduce_partials() doubles; result written to *out (device).
+int reduce_partials();
+hipError_t launch_sumsq(const void* x, int64_t count, int is_f32, double* partial, double* out,
+                        hipStream_t stream);
+
+// Sweep GEMM (sweep_gemm.hip): z[i*e+q] (+)= sum_k c[k*ldc+i] y[k*e+q].
+// acols: columns of c readable from the pointer (>= ntb, multiple of the vector width);
+// c must be aligned to 16 bytes.
+hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t ldc, int64_t acols,
+                            const double* y, double* z, int accumulate, hipStream_t stream);
+hipError_t launch_sweep_f32(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols,
+                            const float* y, float* z, int accumulate, hipStream_t stream);
+hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols,
+                             const float* y, float* z, int accumulate, hipStream_t stream);
+
+// Gram (gram.hip).
+hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, double* k_w,
+                       double* k_z, int nseg, double* scratch, hipStream_t stream);
+
+// Algorithm 4 + trace (geneig.hip).
+hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max,
+                               double tau, double rho, double* dos, int32_t* ranks, double* scratch,
+                               hipStream_t stream);
+size_t geneig_lds_bytes(int nv);
+
+}  // namespace ssm

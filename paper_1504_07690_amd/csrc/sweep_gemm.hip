@@ -1,0 +1,377 @@
+// The sweep of Algorithm 5 (steps 6-8) as a matrix product on the matrix cores.
+//
+// For a chunk of kc Chebyshev blocks Y_k = T_k(A~) W (each e = N*N_v contiguous
+// values) and a batch of ntb sweep points:
+//
+//     Z_i[q] (+)= sum_k mu_k(t_i) Y_k[q]          i < ntb, q < e
+//
+// i.e. Z (ntb x e, row-major) = C^T (ntb x kc) * Y (kc x e, row-major), where the
+// coefficient table C is stored k-major: C[k*ldc + i].  Both operands are read
+// along their contiguous index, staged in LDS in [k][m] / [k][n] order, and fed to
+// MFMA tiles.  Output tiles are (points x elements); a workgroup's tile pairs one
+// slice of Y with many points, so each Y value fetched from memory serves BM points.
+//
+// XCD-aware order: workgroup b runs on XCD b % 8; the remap below gives every XCD
+// a run of consecutive (point-tile, element-tile) pairs with the point tile
+// fastest, so all point tiles that read one Y slice share that XCD's L2.
+#include "ssm_kernels.h"
+
+namespace ssm {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void tile_coords(int mt, int nt_tiles, int& m_tile, int& n_tile) {
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7;
+  const int local = bid >> 3;
+  m_tile = local % mt;
+  n_tile = xcd + 8 * (local / mt);
+  if (n_tile >= nt_tiles) n_tile = -1;
+}
+
+// ---------------------------------------------------------------------------
+// FP32: v_mfma_f32_32x32x2_f32.  Tile 128 points x 128 elements x 16 k, four
+// waves in a 2 x 2 arrangement, each wave 64 x 64 = 2 x 2 MFMA blocks.
+// Operand lanes: a = A[m = lane%32][k = lane/32], b = B[k = lane/32][n = lane%32];
+// result register r of lane l holds D[8(r/4) + 4(l/32) + r%4][l%32].
+// ---------------------------------------------------------------------------
+constexpr int F32_BM = 128, F32_BN = 128, F32_BK = 16, F32_PAD = 4;
+
+__global__ void __launch_bounds__(256) sweep_f32_kernel(int64_t e, int kc, int ntb, const float* __restrict__ c,
+                                                        int64_t ldc, int64_t acols, const float* __restrict__ y,
+                                                        float* __restrict__ z, int accumulate, int mt,
+                                                        int nt_tiles) {
+  __shared__ float As[2][F32_BK][F32_BM + F32_PAD];
+  __shared__ float Bs[2][F32_BK][F32_BN + F32_PAD];
+  int m_tile, n_tile;
+  tile_coords(mt, nt_tiles, m_tile, n_tile);
+  if (n_tile < 0) return;
+  const int64_t i0 = (int64_t)m_tile * F32_BM;
+  const int64_t q0 = (int64_t)n_tile * F32_BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // global -> register staging: 2 float4 of A and 2 of B per thread
+  f32x4 ra[2], rb[2];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 5;
+      const int c4 = (idx & 31) * 4;
+      const int k = k0 + kk;
+      f32x4 va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+      if (k < kc) {
+        if (i0 + c4 < acols) va = *(const f32x4*)(c + (int64_t)k * ldc + i0 + c4);
+        if (q0 + c4 < e) vb = *(const f32x4*)(y + (int64_t)k * e + q0 + c4);
+      }
+      ra[u] = va;
+      rb[u] = vb;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 5;
+      const int c4 = (idx & 31) * 4;
+      *(f32x4*)&As[buf][kk][c4] = ra[u];
+      *(f32x4*)&Bs[buf][kk][c4] = rb[u];
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int nk = (kc + F32_BK - 1) / F32_BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tile((kt + 1) * F32_BK);
+#pragma unroll
+    for (int kk = 0; kk < F32_BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float a0 = As[buf][kr][wm * 64 + (lane & 31)];
+      const float a1 = As[buf][kr][wm * 64 + 32 + (lane & 31)];
+      const float b0 = Bs[buf][kr][wn * 64 + (lane & 31)];
+      const float b1 = Bs[buf][kr][wn * 64 + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t col = q0 + wn * 64 + b * 32 + (lane & 31);
+      if (col >= e) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < ntb) {
+          float* p = z + row * e + col;
+          *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64: v_mfma_f64_16x16x4_f64.  Tile 128 points x 64 elements x 16 k, four
+// waves stacked along the points, each wave 32 x 64 = 2 x 4 MFMA blocks.
+// Operand lanes: a = A[m = lane%16][k = lane/16], b = B[k = lane/16][n = lane%16];
+// result register r of lane l holds D[l/16 + 4r][l%16].
+// ---------------------------------------------------------------------------
+constexpr int F64_BM = 128, F64_BN = 64, F64_BK = 16, F64_PAD = 2;
+
+__global__ void __launch_bounds__(256) sweep_f64_kernel(int64_t e, int kc, int ntb, const double* __restrict__ c,
+                                                        int64_t ldc, int64_t acols, const double* __restrict__ y,
+                                                        double* __restrict__ z, int accumulate, int mt,
+                                                        int nt_tiles) {
+  __shared__ double As[2][F64_BK][F64_BM + F64_PAD];
+  __shared__ double Bs[2][F64_BK][F64_BN + F64_PAD];
+  int m_tile, n_tile;
+  tile_coords(mt, nt_tiles, m_tile, n_tile);
+  if (n_tile < 0) return;
+  const int64_t i0 = (int64_t)m_tile * F64_BM;
+  const int64_t q0 = (int64_t)n_tile * F64_BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+  f64x2 ra[4], rb[2];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // A: 16 x 128 doubles = 1024 double2
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 6;
+      const int c2 = (idx & 63) * 2;
+      const int k = k0 + kk;
+      f64x2 v = {0.0, 0.0};
+      if (k < kc && i0 + c2 < acols) v = *(const f64x2*)(c + (int64_t)k * ldc + i0 + c2);
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {  // B: 16 x 64 doubles = 512 double2
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 5;
+      const int c2 = (idx & 31) * 2;
+      const int k = k0 + kk;
+      f64x2 v = {0.0, 0.0};
+      if (k < kc && q0 + c2 < e) v = *(const f64x2*)(y + (int64_t)k * e + q0 + c2);
+      rb[u] = v;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + 256 * u;
+      *(f64x2*)&As[buf][idx >> 6][(idx & 63) * 2] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = tid + 256 * u;
+      *(f64x2*)&Bs[buf][idx >> 5][(idx & 31) * 2] = rb[u];
+    }
+  };
+
+  f64x4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (kc + F64_BK - 1) / F64_BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tile((kt + 1) * F64_BK);
+#pragma unroll
+    for (int kk = 0; kk < F64_BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[buf][kr][wave * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kr][b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t col = q0 + b * 16 + (lane & 15);
+      if (col >= e) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + wave * 32 + a * 16 + (lane >> 4) + 4 * r;
+        if (row < ntb) {
+          double* p = z + row * e + col;
+          *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 inputs, FP32 accumulation: v_mfma_f32_32x32x16_bf16.  Tile 128 x 128 x 32.
+// Operand lanes hold 8 consecutive k: a = A[m = lane%32][k = 8(lane/32) + j],
+// b = B[k = 8(lane/32) + j][n = lane%32]; the result layout is that of the FP32
+// 32x32 MFMA.  C and Y arrive k-major, so the tiles are transposed into
+// [m][k] / [n][k] order while being rounded to bfloat16 (nearest even).
+// ---------------------------------------------------------------------------
+constexpr int BF_BM = 128, BF_BN = 128, BF_BK = 32, BF_PADK = 8;
+
+__global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int ntb, const float* __restrict__ c,
+                                                         int64_t ldc, int64_t acols, const float* __restrict__ y,
+                                                         float* __restrict__ z, int accumulate, int mt,
+                                                         int nt_tiles) {
+  __shared__ __bf16 As[BF_BM][BF_BK + BF_PADK];
+  __shared__ __bf16 Bs[BF_BN][BF_BK + BF_PADK];
+  int m_tile, n_tile;
+  tile_coords(mt, nt_tiles, m_tile, n_tile);
+  if (n_tile < 0) return;
+  const int64_t i0 = (int64_t)m_tile * BF_BM;
+  const int64_t q0 = (int64_t)n_tile * BF_BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  f32x4 ra[4], rb[4];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // 32 x 128 floats = 1024 float4 per operand
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 5;
+      const int c4 = (idx & 31) * 4;
+      const int k = k0 + kk;
+      f32x4 va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+      if (k < kc) {
+        if (i0 + c4 < acols) va = *(const f32x4*)(c + (int64_t)k * ldc + i0 + c4);
+        if (q0 + c4 < e) vb = *(const f32x4*)(y + (int64_t)k * e + q0 + c4);
+      }
+      ra[u] = va;
+      rb[u] = vb;
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = tid + 256 * u;
+      const int kk = idx >> 5;
+      const int c4 = (idx & 31) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        As[c4 + j][kk] = (__bf16)ra[u][j];
+        Bs[c4 + j][kk] = (__bf16)rb[u][j];
+      }
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int nk = (kc + BF_BK - 1) / BF_BK;
+  load_tile(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    store_tile();
+    __syncthreads();
+    if (kt + 1 < nk) load_tile((kt + 1) * BF_BK);
+#pragma unroll
+    for (int kk = 0; kk < BF_BK; kk += 16) {
+      const int kb = kk + 8 * (lane >> 5);
+      const bf16x8 a0 = *(const bf16x8*)&As[wm * 64 + (lane & 31)][kb];
+      const bf16x8 a1 = *(const bf16x8*)&As[wm * 64 + 32 + (lane & 31)][kb];
+      const bf16x8 b0 = *(const bf16x8*)&Bs[wn * 64 + (lane & 31)][kb];
+      const bf16x8 b1 = *(const bf16x8*)&Bs[wn * 64 + 32 + (lane & 31)][kb];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t col = q0 + wn * 64 + b * 32 + (lane & 31);
+      if (col >= e) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < ntb) {
+          float* p = z + row * e + col;
+          *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+        }
+      }
+    }
+}
+
+template <typename T, typename K>
+hipError_t launch_tiles(K kernel, int bm, int bn, int64_t e, int kc, int ntb, const T* c, int64_t ldc,
+                        int64_t acols, const T* y, T* z, int accumulate, hipStream_t stream) {
+  const int mt = (ntb + bm - 1) / bm;
+  const int64_t ntiles = (e + bn - 1) / bn;
+  const int64_t nt_pad = (ntiles + 7) / 8 * 8;
+  const int64_t blocks = (int64_t)mt * nt_pad;
+  if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, stream, e, kc, ntb, c, ldc, acols, y, z,
+                     accumulate, mt, (int)ntiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep_f32(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols, const float* y,
+                            float* z, int accumulate, hipStream_t stream) {
+  return launch_tiles(sweep_f32_kernel, F32_BM, F32_BN, e, kc, ntb, c, ldc, acols, y, z, accumulate, stream);
+}
+
+hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t ldc, int64_t acols,
+                            const double* y, double* z, int accumulate, hipStream_t stream) {
+  return launch_tiles(sweep_f64_kernel, F64_BM, F64_BN, e, kc, ntb, c, ldc, acols, y, z, accumulate, stream);
+}
+
+hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols, const float* y,
+                             float* z, int accumulate, hipStream_t stream) {
+  return launch_tiles(sweep_bf16_kernel, BF_BM, BF_BN, e, kc, ntb, c, ldc, acols, y, z, accumulate, stream);
+}
+
+}  // namespace ssm

@@ -1,0 +1,215 @@
+"""Python binding of libssm: torch supplies device memory and the stream, every
+step runs in the library's HIP kernels.  Names follow include/ssm.h.
+
+Nothing here computes any part of the method: the functions check shapes,
+place arrays on the device and forward pointers to the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+PRECISION = {"fp64": A.SSM_FP64, "fp32": A.SSM_FP32, "bf16": A.SSM_FP32_BF16SWEEP}
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("device tensor expected")
+
+
+class DeviceCSR:
+    """A CSR matrix (workloads.CSR or arrays) uploaded to the device."""
+
+    def __init__(self, n, row_ptr, col_idx, values, dtype=torch.float32, device="cuda:0"):
+        self.n = int(n)
+        self.row_ptr = torch.as_tensor(np.asarray(row_ptr, dtype=np.int32)).to(device)
+        self.col_idx = torch.as_tensor(np.asarray(col_idx, dtype=np.int32)).to(device)
+        self.values = torch.as_tensor(np.asarray(values, dtype=np.float64)).to(device=device, dtype=dtype)
+        self.nnz = int(self.col_idx.numel())
+
+    @classmethod
+    def from_csr(cls, csr, dtype=torch.float32, device="cuda:0"):
+        return cls(csr.n, csr.row_ptr, csr.col_idx, csr.values, dtype, device)
+
+    def struct(self) -> A.ssm_csr:
+        return A.ssm_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                         self.values.data_ptr())
+
+
+def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed) -> A.ssm_params:
+    return A.ssm_params(float(lo), float(hi), float(sigma), float(tau), float(rho), int(nv), int(degree),
+                        int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def workspace_size(csr: DeviceCSR, *, lo, hi, sigma, nv, degree, nt, precision="fp32", tau=1e-7, rho=1e-3,
+                   seed=0, budget=0) -> int:
+    out = C.c_size_t(0)
+    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed)
+    A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(p), C.c_size_t(budget), C.byref(out)),
+            "ssm_workspace_size")
+    return int(out.value)
+
+
+class SSM:
+    """One context of the spectrum sweeping method (Algorithm 5) on the device."""
+
+    def __init__(self, csr: DeviceCSR, *, lo, hi, sigma, nv, degree, t, precision="fp32", tau=1e-7, rho=1e-3,
+                 seed=0, w: torch.Tensor | None = None, budget=0, device="cuda:0"):
+        self.csr = csr
+        self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+        self.nt = int(self.t.size)
+        self.nv = int(nv)
+        self.precision = precision
+        self.elem = torch.float64 if precision == "fp64" else torch.float32
+        if w is not None:
+            _require_cuda(w)
+            if w.dtype != self.elem or tuple(w.shape) != (csr.n, nv) or not w.is_contiguous():
+                raise ValueError(f"w must be a contiguous {self.elem} tensor of shape ({csr.n}, {nv})")
+        self.w_in = w
+        self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed)
+        size = C.c_size_t(0)
+        A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(self.params), C.c_size_t(budget),
+                                         C.byref(size)), "ssm_workspace_size")
+        if budget:
+            size = C.c_size_t(budget)
+        self.ws = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self._off = (-base) % 256
+        self._ctx = C.c_void_p(0)
+        tp = self.t.ctypes.data_as(C.POINTER(C.c_double))
+        A.check(A.lib.ssm_create(C.byref(csr.struct()), C.byref(self.params), tp, _ptr(w),
+                                 C.c_void_p(base + self._off), C.c_size_t(int(size.value)), _stream(),
+                                 C.byref(self._ctx)), "ssm_create")
+
+    def dos(self):
+        """(dos, r1, r2): the DOS estimate at the sweep points (A's units) and kept counts."""
+        out = np.zeros(self.nt, dtype=np.float64)
+        ranks = np.zeros(2 * self.nt, dtype=np.int32)
+        A.check(A.lib.ssm_dos(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)),
+                              ranks.ctypes.data_as(C.POINTER(C.c_int32))), "ssm_dos")
+        return out, ranks[: self.nt].copy(), ranks[self.nt:].copy()
+
+    def trace(self, w) -> float:
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        tr = C.c_double(0.0)
+        A.check(A.lib.ssm_trace(self._ctx, w.ctypes.data_as(C.POINTER(C.c_double)), C.byref(tr)), "ssm_trace")
+        return tr.value
+
+    def stats(self) -> dict:
+        s = A.ssm_stats()
+        A.check(A.lib.ssm_get_stats(self._ctx, C.byref(s)), "ssm_get_stats")
+        return {k: getattr(s, k) for k, _ in A.ssm_stats._fields_}
+
+    def _view(self, ptr, count, dtype):
+        off = ptr - self.ws.data_ptr()
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.ws[off: off + nbytes].view(dtype)
+
+    def views(self) -> dict:
+        """Device views into the context's buffers (see ssm_get_views)."""
+        v = A.ssm_views()
+        A.check(A.lib.ssm_get_views(self._ctx, C.byref(v)), "ssm_get_views")
+        n, nv, nt = self.csr.n, self.nv, self.nt
+        e = n * nv
+        m1 = self.params.degree + 1
+        ldc = (nt + 3) // 4 * 4
+        out = {
+            "y": self._view(v.y, v.chunk * e, self.elem).view(v.chunk, n, nv),
+            "z": self._view(v.z, v.batch * e, self.elem).view(v.batch, n, nv),
+            "k_w": self._view(v.k_w, nt * nv * nv, torch.float64).view(nt, nv, nv),
+            "k_z": self._view(v.k_z, nt * nv * nv, torch.float64).view(nt, nv, nv),
+            "coeff": self._view(v.coeff, m1 * ldc, torch.float64).view(m1, ldc)[:, :nt],
+            "chunk": v.chunk, "batch": v.batch, "first_point_of_last_batch": v.first_point_of_last_batch,
+        }
+        out["w"] = self.w_in if self.w_in is not None else self._view(v.w, e, self.elem).view(n, nv)
+        return out
+
+    def close(self):
+        if self._ctx:
+            A.check(A.lib.ssm_destroy(self._ctx), "ssm_destroy")
+            self._ctx = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace_weights(f, *, lo, hi, nt, n, sigma, a=0.9, sigma_tilde=0.016) -> np.ndarray:
+    """Algorithm 8 weights (host, in the library): Tr f(A) ~= sum_i w_i dos_i."""
+    cb = A.SCALAR_FN(lambda x, _u: float(f(x)))
+    w = np.zeros(int(nt), dtype=np.float64)
+    A.check(A.lib.ssm_trace_weights(float(lo), float(hi), int(nt), int(n), float(sigma), float(a),
+                                    float(sigma_tilde), cb, None, w.ctypes.data_as(C.POINTER(C.c_double))),
+            "ssm_trace_weights")
+    return w
+
+
+# ----------------------------------------------------------------------------
+# Stage calls (each enqueues on torch's current stream)
+# ----------------------------------------------------------------------------
+def coefficients(lo, hi, sigma, n, t: torch.Tensor, degree, out: torch.Tensor, out32: torch.Tensor | None = None):
+    _require_cuda(t, out, out32)
+    nt = t.numel()
+    assert t.dtype == torch.float64 and out.dtype == torch.float64 and out.numel() >= (degree + 1) * nt
+    A.check(A.lib.ssm_coefficients(float(lo), float(hi), float(sigma), int(n), _ptr(t), int(nt), int(degree),
+                                   _ptr(out), _ptr(out32), _stream()), "ssm_coefficients")
+
+
+def gaussian_block(seed, out: torch.Tensor):
+    _require_cuda(out)
+    n, nv = out.shape
+    dtype = {torch.float64: 0, torch.float32: 1}[out.dtype]
+    A.check(A.lib.ssm_gaussian_block(int(seed) & 0xFFFFFFFFFFFFFFFF, int(n), int(nv), dtype, _ptr(out), _stream()),
+            "ssm_gaussian_block")
+
+
+def chebyshev(csr: DeviceCSR, lo, hi, precision, w: torch.Tensor, y: torch.Tensor):
+    _require_cuda(w, y)
+    m1, n, nv = y.shape
+    A.check(A.lib.ssm_chebyshev(C.byref(csr.struct()), float(lo), float(hi), PRECISION[precision], int(nv),
+                                int(m1 - 1), _ptr(w), _ptr(y), _stream()), "ssm_chebyshev")
+
+
+def sweep(precision, c: torch.Tensor, y: torch.Tensor, z: torch.Tensor, accumulate=False):
+    """z[i] (+)= sum_k c[k, i] y[k] with c (kc x ldc), y (kc x ...), z (ntb x ...)."""
+    _require_cuda(c, y, z)
+    kc, ldc = c.shape
+    ntb = z.shape[0]
+    e = y[0].numel()
+    A.check(A.lib.ssm_sweep(PRECISION[precision], int(e), int(kc), int(ntb), _ptr(c), int(ldc), _ptr(y), _ptr(z),
+                            int(bool(accumulate)), _stream()), "ssm_sweep")
+
+
+def gram(precision, w: torch.Tensor, z: torch.Tensor, k_w: torch.Tensor, k_z: torch.Tensor, nseg=1):
+    _require_cuda(w, z, k_w, k_z)
+    n, nv = w.shape
+    ntb = z.shape[0]
+    scratch = torch.empty(nseg * ntb * 2 * nv * nv, dtype=torch.float64, device=w.device)
+    A.check(A.lib.ssm_gram(PRECISION[precision], int(n), int(nv), int(ntb), _ptr(w), _ptr(z), _ptr(k_w), _ptr(k_z),
+                           int(nseg), _ptr(scratch), _stream()), "ssm_gram")
+    return scratch
+
+
+def geneig_trace(k_w: torch.Tensor, k_z: torch.Tensor, g_max, tau, rho, dos: torch.Tensor,
+                 ranks: torch.Tensor | None = None):
+    _require_cuda(k_w, k_z, dos, ranks)
+    ntb, nv, _ = k_w.shape
+    scratch = torch.empty(ntb * nv * nv, dtype=torch.float64, device=k_w.device)
+    A.check(A.lib.ssm_geneig_trace(int(nv), int(ntb), _ptr(k_w), _ptr(k_z), float(g_max), float(tau), float(rho),
+                                   _ptr(dos), _ptr(ranks), _ptr(scratch), _stream()), "ssm_geneig_trace")
+    return scratch

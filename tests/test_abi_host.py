@@ -1,0 +1,188 @@
+"""Host-side checks of libssm that need no GPU: the library loads, exports every
+call declared in include/ssm.h, validates arguments before touching the device,
+plans its workspace, and computes the Algorithm 8 weights like the oracle."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ssm_oracle as O
+from paper_1504_07690_amd import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1504_07690_amd", "libssm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libssm.so not built")
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1504_07690_amd import _abi
+    return _abi
+
+
+def declared_calls():
+    src = open(os.path.join(ROOT, "include", "ssm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_call_is_exported(A):
+    names = declared_calls()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(A.lib, name), name
+    assert set(names) == set(A.EXPORTED)
+
+
+def _dummy_csr(A, n=64, nnz=200):
+    # host addresses stand in for device pointers: validation must reject or plan
+    # without dereferencing them
+    return A.ssm_csr(n, nnz, 0x1000, 0x2000, 0x3000)
+
+
+def _params(A, **kw):
+    p = dict(lo=-1.0, hi=1.0, sigma=0.05, tau=1e-7, range_slack=1e-3, nv=8, degree=50, nt=20, precision=1, seed=1)
+    p.update(kw)
+    return A.ssm_params(**p)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(lo=1.0, hi=-1.0), 1), (dict(hi=float("nan")), 1), (dict(sigma=0.0), 1), (dict(sigma=-1.0), 1),
+    (dict(nv=6), 1), (dict(nv=0), 1), (dict(nv=128), 7), (dict(degree=0), 1), (dict(degree=5000), 7),
+    (dict(nt=0), 1), (dict(precision=7), 1), (dict(tau=2.0), 1),
+])
+def test_workspace_size_rejects_bad_params(A, bad, status):
+    out = C.c_size_t(0)
+    st = A.lib.ssm_workspace_size(C.byref(_dummy_csr(A)), C.byref(_params(A, **bad)), 0, C.byref(out))
+    assert st == status
+    assert len(A.lib.ssm_last_error()) > 0
+
+
+def test_workspace_size_rejects_bad_csr(A):
+    out = C.c_size_t(0)
+    p = _params(A)
+    for csr in (A.ssm_csr(0, 10, 1, 1, 1), A.ssm_csr(10, 0, 1, 1, 1), A.ssm_csr(10, 10, 0, 1, 1)):
+        assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == A.SSM_ERR_ARG
+
+
+def test_workspace_plan_single_pass_size(A):
+    """With no budget the plan holds every T_k W and every Z(t_i)."""
+    n, nv, m, nt = 1000, 8, 50, 20
+    out = C.c_size_t(0)
+    p = _params(A, nv=nv, degree=m, nt=nt, precision=0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(out)) == 0
+    e = n * nv * 8
+    assert out.value >= (m + 1) * e + nt * e
+    assert out.value < (m + 1) * e + nt * e + 8 * 1024 * 1024
+
+
+def test_workspace_budget_forces_more_passes_or_chunks(A):
+    n, nv, m, nt = 100000, 8, 200, 64
+    p = _params(A, nv=nv, degree=m, nt=nt, precision=1)
+    full = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(full)) == 0
+    small = C.c_size_t(0)
+    budget = full.value // 4
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), budget, C.byref(small)) == 0
+    assert small.value <= budget
+    tiny = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 1 << 20, C.byref(tiny)) == \
+        A.SSM_ERR_WORKSPACE
+
+
+def test_create_validates_before_device_work(A):
+    ctx = C.c_void_p(0)
+    t = (C.c_double * 20)(*np.linspace(-0.9, 0.9, 20))
+    p = _params(A)
+    # misaligned workspace
+    st = A.lib.ssm_create(C.byref(_dummy_csr(A)), C.byref(p), t, None, C.c_void_p(0x1001), 1 << 30, None,
+                          C.byref(ctx))
+    assert st == A.SSM_ERR_WORKSPACE
+    # non-finite sweep point
+    t[3] = float("inf")
+    st = A.lib.ssm_create(C.byref(_dummy_csr(A)), C.byref(p), t, None, C.c_void_p(0x1000), 1 << 30, None,
+                          C.byref(ctx))
+    assert st == A.SSM_ERR_ARG
+    assert not ctx.value
+
+
+def test_trace_before_dos_is_state_error_and_null_ctx(A):
+    tr = C.c_double(0)
+    w = (C.c_double * 3)()
+    assert A.lib.ssm_trace(None, w, C.byref(tr)) == A.SSM_ERR_ARG
+    assert A.lib.ssm_destroy(None) == A.SSM_ERR_ARG
+
+
+def test_stage_calls_validate(A):
+    assert A.lib.ssm_sweep(1, 100, 4, 8, None, 8, None, None, 0, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_sweep(1, 102, 4, 8, 1, 8, 1, 1, 0, None) == A.SSM_ERR_ARG    # e not a multiple of 4
+    assert A.lib.ssm_sweep(1, 100, 4, 8, 1, 6, 1, 1, 0, None) == A.SSM_ERR_ARG    # ldc < ntb
+    assert A.lib.ssm_gram(1, 100, 100, 4, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_UNSUPPORTED
+    assert A.lib.ssm_geneig_trace(8, 4, 1, 1, -1.0, 1e-7, 1e-3, 1, None, 1, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_coefficients(1.0, -1.0, 0.1, 10, 1, 4, 10, 1, None, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_gaussian_block(1, 10, 8, 3, 1, None) == A.SSM_ERR_ARG
+
+
+def test_status_strings(A):
+    for s in range(8):
+        assert len(A.lib.ssm_status_str(s)) > 0
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 8 weights: library (host C++) against the oracle
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("fname,sigma_hat,nt", [("log", 0.005, 1000), ("exp", 0.005, 1000), ("fermi", 0.005, 1200),
+                                                ("x2", 0.004, 1500)])
+def test_trace_weights_match_oracle(fname, sigma_hat, nt):
+    """Library weights (O(nt^2) cosine convolution) against the oracle's (FFT).
+
+    Rounding in either is amplified by up to 1/eta = 1e10 at the cutoff
+    wavenumber, but a regularised DOS is damped there by the same Gaussian, so
+    sum_i w_i phi_sigma(t_i) is compared tightly and the raw weights loosely.
+    sigma^ <= 0.005 keeps the window (sigma~ = 0.016) inside the condition of
+    Section 5: its Fourier transform decays faster than the Gaussian's."""
+    from paper_1504_07690_amd import ssm as S
+    a = WL.make_matrix(1)
+    lam = np.linalg.eigvalsh(a.to_dense())
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    f = {"log": lambda x: np.log(np.maximum(x, 0.05)),
+         "exp": lambda x: np.exp(-0.3 * x),
+         "fermi": lambda x: 1.0 / (1.0 + np.exp(10.0 * (x - 4.0))),
+         "x2": lambda x: x * x}[fname]
+    sigma = sigma_hat * hw
+    w_lib = S.trace_weights(lambda x: float(f(np.float64(x))), lo=lo, hi=hi, nt=nt, n=a.n, sigma=sigma)
+    w_ref = O.trace_weights(f, a.n, lo, hi, nt, sigma)
+    phi = O.exact_dos(lam, 0.5 * (lo + hi) + hw * WL.midpoint_grid(nt), sigma)
+    tr_ref = w_ref @ phi
+    assert abs(w_lib @ phi - tr_ref) <= 1e-12 * abs(w_ref) @ phi
+    assert np.abs(w_lib - w_ref).max() <= 1e-4 * np.abs(w_ref).max()
+
+
+def test_trace_weights_reproduce_exact_trace():
+    """Library weights with the exact DOS give Tr A^2 of the workload matrix."""
+    from paper_1504_07690_amd import ssm as S
+    a = WL.make_matrix(1)
+    dense = a.to_dense()
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    lam = np.linalg.eigvalsh(dense)
+    nt = 1000
+    sigma = 0.005 * hw
+    t = 0.5 * (lo + hi) + hw * WL.midpoint_grid(nt)
+    w = S.trace_weights(lambda x: x * x, lo=lo, hi=hi, nt=nt, n=a.n, sigma=sigma)
+    assert abs(w @ O.exact_dos(lam, t, sigma) - np.sum(dense * dense)) < 1e-11 * np.sum(dense * dense)
+
+
+def test_trace_weights_validate():
+    from paper_1504_07690_amd import ssm as S
+    from paper_1504_07690_amd._abi import SSMError
+    with pytest.raises(SSMError):
+        S.trace_weights(lambda x: x, lo=0.0, hi=1.0, nt=100, n=10, sigma=0.01, a=1.5)
+    with pytest.raises(SSMError):
+        S.trace_weights(lambda x: math.log(x) if x > 0 else float("nan"), lo=-1.0, hi=1.0, nt=100, n=10,
+                        sigma=0.01)
