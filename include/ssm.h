@@ -54,8 +54,11 @@ typedef enum ssm_status {
 typedef enum ssm_precision {
   SSM_FP64 = 0,            /* recurrence and sweep in FP64 (CSR values double) */
   SSM_FP32 = 1,            /* recurrence and sweep in FP32 (CSR values float), FP32 MFMA sweep */
-  SSM_FP32_BF16SWEEP = 2   /* FP32 recurrence; sweep with BF16 inputs (round to nearest even)
+  SSM_FP32_BF16SWEEP = 2,  /* FP32 recurrence; sweep with BF16 inputs (round to nearest even)
                               and FP32 accumulation on MFMA (CSR values float) */
+  SSM_FP32_BF16X3 = 3      /* FP32 recurrence; sweep with each FP32 operand split into
+                              hi + lo bfloat16 terms and the three products hi.hi + hi.lo +
+                              lo.hi on BF16 MFMA, FP32 accumulation (CSR values float) */
 } ssm_precision;
 
 /* Sparse real symmetric matrix in CSR form, all arrays on the device and
@@ -193,15 +196,32 @@ ssm_status ssm_chebyshev(const ssm_csr* a, double lo, double hi, int32_t precisi
  * with e = N * N_v elements per block.  accumulate = 0 overwrites z.
  * SSM_FP64: c, y, z double (FP64 MFMA).  SSM_FP32: c, y, z float (FP32 MFMA).
  * SSM_FP32_BF16SWEEP: c, y, z float; c and y rounded to bfloat16 (nearest
- * even) before the products, FP32 accumulation (BF16 MFMA). */
+ * even) before the products, FP32 accumulation (BF16 MFMA).  SSM_FP32_BF16X3
+ * takes split tables: use ssm_split_coefficients and ssm_sweep_split. */
 ssm_status ssm_sweep(int32_t precision, int64_t e, int32_t kc, int32_t ntb, const void* c, int64_t ldc,
                      const void* y, void* z, int32_t accumulate, void* stream);
+
+/* Split coefficient table for SSM_FP32_BF16X3: for i < nt, l < m1,
+ * chi[i*ldk + l] = bf16(c[l*ldc + i]) and clo[i*ldk + l] = bf16(c[l*ldc + i] - chi),
+ * each rounded once from the double value to the nearest bfloat16 (ties to even);
+ * entries with l >= m1 are 0.  c: m1 x ldc doubles;
+ * chi, clo: nt x ldk bfloat16 (2 bytes), ldk >= m1, ldk % 8 == 0, 16-byte aligned. */
+ssm_status ssm_split_coefficients(const double* c, int64_t ldc, int32_t nt, int32_t m1, void* chi, void* clo,
+                                  int64_t ldk, void* stream);
+
+/* The sweep of ssm_sweep in the SSM_FP32_BF16X3 arithmetic:
+ * z[i*e + q] (+)= sum_{k<kc} c[k][i] y[k*e + q] with c given by its split tables
+ * (row i at chi + i*ldk, k = 0..kc-1 from the pointer; ldk % 8 == 0, pointers
+ * 16-byte aligned); y and z float, e % 4 == 0. */
+ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, const void* clo, int64_t ldk,
+                           const void* y, void* z, int32_t accumulate, void* stream);
 
 /* Gram matrices of ntb sweep points (Eq. tracelr, Algorithm 5 step 13):
  * k_w[i] = (W^T Z_i + Z_i^T W)/2,  k_z[i] = Z_i^T Z_i  (nv x nv doubles each),
  * Z_i = z + i*n*nv.  Products and sums in FP64 (FP32 inputs widened exactly).
  * w, z: double for SSM_FP64, float otherwise.  The rows are split in nseg
- * segments whose partial sums go to `scratch` (nseg*ntb*2*nv*nv doubles)
+ * segments, each walked by four waves whose partial sums go to `scratch`
+ * (4*nseg*ntb*2*nv*nv doubles)
  * and are then added in a fixed order (deterministic). */
 ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
                     double* k_w, double* k_z, int32_t nseg, double* scratch, void* stream);

@@ -20,7 +20,7 @@ lib = C.CDLL(LIB_PATH)
 SSM_OK, SSM_ERR_ARG, SSM_ERR_WORKSPACE, SSM_ERR_HIP, SSM_ERR_BOUNDS, SSM_ERR_NONFINITE, SSM_ERR_STATE, \
     SSM_ERR_UNSUPPORTED = range(8)
 # precisions
-SSM_FP64, SSM_FP32, SSM_FP32_BF16SWEEP = 0, 1, 2
+SSM_FP64, SSM_FP32, SSM_FP32_BF16SWEEP, SSM_FP32_BF16X3 = 0, 1, 2, 3
 
 
 class ssm_csr(C.Structure):
@@ -70,6 +70,8 @@ _SIGS = {
     "ssm_chebyshev": (C.c_int, [C.POINTER(ssm_csr), C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
                                 _P, _P, _P]),
     "ssm_sweep": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, C.c_int64, _P, _P, C.c_int32, _P]),
+    "ssm_split_coefficients": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P]),
+    "ssm_sweep_split": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P, _P, C.c_int32, _P]),
     "ssm_gram": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "ssm_geneig_trace": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P,
                                    _P, _P]),

@@ -20,20 +20,43 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+// Rows are dealt to XCDs in contiguous ranges: workgroup b runs on XCD b % 8, so
+// logical block (b % 8) * per_xcd + b / 8 gives XCD x the rows of blocks
+// [x per_xcd, (x+1) per_xcd), swept in order.  A stencil neighbour a few planes
+// away was then gathered by the same XCD shortly before, and is found in its L2.
+// Up to 8 CSR entries of a row are fetched before their gathers are issued, so the
+// gathers of one row are in flight together.
 template <typename T, typename V>
-__global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, const int32_t* __restrict__ row_ptr,
+__global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
+                                                        const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col_idx,
                                                         const T* __restrict__ val, T a, T b, T c,
                                                         const V* __restrict__ x, const V* __restrict__ xprev,
                                                         V* __restrict__ out) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lblock >= nblocks) return;
+  const int64_t gid = lblock * blockDim.x + threadIdx.x;
   const int64_t r = gid / nvv;
   if (r >= n) return;
   const int q = (int)(gid - r * nvv);
   const int p0 = row_ptr[r];
   const int p1 = row_ptr[r + 1];
   V acc = (V)(T)0;
-  for (int p = p0; p < p1; ++p) acc += val[p] * x[(int64_t)col_idx[p] * nvv + q];
+  for (int p = p0; p < p1; p += 8) {
+    int cols[8];
+    T vals[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool ok = p + j < p1;
+      cols[j] = ok ? col_idx[p + j] : (int)r;
+      vals[j] = ok ? val[p + j] : (T)0;
+    }
+    V g[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = x[(int64_t)cols[j] * nvv + q];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
+  }
   V res = a * acc + b * x[gid];
   if (xprev) res += c * xprev[gid];
   out[gid] = res;
@@ -44,9 +67,11 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
                   T c, const T* x, const T* xprev, T* out, hipStream_t stream) {
   const int nvv = nv / VEC;
   const int64_t threads = n * nvv;
-  const unsigned blocks = (unsigned)((threads + 255) / 256);
-  hipLaunchKernelGGL((cheb_step_kernel<T, V>), dim3(blocks), dim3(256), 0, stream, n, nvv, row_ptr, col_idx,
-                     val, a, b, c, (const V*)x, (const V*)xprev, (V*)out);
+  const int64_t nblocks = (threads + 255) / 256;
+  const int64_t per_xcd = (nblocks + 7) / 8;
+  if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cheb_step_kernel<T, V>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv, nblocks,
+                     per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (V*)out);
   return hipGetLastError();
 }
 

@@ -5,12 +5,13 @@
 // in FP64 on v_mfma_f64_16x16x4_f64.  FP32 inputs are widened to FP64 exactly, so
 // every product is exact and only the FP64 sums round.
 //
-// Work split: one workgroup per (sweep point, row segment).  A workgroup streams its
-// rows through LDS, R rows at a time, as FP64 [row][col] tiles of Z_i and W padded
-// to NP = 16*T columns.  Only the upper 16x16 blocks (a <= b) are formed: block
-// (a, b) of Z^T Z, and block (a, b) of W^T Z + Z^T W as two MFMA chains into one
-// accumulator.  The blocks are dealt round-robin to the four waves.  Each segment
-// writes its partial blocks to scratch; a second kernel adds the segments in a
+// Work split: one workgroup per (sweep point, row segment); each of its four waves
+// walks a contiguous quarter of the segment, four rows per MFMA step (the MFMA's
+// k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of W^T Z + Z^T W
+// in registers, so its operands come straight from memory: lane l reads column
+// 16a + l%16 of row r + l/16 for each column block a, for Z_i and W (a 4-row slab
+// is contiguous), two steps ahead of the MFMAs that consume them.  Each wave
+// writes its partial blocks to scratch; a second kernel adds the partials in a
 // fixed order, mirrors the lower triangle and halves K_W (deterministic).
 #include "ssm_kernels.h"
 
@@ -18,139 +19,151 @@ namespace ssm {
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int GR_R = 32;  // rows per LDS stage (a multiple of the MFMA k = 4)
+constexpr int GR_WAVES = 4;
 
 template <int T>
 struct GramTiles {
-  static constexpr int NP = 16 * T;
-  static constexpr int NPAIR = T * (T + 1) / 2;
-  static constexpr int PW = (NPAIR + 3) / 4;  // pairs per wave
+  static constexpr int NPAIR = T * (T + 1) / 2;  // upper 16x16 blocks (a <= b)
 };
+
+template <int T, typename In>
+struct GramStep {
+  In z[T], w[T];
+};
+
+// Operand loads are buffer loads over the wave's own rows: the resource's byte range
+// ends at the last row of the wave, and the hardware returns 0 for reads past it, so
+// the rows of the last partial step arrive as zeros with no clamping, masking or
+// branching.  Columns 16a + l%16 >= N_v of a row inside the range read the next row;
+// they only feed output entries that are never stored.  Unpredicated loads whose
+// values are used as loaded let the compiler count them: waiting for the oldest
+// buffer does not also wait for the prefetch just issued.
+template <typename In>
+__device__ __forceinline__ In buffer_load(__amdgpu_buffer_rsrc_t r, int byte_off);
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer access (gfx9 family)
+
+template <int T, typename In>
+__device__ __forceinline__ void gram_load(GramStep<T, In>& st, __amdgpu_buffer_rsrc_t rz, __amdgpu_buffer_rsrc_t rw,
+                                          int rel_row, int nv, const int (&lane_off)[T]) {
+  const int base = rel_row * nv * (int)sizeof(In);
+#pragma unroll
+  for (int a = 0; a < T; ++a) {
+    st.z[a] = buffer_load<In>(rz, base + lane_off[a]);
+    st.w[a] = buffer_load<In>(rw, base + lane_off[a]);
+  }
+}
 
 template <int T, typename In>
 __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, const In* __restrict__ w,
                                                    const In* __restrict__ z, int64_t rows_per_seg,
                                                    double* __restrict__ part) {
   using G = GramTiles<T>;
-  constexpr int LD = G::NP + 1;
-  __shared__ double Zs[GR_R][LD];
-  __shared__ double Ws[GR_R][LD];
   const int i = blockIdx.x;
   const int seg = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int64_t r_begin = (int64_t)seg * rows_per_seg;
-  const int64_t r_end = (r_begin + rows_per_seg < n) ? r_begin + rows_per_seg : n;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: the buffer resources stay scalar
+  const int64_t s_begin = (int64_t)seg * rows_per_seg;
+  const int64_t s_end = (s_begin + rows_per_seg < n) ? s_begin + rows_per_seg : n;
+  // contiguous quarter of the segment, a multiple of 4 rows
+  int64_t q = (s_end - s_begin + GR_WAVES - 1) / GR_WAVES;
+  q = (q + 3) / 4 * 4;
+  const int64_t r_begin = s_begin + wave * q;
+  const int64_t r_end = (r_begin + q < s_end) ? r_begin + q : s_end;
   const In* zi = z + (int64_t)i * n * nv;
-
-  // this wave's pairs (a <= b), enumerated row by row of the upper triangle
-  int pa[G::PW], pb[G::PW];
+  const int rows = (int)((r_end > r_begin) ? r_end - r_begin : 0);
+  const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(zi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(w + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+  int lane_off[T];
 #pragma unroll
-  for (int u = 0; u < G::PW; ++u) {
-    const int pidx = wave + 4 * u;
-    int a = 0, b = 0, cnt = 0;
-    for (int aa = 0; aa < T; ++aa)
-      for (int bb = aa; bb < T; ++bb) {
-        if (cnt == pidx) { a = aa; b = bb; }
-        ++cnt;
-      }
-    pa[u] = (pidx < G::NPAIR) ? a : -1;
-    pb[u] = b;
+  for (int a = 0; a < T; ++a) lane_off[a] = ((lane >> 4) * nv + 16 * a + (lane & 15)) * (int)sizeof(In);
+
+  f64x4 acc_zz[G::NPAIR], acc_wz[G::NPAIR];
+#pragma unroll
+  for (int p = 0; p < G::NPAIR; ++p) {
+    acc_zz[p] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    acc_wz[p] = (f64x4){0.0, 0.0, 0.0, 0.0};
   }
 
-  f64x4 acc_zz[G::PW], acc_wz[G::PW];
+  // two load buffers in rotation: each is refilled right after it is consumed with
+  // the rows two steps (8 rows) ahead
+  GramStep<T, In> buf0, buf1;
+  // issue order buf0 then buf1, as in the loop, so the wait counts match on entry
+  gram_load<T, In>(buf0, rz, rw, 0, nv, lane_off);
+  __builtin_amdgcn_sched_barrier(0);
+  gram_load<T, In>(buf1, rz, rw, 4, nv, lane_off);
+  __builtin_amdgcn_sched_barrier(0);
+  auto step = [&](GramStep<T, In>& b, int rr) {
+    double zf[T], wf[T];
 #pragma unroll
-  for (int u = 0; u < G::PW; ++u) {
-    acc_zz[u] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    acc_wz[u] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  }
-
-  // zero the padding columns once (the loads never touch them)
-  for (int idx = tid; idx < GR_R * (LD - nv); idx += 256) {
-    const int rr = idx / (LD - nv), cc = nv + idx % (LD - nv);
-    Zs[rr][cc] = 0.0;
-    Ws[rr][cc] = 0.0;
-  }
-
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += GR_R) {
-    const int rows = (r_end - r0 < GR_R) ? (int)(r_end - r0) : GR_R;
-    __syncthreads();  // previous stage fully consumed
-    // load rows [r0, r0+rows) of Z_i and W (contiguous), zero the missing rows
-    const int nvec = GR_R * nv / 4;
-    for (int idx = tid; idx < nvec; idx += 256) {
-      const int flat = idx * 4;
-      const int rr = flat / nv, cc = flat % nv;
-      double zv[4] = {0.0, 0.0, 0.0, 0.0}, wv[4] = {0.0, 0.0, 0.0, 0.0};
-      if (rr < rows) {
-        const int64_t off = (r0 + rr) * nv + cc;
-        if constexpr (sizeof(In) == 4) {
-          const f32x4 a = *(const f32x4*)(zi + off);
-          const f32x4 b = *(const f32x4*)(w + off);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) { zv[j] = (double)a[j]; wv[j] = (double)b[j]; }
-        } else {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const f64x2 a = *(const f64x2*)(zi + off + 2 * h);
-            const f64x2 b = *(const f64x2*)(w + off + 2 * h);
-            zv[2 * h] = a[0]; zv[2 * h + 1] = a[1];
-            wv[2 * h] = b[0]; wv[2 * h + 1] = b[1];
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        Zs[rr][cc + j] = zv[j];
-        Ws[rr][cc + j] = wv[j];
-      }
+    for (int a = 0; a < T; ++a) {
+      zf[a] = (double)b.z[a];
+      wf[a] = (double)b.w[a];
     }
-    __syncthreads();
+    gram_load<T, In>(b, rz, rw, rr + 8, nv, lane_off);
+    // pair p = (a, b), a <= b, numbered row by row; fully unrolled, so every
+    // operand and accumulator index is a compile-time constant
 #pragma unroll
-    for (int kk = 0; kk < GR_R; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double zf[T], wf[T];
+    for (int a = 0; a < T; ++a)
 #pragma unroll
-      for (int a = 0; a < T; ++a) {
-        zf[a] = Zs[kr][16 * a + (lane & 15)];
-        wf[a] = Ws[kr][16 * a + (lane & 15)];
+      for (int bb = a; bb < T; ++bb) {
+        const int p = a * T - a * (a - 1) / 2 + (bb - a);
+        acc_zz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[a], zf[bb], acc_zz[p], 0, 0, 0);
       }
 #pragma unroll
-      for (int u = 0; u < G::PW; ++u) {
-        if (pa[u] < 0) continue;
-        double za = 0.0, zb = 0.0, wa = 0.0, wb = 0.0;
+    for (int a = 0; a < T; ++a)
 #pragma unroll
-        for (int a = 0; a < T; ++a) {
-          if (a == pa[u]) { za = zf[a]; wa = wf[a]; }
-          if (a == pb[u]) { zb = zf[a]; wb = wf[a]; }
-        }
-        acc_zz[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, zb, acc_zz[u], 0, 0, 0);
-        acc_wz[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, zb, acc_wz[u], 0, 0, 0);
-        acc_wz[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, wb, acc_wz[u], 0, 0, 0);
+      for (int bb = a; bb < T; ++bb) {
+        const int p = a * T - a * (a - 1) / 2 + (bb - a);
+        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wf[a], zf[bb], acc_wz[p], 0, 0, 0);
       }
-    }
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int bb = a; bb < T; ++bb) {
+        const int p = a * T - a * (a - 1) / 2 + (bb - a);
+        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[a], wf[bb], acc_wz[p], 0, 0, 0);
+      }
+    __builtin_amdgcn_sched_barrier(0);  // keep steps apart: their operands need not be live together
+  };
+#pragma clang loop unroll(disable)
+  for (int rr = 0; rr < rows; rr += 8) {
+    step(buf0, rr);
+    step(buf1, rr + 4);
   }
 
-  // partial blocks -> scratch: part[((seg*ntb + i)*2 + {0: ZZ, 1: WZ+ZW}) * nv*nv + row*nv + col]
+  // partial blocks -> scratch slot (seg, wave):
+  // part[((slot*ntb + i)*2 + {0: ZZ, 1: WZ+ZW}) * nv*nv + row*nv + col]
   const int64_t nn = (int64_t)nv * nv;
-  double* pz = part + ((int64_t)seg * ntb + i) * 2 * nn;
+  const int slot = seg * GR_WAVES + wave;
+  double* pz = part + ((int64_t)slot * ntb + i) * 2 * nn;
   double* pw = pz + nn;
 #pragma unroll
-  for (int u = 0; u < G::PW; ++u) {
-    if (pa[u] < 0) continue;
-    const int col = 16 * pb[u] + (lane & 15);
+  for (int a = 0; a < T; ++a)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * pa[u] + (lane >> 4) + 4 * r;  // FP64 result layout: D[l/16 + 4r][l%16]
-      if (row < nv && col < nv) {
-        pz[(int64_t)row * nv + col] = acc_zz[u][r];
-        pw[(int64_t)row * nv + col] = acc_wz[u][r];
+    for (int b = a; b < T; ++b) {
+      const int p = a * T - a * (a - 1) / 2 + (b - a);
+      const int col = 16 * b + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * a + (lane >> 4) + 4 * r;  // FP64 result layout: D[l/16 + 4r][l%16]
+        if (row < nv && col < nv) {
+          pz[(int64_t)row * nv + col] = acc_zz[p][r];
+          pw[(int64_t)row * nv + col] = acc_wz[p][r];
+        }
       }
     }
-  }
 }
 
 // K(i)[r][c] = sum over segments of the stored upper block entry; the lower blocks
@@ -180,45 +193,50 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int n
   k_w[gid] = 0.25 * (sw1 + sw2);
 }
 
-template <int T>
-hipError_t launch_t(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, int nseg,
-                    double* scratch, hipStream_t stream) {
+int64_t rows_per_segment(int64_t n, int nseg) {
   int64_t rps = (n + nseg - 1) / nseg;
-  rps = (rps + GR_R - 1) / GR_R * GR_R;
-  const int segs = (int)((n + rps - 1) / rps);
+  return (rps + 4 * GR_WAVES - 1) / (4 * GR_WAVES) * (4 * GR_WAVES);
+}
+
+template <int T>
+hipError_t launch_t(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, int64_t rps, int segs,
+                    double* scratch, hipStream_t stream) {
   dim3 grid(ntb, segs);
   if (is_f32)
-    hipLaunchKernelGGL((gram_kernel<T, float>), grid, dim3(256), 0, stream, n, nv, ntb, (const float*)w,
+    hipLaunchKernelGGL((gram_kernel<T, float>), grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb, (const float*)w,
                        (const float*)z, rps, scratch);
   else
-    hipLaunchKernelGGL((gram_kernel<T, double>), grid, dim3(256), 0, stream, n, nv, ntb, (const double*)w,
-                       (const double*)z, rps, scratch);
+    hipLaunchKernelGGL((gram_kernel<T, double>), grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
+                       (const double*)w, (const double*)z, rps, scratch);
   return hipGetLastError();
 }
 
 }  // namespace
 
+int gram_scratch_slots(int nseg) { return nseg * GR_WAVES; }
+
 hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, double* k_w,
                        double* k_z, int nseg, double* scratch, hipStream_t stream) {
   // the number of segments actually used can drop when rows are rounded up
-  int64_t rps = (n + nseg - 1) / nseg;
-  rps = (rps + GR_R - 1) / GR_R * GR_R;
+  const int64_t rps = rows_per_segment(n, nseg);
   const int segs = (int)((n + rps - 1) / rps);
   const int t = (nv + 15) / 16;
+  // a wave's rows (plus the 8-row prefetch overrun) must be addressable by 32-bit byte offsets
+  if ((rps / GR_WAVES + 16) * (int64_t)nv * (is_f32 ? 4 : 8) >= (int64_t)1 << 31) return hipErrorInvalidValue;
   hipError_t err;
   switch (t) {
-    case 1: err = launch_t<1>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
-    case 2: err = launch_t<2>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
-    case 3: err = launch_t<3>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
-    case 4: err = launch_t<4>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
-    case 5: err = launch_t<5>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
-    case 6: err = launch_t<6>(is_f32, n, nv, ntb, w, z, nseg, scratch, stream); break;
+    case 1: err = launch_t<1>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
+    case 2: err = launch_t<2>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
+    case 3: err = launch_t<3>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
+    case 4: err = launch_t<4>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
+    case 5: err = launch_t<5>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
+    case 6: err = launch_t<6>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
     default: return hipErrorInvalidValue;
   }
   if (err != hipSuccess) return err;
   const int64_t total = (int64_t)ntb * nv * nv;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, nv, ntb,
-                     segs, scratch, k_w, k_z);
+                     segs * GR_WAVES, scratch, k_w, k_z);
   return hipGetLastError();
 }
 

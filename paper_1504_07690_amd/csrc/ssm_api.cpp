@@ -73,7 +73,7 @@ ssm_status check_params(const ssm_params* p) {
   if (p->degree < 1) return fail(SSM_ERR_ARG, "degree must be >= 1");
   if (p->degree > kMaxDegree) return fail(SSM_ERR_UNSUPPORTED, "degree > %d is not implemented", kMaxDegree);
   if (p->nt < 1) return fail(SSM_ERR_ARG, "nt must be >= 1");
-  if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16SWEEP)
+  if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16X3)
     return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
   return SSM_OK;
 }
@@ -83,13 +83,15 @@ double eff_rho(const ssm_params* p) { return p->range_slack >= 0 ? p->range_slac
 
 struct Plan {
   int passes = 1, chunk = 1, batch = 1, nseg = 1;
-  int64_t ldc = 4;
-  size_t off_t = 0, off_c64 = 0, off_c32 = 0, off_w = 0, off_y = 0, off_z = 0, off_kw = 0, off_kz = 0,
+  int64_t ldc = 4, ldk = 8;
+  size_t off_t = 0, off_c64 = 0, off_c32 = 0, off_chi = 0, off_clo = 0, off_w = 0, off_y = 0, off_z = 0, off_kw = 0, off_kz = 0,
          off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, total = 0;
 };
 
+// Row segments of the Gram: enough (point, segment) workgroups to cover the 256 CUs a few
+// times, each wave keeping at least 64 rows.
 int gram_segments(int64_t n, int batch) {
-  int s = (int)std::min<int64_t>(64, std::max<int64_t>(1, (2048 + batch - 1) / batch));
+  int s = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + batch - 1) / batch));
   while (s > 1 && n / s < 256) --s;
   return s;
 }
@@ -107,6 +109,9 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_t = take(p->nt * 8);
   pl.off_c64 = take((size_t)(p->degree + 1) * pl.ldc * 8);
   pl.off_c32 = take(p->precision == SSM_FP64 ? 0 : (size_t)(p->degree + 1) * pl.ldc * 4);
+  const bool split = p->precision == SSM_FP32_BF16X3;
+  pl.off_chi = take(split ? (size_t)p->nt * pl.ldk * 2 : 0);
+  pl.off_clo = take(split ? (size_t)p->nt * pl.ldk * 2 : 0);
   pl.off_w = take(own_w ? e * es : 0);
   pl.off_kw = take((size_t)p->nt * nn * 8);
   pl.off_kz = take((size_t)p->nt * nn * 8);
@@ -114,7 +119,7 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_dos = take(p->nt * 8);
   pl.off_ranks = take(2 * (size_t)p->nt * 4);
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
-  pl.off_gpart = take((size_t)pl.nseg * pl.batch * 2 * nn * 8);
+  pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * pl.batch * 2 * nn * 8);
   pl.off_z = take((size_t)pl.batch * e * es);
   pl.off_y = take((size_t)pl.chunk * e * es);
   pl.total = o;
@@ -135,6 +140,7 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
     if ((p->nt + batch - 1) / batch != passes) continue;  // same batch as a smaller pass count
     Plan pl;
     pl.ldc = (p->nt + 3) / 4 * 4;
+    pl.ldk = (m1 + 7) / 8 * 8;
     pl.passes = passes;
     pl.batch = batch;
     pl.nseg = gram_segments(a->n, batch);
@@ -144,9 +150,13 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
     int chunk = m1;
     if (budget) {
       const double room = (double)budget - (double)fixed;
-      const double per = (double)align_up((size_t)e * es) + 0.0;
-      chunk = room > 0 ? (int)std::min<double>(m1, std::floor(room / ((double)e * es)) - 1) : 0;
-      (void)per;
+      chunk = room > 0 ? (int)std::min<double>(m1, std::floor(room / ((double)e * es))) : 0;
+      for (; chunk >= 1; --chunk) {  // the ring's size is rounded up to the alignment
+        pl.chunk = chunk;
+        layout(pl, a, p, own_w);
+        if (pl.total <= budget) break;
+      }
+      if (chunk < m1) chunk -= chunk % kMinChunk;  // chunk starts stay 16-byte aligned in the split tables
       if (chunk < std::min(m1, kMinChunk)) continue;
     }
     pl.chunk = chunk;
@@ -177,6 +187,8 @@ struct ssm_ctx {
   double* t = nullptr;
   double* c64 = nullptr;
   float* c32 = nullptr;
+  __bf16* chi = nullptr;
+  __bf16* clo = nullptr;
   void* w = nullptr;
   void* y = nullptr;
   void* z = nullptr;
@@ -248,6 +260,10 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->t = (double*)(c->ws + pl.off_t);
   c->c64 = (double*)(c->ws + pl.off_c64);
   c->c32 = p->precision == SSM_FP64 ? nullptr : (float*)(c->ws + pl.off_c32);
+  if (p->precision == SSM_FP32_BF16X3) {
+    c->chi = (__bf16*)(c->ws + pl.off_chi);
+    c->clo = (__bf16*)(c->ws + pl.off_clo);
+  }
   c->w = own_w ? (void*)(c->ws + pl.off_w) : const_cast<void*>(w_dev);
   c->y = c->ws + pl.off_y;
   c->z = c->ws + pl.off_z;
@@ -278,6 +294,11 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   if ((e = ssm::launch_coefficients(c0, hw, p->sigma, inv_norm, c->t, p->nt, p->degree, n_theta_for(p->degree),
                                     c->c64, c->c32, pl.ldc, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "coefficient kernel"));
+  if (c->chi) {
+    if ((e = ssm::launch_split_coefficients(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, pl.ldk, p->nt,
+                                            c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "coefficient split kernel"));
+  }
   if (own_w) {
     if ((e = ssm::launch_gaussian_block(p->seed, a->n, p->nv, p->precision == SSM_FP64 ? 0 : 1, c->w,
                                         c->stream)) != hipSuccess)
@@ -369,6 +390,10 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
       if (f64)
         err = ssm::launch_sweep_f64(e, kc, nb, c->c64 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0, (const double*)c->y,
                                     (double*)c->z, ch > 0, st);
+      else if (p.precision == SSM_FP32_BF16X3)
+        err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
+                                       c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0, (const float*)c->y,
+                                       (float*)c->z, ch > 0, st);
       else if (p.precision == SSM_FP32)
         err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
                                     (const float*)c->y, (float*)c->z, ch > 0, st);
@@ -571,7 +596,7 @@ ssm_status ssm_chebyshev(const ssm_csr* a, double lo, double hi, int32_t precisi
   if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(SSM_ERR_ARG, "need finite lo < hi");
   if (nv < 4 || nv % 4 != 0) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4");
   if (degree < 0) return fail(SSM_ERR_ARG, "degree must be >= 0");
-  if (precision < SSM_FP64 || precision > SSM_FP32_BF16SWEEP) return fail(SSM_ERR_ARG, "bad precision");
+  if (precision < SSM_FP64 || precision > SSM_FP32_BF16X3) return fail(SSM_ERR_ARG, "bad precision");
   const bool f64 = precision == SSM_FP64;
   const size_t es = f64 ? 8 : 4;
   const int64_t e = a->n * nv;
@@ -607,9 +632,30 @@ ssm_status ssm_sweep(int32_t precision, int64_t e, int32_t kc, int32_t ntb, cons
     err = ssm::launch_sweep_f32(e, kc, ntb, (const float*)c, ldc, ldc, (const float*)y, (float*)z, accumulate, st);
   else if (precision == SSM_FP32_BF16SWEEP)
     err = ssm::launch_sweep_bf16(e, kc, ntb, (const float*)c, ldc, ldc, (const float*)y, (float*)z, accumulate, st);
+  else if (precision == SSM_FP32_BF16X3)
+    return fail(SSM_ERR_ARG, "SSM_FP32_BF16X3 takes split tables: use ssm_split_coefficients and ssm_sweep_split");
   else
     return fail(SSM_ERR_ARG, "bad precision");
   return err == hipSuccess ? SSM_OK : hip_fail(err, "sweep GEMM");
+}
+
+ssm_status ssm_split_coefficients(const double* c, int64_t ldc, int32_t nt, int32_t m1, void* chi, void* clo,
+                                  int64_t ldk, void* stream) {
+  if (!c || !chi || !clo) return fail(SSM_ERR_ARG, "c, chi, clo must be non-NULL");
+  if (nt < 1 || m1 < 1 || ldc < nt || ldk < m1 || ldk % 8) return fail(SSM_ERR_ARG, "need ldc >= nt, ldk >= m1, ldk % 8 == 0");
+  if (((uintptr_t)chi | (uintptr_t)clo) % 16) return fail(SSM_ERR_ARG, "chi, clo must be 16-byte aligned");
+  hipError_t err = ssm::launch_split_coefficients(c, ldc, nt, m1, (__bf16*)chi, (__bf16*)clo, ldk, nt, (hipStream_t)stream);
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "coefficient split kernel");
+}
+
+ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, const void* clo, int64_t ldk,
+                           const void* y, void* z, int32_t accumulate, void* stream) {
+  if (!chi || !clo || !y || !z) return fail(SSM_ERR_ARG, "chi, clo, y, z must be non-NULL");
+  if (e < 1 || kc < 1 || ntb < 1 || ldk < kc || ldk % 8 || e % 4) return fail(SSM_ERR_ARG, "need e % 4 == 0, ldk >= kc, ldk % 8 == 0");
+  if (((uintptr_t)chi | (uintptr_t)clo | (uintptr_t)y) % 16) return fail(SSM_ERR_ARG, "pointers must be 16-byte aligned");
+  hipError_t err = ssm::launch_sweep_bf16x3(e, kc, ntb, (const __bf16*)chi, (const __bf16*)clo, ldk, ntb,
+                                            (const float*)y, (float*)z, accumulate, (hipStream_t)stream);
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "split sweep GEMM");
 }
 
 ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z, double* k_w,
@@ -618,7 +664,7 @@ ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const
   if (n < 1 || ntb < 1 || nseg < 1) return fail(SSM_ERR_ARG, "need n, ntb, nseg >= 1");
   if (nv < 4 || nv % 4) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4");
   if (nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d", kMaxNv);
-  if (precision < SSM_FP64 || precision > SSM_FP32_BF16SWEEP) return fail(SSM_ERR_ARG, "bad precision");
+  if (precision < SSM_FP64 || precision > SSM_FP32_BF16X3) return fail(SSM_ERR_ARG, "bad precision");
   hipError_t err = ssm::launch_gram(precision != SSM_FP64, n, nv, ntb, w, z, k_w, k_z, nseg, scratch, (hipStream_t)stream);
   return err == hipSuccess ? SSM_OK : hip_fail(err, "Gram kernel");
 }

@@ -39,7 +39,16 @@ hipError_t launch_sweep_f32(int64_t e, int kc, int ntb, const float* c, int64_t 
 hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols,
                              const float* y, float* z, int accumulate, hipStream_t stream);
 
-// Gram (gram.hip).
+// Split-BF16 sweep: chi/clo [i][ldk] (k contiguous, ldk % 8 == 0, 16-byte aligned rows),
+// arows = rows of chi/clo readable from the pointers.
+hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
+                               int64_t arows, const float* y, float* z, int accumulate, hipStream_t stream);
+size_t sweep_bf16x3_lds_bytes();
+hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo,
+                                     int64_t ldk, int ntp, hipStream_t stream);
+
+// Gram (gram.hip).  scratch: gram_scratch_slots(nseg) * ntb * 2 * nv * nv doubles.
+int gram_scratch_slots(int nseg);
 hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, double* k_w,
                        double* k_z, int nseg, double* scratch, hipStream_t stream);
 

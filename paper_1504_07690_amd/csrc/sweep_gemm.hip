@@ -344,6 +344,183 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split BF16 ("bf16x3", Henry, Tang & Heinecke, ARITH 2019): every FP32 operand x
+// is written as hi + lo with hi = bf16(x), lo = bf16(x - hi) (both round to nearest
+// even), and C^T Y ~= Chi^T Yhi + Chi^T Ylo + Clo^T Yhi on v_mfma_f32_32x32x16_bf16
+// with FP32 accumulation: about 16 mantissa bits per product at BF16 matrix rate.
+// The coefficients arrive pre-split in k-contiguous tables chi/clo [i][ldk]; the Y
+// tile is split in registers while being transposed: a thread reads 8 consecutive
+// k of 2 elements (8 float2) and writes, per element, 8 k of hi and of lo as two
+// 16-byte LDS stores.  Tile 256 points x 256 elements x 16 k; four waves in 2 x 2,
+// each 128 x 128 = 4 x 4 MFMA blocks (256 accumulators).
+// ---------------------------------------------------------------------------
+constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 16, X3_LDK = X3_BK + 8;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__global__ void __launch_bounds__(256) sweep_bf16x3_kernel(int64_t e, int kc, int ntb,
+                                                           const __bf16* __restrict__ chi,
+                                                           const __bf16* __restrict__ clo, int64_t ldk,
+                                                           int64_t arows, const float* __restrict__ y,
+                                                           float* __restrict__ z, int accumulate, int mt,
+                                                           int nt_tiles) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
+  __bf16(*Ahi)[X3_LDK] = (__bf16(*)[X3_LDK])x3_lds;
+  __bf16(*Alo)[X3_LDK] = Ahi + X3_BM;
+  __bf16(*Bhi)[X3_LDK] = Alo + X3_BM;
+  __bf16(*Blo)[X3_LDK] = Bhi + X3_BN;
+  int m_tile, n_tile;
+  tile_coords(mt, nt_tiles, m_tile, n_tile);
+  if (n_tile < 0) return;
+  const int64_t i0 = (int64_t)m_tile * X3_BM;
+  const int64_t q0 = (int64_t)n_tile * X3_BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // A staging: 256 rows x 16 k of hi and of lo = 2 x 512 16-byte pieces; thread t
+  // moves pieces t and t+256 of each (row = piece/2, k-octet = piece%2)
+  u16x8 ra_hi[2], ra_lo[2];
+  // B staging: elements (tid % 128) * 2 .. +1, k-octet tid / 128
+  f32x2 rb[8];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int piece = tid + 256 * u;
+      const int row = piece >> 1;
+      const int ko = (piece & 1) * 8;
+      const int64_t i = i0 + row;
+      const int k = k0 + ko;
+      u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (i < arows && k < kc) {
+        vh = *(const u16x8*)(chi + i * ldk + k);
+        vl = *(const u16x8*)(clo + i * ldk + k);
+        if (k + 8 > kc) {  // entries past the chunk belong to the next chunk
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (k + j >= kc) { vh[j] = 0; vl[j] = 0; }
+        }
+      }
+      ra_hi[u] = vh;
+      ra_lo[u] = vl;
+    }
+    const int c2 = (tid & 127) * 2;
+    const int ko = (tid >> 7) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + ko + j;
+      f32x2 v = {0.f, 0.f};
+      if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
+      rb[j] = v;
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int piece = tid + 256 * u;
+      *(u16x8*)&Ahi[piece >> 1][(piece & 1) * 8] = ra_hi[u];
+      *(u16x8*)&Alo[piece >> 1][(piece & 1) * 8] = ra_lo[u];
+    }
+    const int c2 = (tid & 127) * 2;
+    const int ko = (tid >> 7) * 8;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        __bf16 hh, ll;
+        split_bf16(rb[j][c], hh, ll);
+        h[j] = hh;
+        l[j] = ll;
+      }
+      *(bf16x8*)&Bhi[c2 + c][ko] = h;
+      *(bf16x8*)&Blo[c2 + c][ko] = l;
+    }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  const int nk = (kc + X3_BK - 1) / X3_BK;
+  load_tile(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    store_tile();
+    __syncthreads();
+    if (kt + 1 < nk) load_tile((kt + 1) * X3_BK);
+#pragma unroll
+    for (int kk = 0; kk < X3_BK; kk += 16) {
+      const int kb = kk + 8 * (lane >> 5);
+      bf16x8 bh[4], bl[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        bh[b] = *(const bf16x8*)&Bhi[wn * 128 + b * 32 + (lane & 31)][kb];
+        bl[b] = *(const bf16x8*)&Blo[wn * 128 + b * 32 + (lane & 31)][kb];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const bf16x8 ah = *(const bf16x8*)&Ahi[wm * 128 + a * 32 + (lane & 31)][kb];
+        const bf16x8 al = *(const bf16x8*)&Alo[wm * 128 + a * 32 + (lane & 31)][kb];
+        // small products first, the three products of one block four MFMAs apart
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t col = q0 + wn * 128 + b * 32 + (lane & 31);
+      if (col >= e) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = i0 + wm * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < ntb) {
+          float* p = z + row * e + col;
+          *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+        }
+      }
+    }
+}
+
+// chi/clo[i][k] = split of the FP64 coefficient c[k][i] (i < nt, k < m1), zero padded;
+// each part is rounded once, from double, to the nearest bfloat16 (ties to even)
+__global__ void __launch_bounds__(256) split_coefficients_kernel(const double* __restrict__ c, int64_t ldc, int nt,
+                                                                 int m1, __bf16* __restrict__ chi,
+                                                                 __bf16* __restrict__ clo, int64_t ldk, int ntp) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)ntp * ldk) return;
+  const int i = (int)(gid / ldk);
+  const int k = (int)(gid - (int64_t)i * ldk);
+  __bf16 hi = (__bf16)0.f, lo = (__bf16)0.f;
+  if (i < nt && k < m1) {
+    const double v = c[(int64_t)k * ldc + i];
+    hi = (__bf16)v;                 // one rounding, double -> bfloat16, nearest even
+    lo = (__bf16)(v - (double)hi);  // the remainder, rounded the same way
+  }
+  chi[gid] = hi;
+  clo[gid] = lo;
+}
+
 template <typename T, typename K>
 hipError_t launch_tiles(K kernel, int bm, int bn, int64_t e, int kc, int ntb, const T* c, int64_t ldc,
                         int64_t acols, const T* y, T* z, int accumulate, hipStream_t stream) {
@@ -367,6 +544,32 @@ hipError_t launch_sweep_f32(int64_t e, int kc, int ntb, const float* c, int64_t 
 hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t ldc, int64_t acols,
                             const double* y, double* z, int accumulate, hipStream_t stream) {
   return launch_tiles(sweep_f64_kernel, F64_BM, F64_BN, e, kc, ntb, c, ldc, acols, y, z, accumulate, stream);
+}
+
+size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * (X3_BM + X3_BN) * X3_LDK * sizeof(__bf16); }
+
+hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
+                               int64_t arows, const float* y, float* z, int accumulate, hipStream_t stream) {
+  const size_t lds = sweep_bf16x3_lds_bytes();
+  hipError_t err = hipFuncSetAttribute((const void*)sweep_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+  if (err != hipSuccess) return err;
+  const int mt = (ntb + X3_BM - 1) / X3_BM;
+  const int64_t ntiles = (e + X3_BN - 1) / X3_BN;
+  const int64_t nt_pad = (ntiles + 7) / 8 * 8;
+  const int64_t blocks = (int64_t)mt * nt_pad;
+  if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(256), lds, stream, e, kc, ntb, chi, clo, ldk,
+                     arows, y, z, accumulate, mt, (int)ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo,
+                                     int64_t ldk, int ntp, hipStream_t stream) {
+  const int64_t total = (int64_t)ntp * ldk;
+  hipLaunchKernelGGL(split_coefficients_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, c, ldc,
+                     nt, m1, chi, clo, ldk, ntp);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t ldc, int64_t acols, const float* y,

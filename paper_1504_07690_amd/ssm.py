@@ -13,7 +13,7 @@ import torch
 
 from . import _abi as A
 
-PRECISION = {"fp64": A.SSM_FP64, "fp32": A.SSM_FP32, "bf16": A.SSM_FP32_BF16SWEEP}
+PRECISION = {"fp64": A.SSM_FP64, "fp32": A.SSM_FP32, "bf16": A.SSM_FP32_BF16SWEEP, "bf16x3": A.SSM_FP32_BF16X3}
 
 
 def _ptr(t: torch.Tensor | None):
@@ -195,11 +195,34 @@ def sweep(precision, c: torch.Tensor, y: torch.Tensor, z: torch.Tensor, accumula
                             int(bool(accumulate)), _stream()), "ssm_sweep")
 
 
+def split_coefficients(c: torch.Tensor, nt: int, ldk: int):
+    """Split tables (chi, clo) of the FP64 coefficient table c (m1 x ldc) for bf16x3."""
+    _require_cuda(c)
+    m1, ldc = c.shape
+    chi = torch.empty(nt * ldk, dtype=torch.bfloat16, device=c.device)
+    clo = torch.empty_like(chi)
+    A.check(A.lib.ssm_split_coefficients(_ptr(c), int(ldc), int(nt), int(m1), _ptr(chi), _ptr(clo), int(ldk),
+                                         _stream()), "ssm_split_coefficients")
+    return chi.view(nt, ldk), clo.view(nt, ldk)
+
+
+def sweep_split(chi: torch.Tensor, clo: torch.Tensor, y: torch.Tensor, z: torch.Tensor, kc=None, accumulate=False):
+    """z[i] (+)= sum_{k<kc} c[k, i] y[k] in the bf16x3 arithmetic, c given by its split tables."""
+    _require_cuda(chi, clo, y, z)
+    ntb_tab, ldk = chi.shape
+    kc = y.shape[0] if kc is None else kc
+    ntb = z.shape[0]
+    assert ntb <= ntb_tab
+    e = y[0].numel()
+    A.check(A.lib.ssm_sweep_split(int(e), int(kc), int(ntb), _ptr(chi), _ptr(clo), int(ldk), _ptr(y), _ptr(z),
+                                  int(bool(accumulate)), _stream()), "ssm_sweep_split")
+
+
 def gram(precision, w: torch.Tensor, z: torch.Tensor, k_w: torch.Tensor, k_z: torch.Tensor, nseg=1):
     _require_cuda(w, z, k_w, k_z)
     n, nv = w.shape
     ntb = z.shape[0]
-    scratch = torch.empty(nseg * ntb * 2 * nv * nv, dtype=torch.float64, device=w.device)
+    scratch = torch.empty(4 * nseg * ntb * 2 * nv * nv, dtype=torch.float64, device=w.device)
     A.check(A.lib.ssm_gram(PRECISION[precision], int(n), int(nv), int(ntb), _ptr(w), _ptr(z), _ptr(k_w), _ptr(k_z),
                            int(nseg), _ptr(scratch), _stream()), "ssm_gram")
     return scratch

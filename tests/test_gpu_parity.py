@@ -145,6 +145,57 @@ def test_sweep(S, precision, kc, ntb, ldc, n, nv):
     assert np.all(np.abs(zd.cpu().numpy() - (ref + z0)) <= tol * (mag + np.abs(z0)) + 1e-300)
 
 
+def bf16_from_f64(x):
+    """double -> bfloat16 (8 significant bits), one rounding, ties to even."""
+    m, e = np.frexp(np.asarray(x, dtype=np.float64))
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)
+
+
+def bf16_split(x):
+    """hi = bf16(x), lo = bf16(x - hi) for float32 x (both round to nearest even)."""
+    x = np.asarray(x, dtype=np.float32)
+    hi = bf16_round(x)
+    lo = bf16_round((x - hi).astype(np.float32))
+    return hi.astype(np.float64), lo.astype(np.float64)
+
+
+@pytest.mark.parametrize("kc,ntb,m1,n,nv", [(37, 45, 37, 250, 12), (16, 300, 40, 64, 8), (1, 3, 8, 33, 4),
+                                            (70, 257, 1001, 130, 40)])
+def test_sweep_split_bf16(S, kc, ntb, m1, n, nv):
+    """bf16x3 sweep: the oracle's sweep applied to the split operands
+    (Chi Yhi + Chi Ylo + Clo Yhi), against the device's split tables and kernel."""
+    rng = _rng(kc * 7 + ntb)
+    ldc = (ntb + 3) // 4 * 4
+    ldk = (m1 + 7) // 8 * 8
+    c = rng.standard_normal((m1, ldc))
+    y = rng.standard_normal((kc, n, nv)).astype(np.float32).astype(np.float64)
+    z0 = rng.standard_normal((ntb, n, nv)).astype(np.float32).astype(np.float64)
+    cd = torch.tensor(c, device=DEV)
+    chi, clo = S.split_coefficients(cd, ntb, ldk)
+    # the tables against their definition
+    hi = bf16_from_f64(c[:, :ntb])
+    lo = bf16_from_f64(c[:, :ntb] - hi)
+    assert np.array_equal(chi.float().cpu().numpy()[:, :m1].T, hi)
+    assert np.array_equal(clo.float().cpu().numpy()[:, :m1].T, lo)
+    assert not chi.float().cpu().numpy()[:, m1:].any()
+    yhi, ylo = bf16_split(y)
+    mu_h, mu_l = hi[:kc], lo[:kc]
+    ref = O.sweep(mu_h, iter(yhi)) + O.sweep(mu_h, iter(ylo)) + O.sweep(mu_l, iter(yhi))
+    mag = O.sweep(np.abs(mu_h), iter(np.abs(y))) + O.sweep(np.abs(mu_l), iter(np.abs(y)))
+    tol = (3 * kc + 2) * 2.0 ** -24
+    yd = torch.tensor(y, dtype=torch.float32, device=DEV)
+    zd = torch.tensor(z0, dtype=torch.float32, device=DEV)
+    S.sweep_split(chi, clo, yd, zd, kc=kc, accumulate=False)
+    assert np.all(np.abs(zd.cpu().numpy() - ref) <= tol * mag + 1e-300)
+    zd = torch.tensor(z0, dtype=torch.float32, device=DEV)
+    S.sweep_split(chi, clo, yd, zd, kc=kc, accumulate=True)
+    assert np.all(np.abs(zd.cpu().numpy() - (ref + z0)) <= tol * (mag + np.abs(z0)) + 1e-300)
+    # against the unsplit product: about 16 significant bits
+    full = O.sweep(c[:kc, :ntb], iter(y))
+    fmag = O.sweep(np.abs(c[:kc, :ntb]), iter(np.abs(y)))
+    assert np.all(np.abs(zd.cpu().numpy() - z0 - full) <= 2.0 ** -14 * fmag + 1e-300)
+
+
 # ----------------------------------------------------------------------------
 # Gram
 # ----------------------------------------------------------------------------
@@ -257,7 +308,7 @@ def test_end_to_end_cfg1_fp64(S, cfg1_oracle):
     assert st["passes"] == 1 and st["spmm_launches"] == wl.degree
 
 
-@pytest.mark.parametrize("precision,bound", [("fp32", 1e-3), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-3), ("bf16x3", 1e-3), ("bf16", 2e-2)])
 def test_end_to_end_cfg1_mixed(S, cfg1_oracle, precision, bound):
     """FP32 meets the 1e-3 L1 gate.  Plain BF16 sweep inputs (8-bit mantissa) do not:
     their error is held to the bound measured for that mode, and the mode is
@@ -297,6 +348,8 @@ def test_end_to_end_ragged_anderson(S):
     assert np.abs(d64 - ref["dos"]).max() <= 1e-9 * ref["dos"].max()
     d32, *_ = _run(S, wl, "fp32")
     assert _l1(d32, ref["dos"]) <= 1e-3
+    dx3, *_ = _run(S, wl, "bf16x3")
+    assert _l1(dx3, ref["dos"]) <= 1e-3
 
 
 def test_identity_probe_exact_dos(S):
