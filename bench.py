@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep-point batches would shard across GPUs with no "
@@ -91,6 +94,13 @@ def main():
     from paper_1504_07690_amd import workloads as WL
 
     dev = "cuda:0"
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     t0 = time.time()
     wl = WL.make_workload(2)
     log(f"workload {wl.name}: n={wl.a.n} nnz={wl.a.nnz} nv={wl.nv} M={wl.degree} nt={wl.nt} "

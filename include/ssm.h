@@ -150,6 +150,38 @@ ssm_status ssm_get_views(const ssm_ctx* ctx, ssm_views* out);
 ssm_status ssm_destroy(ssm_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (not in the paper): the gradient of L = sum_i dos_bar[i] * dos[i]
+ * (the DOS of the last ssm_dos) with respect to every stored value of A, each
+ * value taken as an independent variable, the truncation sets of Algorithm 4
+ * frozen.  For Tr f(A) ~= sum_i w_i dos[i] (Algorithm 8) pass dos_bar = w.
+ *   per point:  Kbar_Z = dos_bar_i U (D P D) U^T, Kbar_W = dos_bar_i U (Gamma o
+ *               (Kt D P + P D Kt)) U^T (see geneig.hip), then
+ *               Zbar_i = W Kbar_W + 2 Z_i Kbar_Z;
+ *   Ybar_k = sum_i mu_k(t_i) Zbar_i;
+ *   Lambda_k = Ybar_k + 2 A~ Lambda_{k+1} - Lambda_{k+2} (k = M..1, Lambda_{M+1} =
+ *   Lambda_{M+2} = 0);  grad[e] = alpha (Lambda_1[r_e].W[c_e] + 2 sum_{k>=2}
+ *   Lambda_k[r_e].Y_{k-1}[c_e]),  alpha = 2/(hi - lo),  A symmetric.
+ * Arithmetic: Algorithm 4's backward and Kbar in FP64; Zbar, Ybar and Lambda in
+ * the context's block type; Ybar by the context's sweep kernel, except that
+ * SSM_FP32_BF16X3 forms it with FP32 MFMA (the sum over sweep points cancels
+ * strongly at high k, where the split products' 2^-16 relative error is
+ * amplified); the gradient accumulates in FP64.
+ * Needs the single-pass plan (every T_k(A~)W and every Z_i resident:
+ * SSM_ERR_UNSUPPORTED otherwise) and a previous ssm_dos (SSM_ERR_STATE); it
+ * overwrites the context's Z blocks, so the next backward needs a new ssm_dos.
+ * grad_dev: nnz doubles (device), overwritten.  workspace: device memory of
+ * at least ssm_backward_workspace_size bytes, 256-byte aligned.  Synchronises. */
+ssm_status ssm_backward_workspace_size(const ssm_ctx* ctx, size_t* bytes);
+ssm_status ssm_backward(ssm_ctx* ctx, const double* dos_bar_host, double* grad_dev, void* workspace,
+                        size_t ws_bytes);
+
+/* Device times (milliseconds) of the last ssm_backward. */
+typedef struct ssm_backward_stats {
+  double ms_total, ms_geneig, ms_zbar, ms_ybar, ms_reverse;
+} ssm_backward_stats;
+ssm_status ssm_get_backward_stats(const ssm_ctx* ctx, ssm_backward_stats* out);
+
+/* ------------------------------------------------------------------------
  * Algorithm 8 (host only): weights w_i with Tr f(A) ~= sum_i w_i phi~(t_i),
  * for the nt midpoints t_i = c0 + hw(-1 + (2i+1)/nt) of [lo, hi].
  * h(t) = f(t) pi(t) + c (1 - pi(t)) (Eq. hform, pi of Eq. pifunc with

@@ -41,6 +41,11 @@ class ssm_stats(C.Structure):
                 ("batch", C.c_int32), ("gram_segments", C.c_int32)]
 
 
+class ssm_backward_stats(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_geneig", C.c_double), ("ms_zbar", C.c_double),
+                ("ms_ybar", C.c_double), ("ms_reverse", C.c_double)]
+
+
 class ssm_views(C.Structure):
     _fields_ = [("w", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("k_w", C.c_void_p),
                 ("k_z", C.c_void_p), ("coeff", C.c_void_p), ("chunk", C.c_int32), ("batch", C.c_int32),
@@ -62,6 +67,9 @@ _SIGS = {
     "ssm_get_stats": (C.c_int, [_P, C.POINTER(ssm_stats)]),
     "ssm_get_views": (C.c_int, [_P, C.POINTER(ssm_views)]),
     "ssm_destroy": (C.c_int, [_P]),
+    "ssm_backward_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "ssm_backward": (C.c_int, [_P, C.POINTER(C.c_double), _P, _P, C.c_size_t]),
+    "ssm_get_backward_stats": (C.c_int, [_P, C.POINTER(ssm_backward_stats)]),
     "ssm_trace_weights": (C.c_int, [C.c_double, C.c_double, C.c_int32, C.c_int64, C.c_double, C.c_double,
                                     C.c_double, SCALAR_FN, _P, C.POINTER(C.c_double)]),
     "ssm_coefficients": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int64, _P, C.c_int32, C.c_int32,

@@ -25,14 +25,19 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // [x per_xcd, (x+1) per_xcd), swept in order.  A stencil neighbour a few planes
 // away was then gathered by the same XCD shortly before, and is found in its L2.
 // Up to 8 CSR entries of a row are fetched before their gathers are issued, so the
-// gathers of one row are in flight together.
+// gathers of one row are in flight together.  The block read once (xprev, d) and the
+// block written are streamed with non-temporal hints, leaving the cache to the
+// gathered block x.
+//
+// out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null; the reverse
+// recurrence of the adjoint uses d for its direct seed).
 template <typename T, typename V>
 __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
                                                         const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col_idx,
                                                         const T* __restrict__ val, T a, T b, T c,
                                                         const V* __restrict__ x, const V* __restrict__ xprev,
-                                                        V* __restrict__ out) {
+                                                        const V* __restrict__ d, V* __restrict__ out) {
   const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (lblock >= nblocks) return;
   const int64_t gid = lblock * blockDim.x + threadIdx.x;
@@ -58,20 +63,21 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int6
     for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
   }
   V res = a * acc + b * x[gid];
-  if (xprev) res += c * xprev[gid];
-  out[gid] = res;
+  if (xprev) res += c * __builtin_nontemporal_load(&xprev[gid]);
+  if (d) res += __builtin_nontemporal_load(&d[gid]);
+  __builtin_nontemporal_store(res, &out[gid]);
 }
 
 template <typename T, typename V, int VEC>
 hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx, const T* val, T a, T b,
-                  T c, const T* x, const T* xprev, T* out, hipStream_t stream) {
+                  T c, const T* x, const T* xprev, const T* d, T* out, hipStream_t stream) {
   const int nvv = nv / VEC;
   const int64_t threads = n * nvv;
   const int64_t nblocks = (threads + 255) / 256;
   const int64_t per_xcd = (nblocks + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL((cheb_step_kernel<T, V>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv, nblocks,
-                     per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (V*)out);
+                     per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out);
   return hipGetLastError();
 }
 
@@ -79,14 +85,14 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
 
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
-                                const double* xprev, double* out, hipStream_t stream) {
-  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, out, stream);
+                                const double* xprev, const double* d, double* out, hipStream_t stream) {
+  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, stream);
 }
 
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
-                                const float* xprev, float* out, hipStream_t stream) {
-  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, out, stream);
+                                const float* xprev, const float* d, float* out, hipStream_t stream) {
+  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, stream);
 }
 
 }  // namespace ssm

@@ -243,12 +243,210 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   }
 }
 
+// Backward of Algorithm 4 for one sweep point, truncation sets frozen (the
+// estimate is piecewise smooth in K_W, K_Z; the sets change only on a null set).
+// In the eigenbasis U of K_W (s = eigenvalues), with F(s) = s^-1/2 on the kept
+// set and 0 elsewhere, D = diag(F(s)), Kt = U^T K_Z U, B = D Kt D restricted to
+// the kept set, P = projector (embedded in U coordinates) on the eigenvectors of
+// B whose eigenvalues pass the range test:
+//   phi = tr(P D Kt D),
+//   dphi/dK_Z = U (D P D) U^T,
+//   dphi/dK_W = U (Gamma o (Kt D P + P D Kt)) U^T      (Daleckii-Krein),
+// Gamma_jk = (F(s_j) - F(s_k)) / (s_j - s_k), Gamma_jj = F'(s_j) = -s_j^-3/2 / 2 on
+// the kept set; kept/kept entries are -1/(sqrt s_j sqrt s_k (sqrt s_j + sqrt s_k)).
+// Both are scaled by phibar[i].  Scratch per point: 3 N_v x N_v doubles
+// (U, Kt, and one product).
+__global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, const double* __restrict__ k_w,
+                                                                     const double* __restrict__ k_z, double g_max,
+                                                                     double tau, double rho,
+                                                                     const double* __restrict__ phibar,
+                                                                     double* __restrict__ kw_bar,
+                                                                     double* __restrict__ kz_bar,
+                                                                     double* __restrict__ scratch) {
+  extern __shared__ double lds[];
+  const int n = nv;
+  const int ld = n + 1;
+  GeShared sh;
+  sh.A = lds;
+  sh.V = sh.A + n * ld;
+  sh.s = sh.V + n * ld;
+  sh.scale = sh.s + GE_MAX_NV;
+  sh.cs = sh.scale + GE_MAX_NV;
+  sh.sn = sh.cs + GE_MAX_NV / 2;
+  sh.red = sh.sn + GE_MAX_NV / 2;
+  sh.pp = (int*)(sh.red + GE_THREADS);
+  sh.qq = sh.pp + GE_MAX_NV / 2;
+  sh.kidx = sh.qq + GE_MAX_NV / 2;
+  sh.misc = sh.kidx + GE_MAX_NV;
+  double* f = sh.scale;  // F(s_j) for every j (0 when dropped)
+
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  const double* kw = k_w + i * nn;
+  const double* kz = k_z + i * nn;
+  double* ug = scratch + (3 * i + 0) * nn;   // U
+  double* ktg = scratch + (3 * i + 1) * nn;  // Kt = U^T K_Z U
+  double* tg = scratch + (3 * i + 2) * nn;   // products
+  double* kwb = kw_bar + i * nn;
+  double* kzb = kz_bar + i * nn;
+  const double pb = phibar[i];
+
+  // 1. eig(K_W)
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int r = idx / n, c = idx - r * n;
+    sh.A[r * ld + c] = kw[idx];
+    sh.V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi(sh, sh.V, n, ld);
+  for (int j = tid; j < n; j += GE_THREADS) sh.s[j] = sh.A[j * ld + j];
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) ug[idx] = sh.V[(idx / n) * ld + idx % n];
+  __syncthreads();
+  // 2. truncation (as in the forward kernel)
+  if (tid == 0) {
+    double smax = -INFINITY;
+    for (int j = 0; j < n; ++j) smax = fmax(smax, sh.s[j]);
+    int r1 = 0;
+    for (int j = 0; j < n; ++j) {
+      const bool keep = smax > 0.0 && sh.s[j] >= tau * smax;
+      f[j] = keep ? 1.0 / sqrt(sh.s[j]) : 0.0;
+      if (keep) sh.kidx[r1++] = j;
+    }
+    sh.misc[0] = r1;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int r1 = sh.misc[0];
+  if (r1 == 0 || pb == 0.0) {
+    for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+      kwb[idx] = 0.0;
+      kzb[idx] = 0.0;
+    }
+    return;
+  }
+  // 3. Kt = U^T K_Z U: T = K_Z U (global), then Kt = U^T T -> A and global
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int r = idx / n, c = idx - r * n;
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += kz[(int64_t)r * n + q] * sh.V[q * ld + c];
+    tg[idx] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int r = idx / n, c = idx - r * n;
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += sh.V[q * ld + r] * tg[(int64_t)q * n + c];
+    sh.A[r * ld + c] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // symmetrise, keep a copy
+    const int r = idx / n, c = idx - r * n;
+    ktg[idx] = 0.5 * (sh.A[r * ld + c] + sh.A[c * ld + r]);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // 4. B = D Kt D on the kept set -> A (r1 x r1), eigenvectors -> V
+  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+    const int a = idx / r1, b = idx - a * r1;
+    const int ka = sh.kidx[a], kb = sh.kidx[b];
+    sh.A[a * ld + b] = f[ka] * ktg[(int64_t)ka * n + kb] * f[kb];
+    sh.V[a * ld + b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi(sh, sh.V, r1, ld);
+  // 5. P (U coordinates, n x n) = sum over in-range xi of x x^T, embedded -> global tg
+  const double hi = (1.0 + rho) * g_max;
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) tg[idx] = 0.0;
+  __threadfence_block();
+  __syncthreads();
+  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+    const int a = idx / r1, b = idx - a * r1;
+    double acc = 0.0;
+    for (int j = 0; j < r1; ++j) {
+      const double xi = sh.A[j * ld + j];
+      if (xi >= 0.0 && xi <= hi) acc += sh.V[a * ld + j] * sh.V[b * ld + j];
+    }
+    tg[(int64_t)sh.kidx[a] * n + sh.kidx[b]] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // 6. M1 = Gamma o (Kt D P + P D Kt) -> V;  M2 = D P D -> A
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int j = idx / n, k = idx - j * n;
+    double acc = 0.0;  // (Kt D P)[j][k]
+    for (int q = 0; q < n; ++q) acc += ktg[(int64_t)j * n + q] * f[q] * tg[(int64_t)q * n + k];
+    sh.V[j * ld + k] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int j = idx / n, k = idx - j * n;
+    if (j > k) continue;
+    const double sj = sh.s[j], sk = sh.s[k];
+    const bool kj = f[j] != 0.0, kk = f[k] != 0.0;
+    double g;
+    if (j == k) {
+      g = kj ? -0.5 * f[j] * f[j] * f[j] : 0.0;
+    } else if (kj && kk) {
+      const double qj = sqrt(sj), qk = sqrt(sk);
+      g = -1.0 / (qj * qk * (qj + qk));
+    } else if (kj || kk) {
+      g = (f[j] - f[k]) / (sj - sk);
+    } else {
+      g = 0.0;
+    }
+    const double h = sh.V[j * ld + k] + sh.V[k * ld + j];
+    sh.V[j * ld + k] = g * h;
+    sh.V[k * ld + j] = g * h;
+  }
+  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    const int j = idx / n, k = idx - j * n;
+    sh.A[j * ld + k] = f[j] * tg[idx] * f[k];
+  }
+  __syncthreads();
+  // 7. back to the original coordinates: X = U M U^T, for M1 (-> kw_bar) and M2 (-> kz_bar)
+  for (int which = 0; which < 2; ++which) {
+    const double* m = which == 0 ? sh.V : sh.A;
+    double* out = which == 0 ? kwb : kzb;
+    for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // T = U M
+      const int r = idx / n, c = idx - r * n;
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += ug[(int64_t)r * n + q] * m[q * ld + c];
+      tg[idx] = acc;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // out = T U^T
+      const int r = idx / n, c = idx - r * n;
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += tg[(int64_t)r * n + q] * ug[(int64_t)c * n + q];
+      out[idx] = pb * acc;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 size_t geneig_lds_bytes(int nv) {
   const size_t n = (size_t)nv, ld = n + 1;
   return (2 * n * ld + 2 * GE_MAX_NV + GE_MAX_NV + GE_THREADS) * sizeof(double) +
          (GE_MAX_NV + GE_MAX_NV + 4) * sizeof(int);
+}
+
+hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                                  double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
+                                  hipStream_t stream) {
+  if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
+  const size_t lds = geneig_lds_bytes(nv);
+  hipError_t err = hipFuncSetAttribute((const void*)geneig_backward_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(geneig_backward_kernel, dim3(ntb), dim3(GE_THREADS), lds, stream, nv, k_w, k_z, g_max, tau, rho,
+                     phibar, kw_bar, kz_bar, scratch);
+  return hipGetLastError();
 }
 
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,

@@ -204,6 +204,8 @@ struct ssm_ctx {
   ssm_stats stats{};
   std::vector<hipEvent_t> events;
   int last_batch_start = 0;
+  bool z_valid = false;  // Z holds the last ssm_dos's blocks (the backward overwrites them)
+  ssm_backward_stats bstats{};
 };
 
 extern "C" {
@@ -372,10 +374,11 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
           const double cc = (k == 1) ? 0.0 : -1.0;
           if (f64)
             err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
-                                            (const double*)x, (const double*)xp, (double*)out, st);
+                                            (const double*)x, (const double*)xp, nullptr, (double*)out, st);
           else
             err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
-                                            (float)b, (float)cc, (const float*)x, (const float*)xp, (float*)out, st);
+                                            (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out,
+                                            st);
           ++spmm_launches;
         }
         if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
@@ -461,6 +464,181 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (ranks_host) std::copy(ranks.begin(), ranks.end(), ranks_host);
   c->dos_host = dos;
   c->have_dos = true;
+  c->z_valid = true;
+  return SSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kBackwardSegment = 64;  // Ybar blocks formed per transposed-sweep launch
+
+struct BackwardLayout {
+  size_t phibar, kwb, kzb, gescr, row_of, ct64, ct32, lam, ybar, total;
+  int64_t ldct;
+  int seg;
+};
+
+BackwardLayout backward_layout(const ssm_ctx* c) {
+  const ssm_params& p = c->p;
+  const size_t es = elem_bytes(p.precision);
+  const size_t e = (size_t)c->a.n * p.nv;
+  const size_t nn = (size_t)p.nv * p.nv;
+  const int m1 = p.degree + 1;
+  BackwardLayout L{};
+  L.ldct = (m1 + 3) / 4 * 4;
+  L.seg = std::min(kBackwardSegment, m1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  L.phibar = take(p.nt * 8);
+  L.kwb = take(p.nt * nn * 8);
+  L.kzb = take(p.nt * nn * 8);
+  L.gescr = take(3 * p.nt * nn * 8);
+  L.row_of = take((size_t)c->a.nnz * 4);
+  L.ct64 = take(p.precision == SSM_FP64 ? (size_t)p.nt * L.ldct * 8 : 0);
+  L.ct32 = take(p.precision != SSM_FP64 ? (size_t)p.nt * L.ldct * 4 : 0);
+  L.lam = take(3 * e * es);
+  L.ybar = take((size_t)L.seg * e * es);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+ssm_status ssm_backward_workspace_size(const ssm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(SSM_ERR_ARG, "ctx and bytes must be non-NULL");
+  *bytes = backward_layout(c).total;
+  return SSM_OK;
+}
+
+ssm_status ssm_get_backward_stats(const ssm_ctx* c, ssm_backward_stats* out) {
+  if (!c || !out) return fail(SSM_ERR_ARG, "ctx and out must be non-NULL");
+  *out = c->bstats;
+  return SSM_OK;
+}
+
+ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev, void* workspace, size_t ws_bytes) {
+  if (!c || !dos_bar_host || !grad_dev || !workspace) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+  const ssm_params& p = c->p;
+  const Plan& pl = c->pl;
+  const int m = p.degree, m1 = m + 1;
+  if (pl.passes != 1 || pl.chunk != m1)
+    return fail(SSM_ERR_UNSUPPORTED, "the adjoint needs the single-pass plan (all T_k(A~)W and Z resident)");
+  if (!c->have_dos || !c->z_valid) return fail(SSM_ERR_STATE, "ssm_backward needs a preceding ssm_dos");
+  for (int i = 0; i < p.nt; ++i)
+    if (!std::isfinite(dos_bar_host[i])) return fail(SSM_ERR_ARG, "dos_bar[%d] is not finite", i);
+  const BackwardLayout L = backward_layout(c);
+  if (ws_bytes < L.total || ((uintptr_t)workspace % kAlign))
+    return fail(SSM_ERR_WORKSPACE, "backward needs %zu bytes (256-byte aligned), got %zu", L.total, ws_bytes);
+  char* ws = (char*)workspace;
+  const int64_t n = c->a.n;
+  const int nv = p.nv;
+  const int64_t e = n * nv;
+  const size_t es = elem_bytes(p.precision);
+  const bool f64 = p.precision == SSM_FP64;
+  const double alpha = 2.0 / (p.hi - p.lo);
+  const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
+  const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
+  hipStream_t st = c->stream;
+  double* phibar = (double*)(ws + L.phibar);
+  double* kwb = (double*)(ws + L.kwb);
+  double* kzb = (double*)(ws + L.kzb);
+  double* gescr = (double*)(ws + L.gescr);
+  int32_t* row_of = (int32_t*)(ws + L.row_of);
+  char* lam = ws + L.lam;
+  char* ybar = ws + L.ybar;
+  auto lam_slot = [&](int k) { return lam + (size_t)(k % 3) * e * es; };
+  auto y_slot = [&](int k) -> const char* { return (const char*)c->y + (size_t)k * e * es; };
+
+  hipEvent_t ev[6];
+  for (auto& x : ev) SSM_HIP(hipEventCreate(&x), "hipEventCreate");
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  SSM_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
+  SSM_HIP(hipMemcpyAsync(phibar, dos_bar_host, sizeof(double) * p.nt, hipMemcpyHostToDevice, st), "copy dos_bar");
+  hipError_t err = ssm::launch_geneig_backward(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, phibar, kwb, kzb,
+                                               gescr, st);
+  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 backward kernel");
+  SSM_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
+  err = ssm::launch_zbar(!f64, n, nv, p.nt, c->w, c->z, kwb, kzb, st);
+  if (err != hipSuccess) return hip_fail(err, "Zbar kernel");
+  c->z_valid = false;
+  SSM_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
+  // transposed coefficient table for Ybar = C Zbar
+  err = ssm::launch_transpose_coefficients(c->c64, pl.ldc, p.nt, m1, f64 ? (double*)(ws + L.ct64) : nullptr,
+                                             f64 ? nullptr : (float*)(ws + L.ct32), L.ldct, st);
+  if (err == hipSuccess) err = ssm::launch_row_of(n, c->a.row_ptr, row_of, st);
+  if (err != hipSuccess) return hip_fail(err, "adjoint set-up kernels");
+  SSM_HIP(hipMemsetAsync(grad_dev, 0, sizeof(double) * c->a.nnz, st), "clear gradient");
+
+  float ms_ybar = 0.f, ms_rev = 0.f;
+  const int nseg = (m1 + L.seg - 1) / L.seg;
+  for (int sidx = nseg - 1; sidx >= 0; --sidx) {
+    const int k_lo = sidx * L.seg;
+    const int k_hi = std::min(m, k_lo + L.seg - 1);
+    const int len = k_hi - k_lo + 1;
+    SSM_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
+    if (p.precision == SSM_FP64)
+      err = ssm::launch_sweep_f64(e, p.nt, len, (const double*)(ws + L.ct64) + k_lo, L.ldct, L.ldct - k_lo,
+                                  (const double*)c->z, (double*)ybar, 0, st);
+    else if (p.precision == SSM_FP32_BF16SWEEP)
+      err = ssm::launch_sweep_bf16(e, p.nt, len, (const float*)(ws + L.ct32) + k_lo, L.ldct, L.ldct - k_lo,
+                                   (const float*)c->z, (float*)ybar, 0, st);
+    else  // FP32, and the split-BF16 mode: its transposed sweep runs in FP32 (see the header)
+      err = ssm::launch_sweep_f32(e, p.nt, len, (const float*)(ws + L.ct32) + k_lo, L.ldct, L.ldct - k_lo,
+                                  (const float*)c->z, (float*)ybar, 0, st);
+    if (err != hipSuccess) return hip_fail(err, "transposed sweep");
+    SSM_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
+    for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
+      const char* yb = ybar + (size_t)(k - k_lo) * e * es;
+      char* out = lam_slot(k);
+      if (k == m) {
+        err = hipMemcpyAsync(out, yb, e * es, hipMemcpyDeviceToDevice, st);
+      } else {
+        const void* x = lam_slot(k + 1);
+        const void* xp = (k + 2 <= m) ? (const void*)lam_slot(k + 2) : nullptr;
+        if (f64)
+          err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
+                                          2 * beta, xp ? -1.0 : 0.0, (const double*)x, (const double*)xp,
+                                          (const double*)yb, (double*)out, st);
+        else
+          err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
+                                          (float)(2 * alpha), (float)(2 * beta), xp ? -1.0f : 0.0f, (const float*)x,
+                                          (const float*)xp, (const float*)yb, (float*)out, st);
+      }
+      if (err != hipSuccess) return hip_fail(err, "reverse recurrence");
+      err = ssm::launch_sddmm(!f64, c->a.nnz, nv, row_of, c->a.col_idx, out, y_slot(k - 1),
+                              (k == 1 ? 1.0 : 2.0) * alpha, grad_dev, st);
+      if (err != hipSuccess) return hip_fail(err, "gradient SDDMM");
+    }
+    SSM_HIP(hipEventRecord(ev[5], st), "hipEventRecord");
+    SSM_HIP(hipEventSynchronize(ev[5]), "hipEventSynchronize");
+    float a1 = 0.f, a2 = 0.f;
+    SSM_HIP(hipEventElapsedTime(&a1, ev[3], ev[4]), "hipEventElapsedTime");
+    SSM_HIP(hipEventElapsedTime(&a2, ev[4], ev[5]), "hipEventElapsedTime");
+    ms_ybar += a1;
+    ms_rev += a2;
+  }
+  SSM_HIP(hipStreamSynchronize(st), "ssm_backward sync");
+  float t_all = 0.f, t_ge = 0.f, t_zb = 0.f;
+  SSM_HIP(hipEventElapsedTime(&t_ge, ev[0], ev[1]), "hipEventElapsedTime");
+  SSM_HIP(hipEventElapsedTime(&t_zb, ev[1], ev[2]), "hipEventElapsedTime");
+  SSM_HIP(hipEventElapsedTime(&t_all, ev[0], ev[5]), "hipEventElapsedTime");
+  c->bstats.ms_total = t_all;
+  c->bstats.ms_geneig = t_ge;
+  c->bstats.ms_zbar = t_zb;
+  c->bstats.ms_ybar = ms_ybar;
+  c->bstats.ms_reverse = ms_rev;
   return SSM_OK;
 }
 
@@ -609,10 +787,10 @@ ssm_status ssm_chebyshev(const ssm_csr* a, double lo, double hi, int32_t precisi
     const char* xp = k >= 2 ? (char*)y + (size_t)(k - 2) * e * es : nullptr;
     const double aa = k == 1 ? alpha : 2 * alpha, bb = k == 1 ? beta : 2 * beta, cc = k == 1 ? 0.0 : -1.0;
     hipError_t err = f64 ? ssm::launch_cheb_step_f64(a->n, nv, a->row_ptr, a->col_idx, (const double*)a->values, aa, bb,
-                                                     cc, (const double*)x, (const double*)xp, (double*)out, st)
+                                                     cc, (const double*)x, (const double*)xp, nullptr, (double*)out, st)
                          : ssm::launch_cheb_step_f32(a->n, nv, a->row_ptr, a->col_idx, (const float*)a->values,
                                                      (float)aa, (float)bb, (float)cc, (const float*)x,
-                                                     (const float*)xp, (float*)out, st);
+                                                     (const float*)xp, nullptr, (float*)out, st);
     if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
   }
   return SSM_OK;

@@ -15,14 +15,22 @@ size_t coefficient_lds_bytes(int n_theta);
 hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, void* w, hipStream_t stream);
 
 // One Chebyshev step (cheb_spmm.hip):
-//   out = a * (A x) + b * x + c * xprev   (xprev may be null when c == 0)
+//   out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null)
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
-                                const double* xprev, double* out, hipStream_t stream);
+                                const double* xprev, const double* d, double* out, hipStream_t stream);
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
-                                const float* xprev, float* out, hipStream_t stream);
+                                const float* xprev, const float* d, float* out, hipStream_t stream);
 
+// Adjoint (adjoint.hip).
+hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kw_bar,
+                       const double* kz_bar, hipStream_t stream);
+hipError_t launch_sddmm(int is_f32, int64_t nnz, int nv, const int32_t* row_of, const int32_t* col_idx,
+                        const void* lam, const void* y, double coef, double* abar, hipStream_t stream);
+hipError_t launch_row_of(int64_t n, const int32_t* row_ptr, int32_t* row_of, hipStream_t stream);
+hipError_t launch_transpose_coefficients(const double* c, int64_t ldc, int nt, int m1, double* ct64, float* ct32,
+                                         int64_t ldct, hipStream_t stream);
 // Sum of squares of `count` elements, two deterministic stages (reduce.hip).
 // partial must hold reduce_partials() doubles; result written to *out (device).
 int reduce_partials();
@@ -57,5 +65,10 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
                                double tau, double rho, double* dos, int32_t* ranks, double* scratch,
                                hipStream_t stream);
 size_t geneig_lds_bytes(int nv);
+// Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z.
+// scratch: 3 * ntb * nv * nv doubles.
+hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                                  double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
+                                  hipStream_t stream);
 
 }  // namespace ssm

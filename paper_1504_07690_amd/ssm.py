@@ -137,6 +137,25 @@ class SSM:
         out["w"] = self.w_in if self.w_in is not None else self._view(v.w, e, self.elem).view(n, nv)
         return out
 
+    def backward(self, dos_bar) -> torch.Tensor:
+        """Gradient of sum_i dos_bar[i] dos[i] w.r.t. the stored values (ssm_backward):
+        a float64 device tensor of nnz entries.  Consumes the Z blocks of the last dos()."""
+        dos_bar = np.ascontiguousarray(np.asarray(dos_bar, dtype=np.float64))
+        assert dos_bar.shape == (self.nt,)
+        size = C.c_size_t(0)
+        A.check(A.lib.ssm_backward_workspace_size(self._ctx, C.byref(size)), "ssm_backward_workspace_size")
+        ws = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=self.ws.device)
+        base = ws.data_ptr() + (-ws.data_ptr()) % 256
+        grad = torch.empty(self.csr.nnz, dtype=torch.float64, device=self.ws.device)
+        A.check(A.lib.ssm_backward(self._ctx, dos_bar.ctypes.data_as(C.POINTER(C.c_double)), _ptr(grad),
+                                   C.c_void_p(base), C.c_size_t(int(size.value))), "ssm_backward")
+        return grad
+
+    def backward_stats(self) -> dict:
+        s = A.ssm_backward_stats()
+        A.check(A.lib.ssm_get_backward_stats(self._ctx, C.byref(s)), "ssm_get_backward_stats")
+        return {k: getattr(s, k) for k, _ in A.ssm_backward_stats._fields_}
+
     def close(self):
         if self._ctx:
             A.check(A.lib.ssm_destroy(self._ctx), "ssm_destroy")
@@ -147,6 +166,36 @@ class SSM:
             self.close()
         except Exception:
             pass
+
+
+class SpectrumSweep(torch.autograd.Function):
+    """values (nnz, device) -> DOS estimate at the sweep points (float64, device).
+
+    backward runs the library's adjoint (ssm_backward): the gradient of
+    sum_i grad_out[i] dos[i] with respect to every stored value."""
+
+    @staticmethod
+    def forward(fctx, values, row_ptr, col_idx, n, opts):
+        csr = DeviceCSR.__new__(DeviceCSR)
+        csr.n, csr.row_ptr, csr.col_idx = int(n), row_ptr, col_idx
+        csr.values = values.detach().contiguous()
+        csr.nnz = int(col_idx.numel())
+        obj = SSM(csr, **opts)
+        dos, _, _ = obj.dos()
+        fctx.obj = obj
+        fctx.vdtype = values.dtype
+        return torch.as_tensor(dos, device=values.device)
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        grad = fctx.obj.backward(grad_out.detach().double().cpu().numpy())
+        fctx.obj.close()
+        return grad.to(fctx.vdtype), None, None, None, None
+
+
+def dos_autograd(values: torch.Tensor, row_ptr: torch.Tensor, col_idx: torch.Tensor, n: int, **opts) -> torch.Tensor:
+    """Differentiable DOS: opts are SSM's keyword arguments (lo, hi, sigma, nv, degree, t, ...)."""
+    return SpectrumSweep.apply(values, row_ptr, col_idx, n, opts)
 
 
 def trace_weights(f, *, lo, hi, nt, n, sigma, a=0.9, sigma_tilde=0.016) -> np.ndarray:

@@ -305,3 +305,49 @@ def test_trace_weights_gaussian_semigroup():
     ref = np.exp(-t * t / (2 * r * r)) / math.sqrt(2 * math.pi * r * r)
     # rounding noise in h^ is amplified by at most 1/eta = 1e10 at the cutoff
     assert np.abs(f_tilde - ref).max() < 1e-6 * ref.max()
+
+
+# ----------------------------------------------------------------------------
+# Gradient reference: central differences of the oracle
+# ----------------------------------------------------------------------------
+def _sym_direction(a, seed):
+    """A symmetric perturbation of the stored values (the (r, c) and (c, r) entries equal)."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(a.nnz)
+    m = sp_csr(a, d)
+    m = 0.5 * (m + m.T)
+    m = m.tocsr()
+    m.sort_indices()
+    return np.asarray(m[np.repeat(np.arange(a.n), np.diff(a.row_ptr)), a.col_idx]).ravel()
+
+
+def sp_csr(a, vals):
+    import scipy.sparse as sp
+    return sp.csr_matrix((vals, a.col_idx, a.row_ptr), shape=(a.n, a.n))
+
+
+@pytest.mark.slow
+def test_oracle_trace_gradient_matches_fprime():
+    """With W = I the SS-DGC trace of f is Tr f(A) up to the expansion, truncation and
+    deconvolution errors, so its derivative along a symmetric direction E is
+    Tr(f'(A) E): central differences of the oracle against the dense eigen-decomposition."""
+    rng = np.random.default_rng(4)
+    a = WL.laplacian_2d_dirichlet(8, rng.uniform(-1, 1, 64))
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    nt, degree, sigma = 900, 1200, 0.005 * hw
+    t = 0.5 * (lo + hi) + hw * WL.midpoint_grid(nt)
+    f = lambda x: np.exp(-0.5 * x)
+    w = O.trace_weights(f, a.n, lo, hi, nt, sigma)
+    e = _sym_direction(a, 1)
+    h = 1e-5
+
+    def tr(vals):
+        b = WL.CSR(a.n, a.row_ptr, a.col_idx, vals)
+        return w @ O.ss_dgc(b, np.eye(a.n), t, degree, sigma, lo, hi)["dos"]
+
+    fd = (tr(a.values + h * e) - tr(a.values - h * e)) / (2 * h)
+    lam, q = np.linalg.eigh(a.to_dense())
+    fprime = (q * (-0.5 * np.exp(-0.5 * lam))) @ q.T
+    exact = np.sum(fprime * sp_csr(a, e).toarray())
+    assert abs(fd - exact) <= 1e-6 * abs(exact)
