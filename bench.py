@@ -2,12 +2,15 @@
 
 Workload: the 3D Anderson model on a 64^3 periodic lattice (N = 262144, hopping -1,
 disorder uniform in [-2, 2]), N_v = 80, Chebyshev degree M = 1000, N_t = 1000
-midpoint sweep points, sigma = 0.01 in the rescaled variable; FP32 recurrence and
-sweep, FP64 Gram / Algorithm 4.  One step = one full ssm_dos (coefficients and W
-are set up once, outside the timed region).
+midpoint sweep points, sigma = 0.01 in the rescaled variable.  Default path: FP32
+recurrence, split-BF16 (three BF16 MFMA products, FP32 accumulation) sweep, FP64
+Gram / Algorithm 4; the FP64, FP32 and plain-BF16 paths are timed beside it with
+their DOS L1 against the FP64 path.  One step = one full ssm_dos (coefficients and
+W are set up once, outside the timed region).  The adjoint (ssm_backward) of the
+measured path is timed once after the steps.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16|fp64]
-                    [--no-fp64] [--no-bf16] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
+                    [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -27,6 +30,24 @@ sys.path.insert(0, ROOT)
 METRIC = "Cheb block-SpMM GB/s (% HBM peak); SSM DOS time at fixed L1 error"
 HBM_PEAK_GBPS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE / WRITE_SIZE
+    record (each scaled by what the counter reads for a plain copy of known size),
+    or None when there is no record or the kernel's source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes"]
 
 
 def log(*a):
@@ -75,10 +96,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16", "fp64"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint (ssm_backward)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -108,7 +130,9 @@ def main():
     n, nv, m = wl.a.n, wl.nv, wl.degree
     e = n * nv
 
-    def run(precision, steps, warmup, budget=0):
+    adjoint = {}
+
+    def run(precision, steps, warmup, budget=0, with_adjoint=False):
         dt = torch.float64 if precision == "fp64" else torch.float32
         csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=dev)
         ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=wl.t, precision=precision,
@@ -122,6 +146,20 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t_start) * 1e3 / max(steps, 1)
         st = ctx.stats()
+        if with_adjoint:
+            # gradient of sum_i dos_bar_i dos_i w.r.t. the nnz values, dos_bar weighting the
+            # resolved points (estimate above 1e-2 of its maximum): one warm-up, one timed
+            dos_bar = np.random.default_rng(5).uniform(0.0, 1.0, wl.nt) * (dos > 1e-2 * dos.max())
+            ctx.backward(dos_bar)
+            ctx.dos()
+            torch.cuda.synchronize()
+            t_b = time.perf_counter()
+            g = ctx.backward(dos_bar)
+            torch.cuda.synchronize()
+            adjoint.update(ms=(time.perf_counter() - t_b) * 1e3, phases_ms=ctx.backward_stats(),
+                           grad_finite=bool(torch.isfinite(g).all().item()))
+            del g
+            log(f"{precision} adjoint: {adjoint['ms']:.1f} ms  phases {adjoint['phases_ms']}")
         ctx.close()
         del ctx, csr
         torch.cuda.empty_cache()
@@ -132,7 +170,8 @@ def main():
         free, _ = torch.cuda.mem_get_info()
         return int(free - 6 * (1 << 30))
 
-    ms, dos, r1, r2, st = run(args.precision, args.steps, args.warmup, budget=0)
+    ms, dos, r1, r2, st = run(args.precision, args.steps, args.warmup, budget=0,
+                              with_adjoint=not args.no_adjoint)
     es = 8 if args.precision == "fp64" else 4
 
     # Chebyshev block-SpMM: compulsory bytes per launch = Y_k, Y_{k-1} read, Y_{k+1}
@@ -160,6 +199,10 @@ def main():
                 "achieved": gram_flops / (st["ms_gram"] * 1e-3) / 1e12, "peak": MFMA_PEAK_TFLOPS["fp64"],
                 "unit": "TFLOP/s", "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = pmc_traffic(roof["kernel"])
+    if args.precision == "bf16x3" and dom == "sweep":
+        # achieved counts the algorithmic flops once; the matrix cores run three BF16 products each
+        roof["mfma_issue_frac"] = 3.0 * roof["frac"]
 
     out = {
         "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -190,6 +233,8 @@ def main():
                 comparisons[other] = {"s_per_dos": mso / 1e3,
                                       "dos_l1_vs_fp64": float(np.abs(doso - dos64).sum() / np.abs(dos64).sum())}
     out["comparisons"] = comparisons
+    if adjoint:
+        out["adjoint"] = adjoint
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl)

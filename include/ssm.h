@@ -82,6 +82,11 @@ typedef struct ssm_params {
   int32_t nt;              /* number of sweep points N_t >= 1 */
   int32_t precision;       /* an ssm_precision */
   uint64_t seed;           /* key of the Philox generator for W when ssm_create gets no W */
+  int32_t ckpt_every;      /* s: 0, or s >= 4.  s > 0 plans for ssm_backward: one recurrence
+                              pass (every Z_i resident), and when the ring holds fewer than M+1
+                              blocks, ssm_dos also keeps the pairs (Y_0, Y_1) and (Y_{js-1},
+                              Y_{js}) (Y_k = T_k(A~)W, 1 <= j <= M/s) and the ring keeps >= s
+                              blocks, so that the backward recomputes the rest segment by segment */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)
@@ -161,23 +166,33 @@ ssm_status ssm_destroy(ssm_ctx* ctx);
  *   Lambda_k = Ybar_k + 2 A~ Lambda_{k+1} - Lambda_{k+2} (k = M..1, Lambda_{M+1} =
  *   Lambda_{M+2} = 0);  grad[e] = alpha (Lambda_1[r_e].W[c_e] + 2 sum_{k>=2}
  *   Lambda_k[r_e].Y_{k-1}[c_e]),  alpha = 2/(hi - lo),  A symmetric.
+ * Conditioning: at sweep points outside the spectrum Z_i is rounding noise, and
+ * its contribution to the gradient is that noise amplified by the inverse square
+ * roots of Algorithm 4 (O(1) relative in the FP32 modes).  Give such points zero
+ * dos_bar (the tests and the benchmark weight points whose estimate exceeds 1e-2
+ * of its maximum).
  * Arithmetic: Algorithm 4's backward and Kbar in FP64; Zbar, Ybar and Lambda in
- * the context's block type; Ybar by the context's sweep kernel, except that
- * SSM_FP32_BF16X3 forms it with FP32 MFMA (the sum over sweep points cancels
- * strongly at high k, where the split products' 2^-16 relative error is
- * amplified); the gradient accumulates in FP64.
- * Needs the single-pass plan (every T_k(A~)W and every Z_i resident:
- * SSM_ERR_UNSUPPORTED otherwise) and a previous ssm_dos (SSM_ERR_STATE); it
- * overwrites the context's Z blocks, so the next backward needs a new ssm_dos.
+ * the context's block type, Ybar by the context's sweep kernel; the gradient's
+ * dot products and sums in FP64.
+ * Needs a single-pass plan (every Z_i resident) that holds every T_k(A~)W or
+ * was made with ckpt_every > 0 (SSM_ERR_UNSUPPORTED otherwise), and a previous
+ * ssm_dos (SSM_ERR_STATE).  With checkpoints, T_k(A~)W of each segment of s
+ * degrees is recomputed from its checkpoint pair into the context's ring
+ * (M (s-2)/s extra block products).  It overwrites the context's Z blocks (and
+ * ring), so the next backward needs a new ssm_dos.
  * grad_dev: nnz doubles (device), overwritten.  workspace: device memory of
  * at least ssm_backward_workspace_size bytes, 256-byte aligned.  Synchronises. */
 ssm_status ssm_backward_workspace_size(const ssm_ctx* ctx, size_t* bytes);
 ssm_status ssm_backward(ssm_ctx* ctx, const double* dos_bar_host, double* grad_dev, void* workspace,
                         size_t ws_bytes);
 
-/* Device times (milliseconds) of the last ssm_backward. */
+/* Device times (milliseconds) of the last ssm_backward: Algorithm 4 backward,
+ * Zbar, transposed sweeps, recomputation of T_k(A~)W from checkpoints, reverse
+ * recurrence with the SDDMM. */
 typedef struct ssm_backward_stats {
-  double ms_total, ms_geneig, ms_zbar, ms_ybar, ms_reverse;
+  double ms_total, ms_geneig, ms_zbar, ms_ybar, ms_recompute, ms_reverse;
+  int32_t segments;        /* k-segments of the reverse sweep */
+  int32_t recomputed;      /* blocks T_k(A~)W recomputed from checkpoints */
 } ssm_backward_stats;
 ssm_status ssm_get_backward_stats(const ssm_ctx* ctx, ssm_backward_stats* out);
 

@@ -31,7 +31,7 @@ class ssm_csr(C.Structure):
 class ssm_params(C.Structure):
     _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
                 ("range_slack", C.c_double), ("nv", C.c_int32), ("degree", C.c_int32), ("nt", C.c_int32),
-                ("precision", C.c_int32), ("seed", C.c_uint64)]
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("ckpt_every", C.c_int32)]
 
 
 class ssm_stats(C.Structure):
@@ -43,7 +43,8 @@ class ssm_stats(C.Structure):
 
 class ssm_backward_stats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_geneig", C.c_double), ("ms_zbar", C.c_double),
-                ("ms_ybar", C.c_double), ("ms_reverse", C.c_double)]
+                ("ms_ybar", C.c_double), ("ms_recompute", C.c_double), ("ms_reverse", C.c_double),
+                ("segments", C.c_int32), ("recomputed", C.c_int32)]
 
 
 class ssm_views(C.Structure):

@@ -11,6 +11,7 @@
 namespace ssm {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -86,27 +87,96 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
 }
 
 // ---------------------------------------------------------------------------
-// SDDMM on the pattern of A: abar[e] += coef * sum_j lam[r_e][j] y[c_e][j], one
-// thread per stored entry, FP64 sums.
+// One step of the reverse recurrence fused with the gradient on the pattern:
+//
+//   out = Lambda_k = a (A x) + b x + c xprev + d,   x = Lambda_{k+1}, xprev =
+//         Lambda_{k+2}, d = Ybar_k, (a, b, c) = (2 alpha, 2 beta, -1);
+//         x == NULL gives out = d (k = M), xprev == NULL drops the c term;
+//   abar[p] += coef * Lambda_k[r] . y[c_p] for the stored entries p of row r,
+//         y = Y_{k-1}, in FP64.
+//
+// A row of N_v values is held by L = N_v/4 lanes, 4 values each (16 bytes in FP32,
+// 32 in FP64); a wave holds R = 64/L whole rows, so the L partial dot products of an
+// entry are summed inside the wave with lane permutes.  Rows go to XCDs in contiguous
+// ranges, as in the forward recurrence.
 // ---------------------------------------------------------------------------
-template <typename In>
-__global__ void __launch_bounds__(256) sddmm_kernel(int64_t nnz, int nv, const int32_t* __restrict__ row_of,
-                                                    const int32_t* __restrict__ col_idx, const In* __restrict__ lam,
-                                                    const In* __restrict__ y, double coef, double* __restrict__ abar) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  const In* lr = lam + (int64_t)row_of[e] * nv;
-  const In* yc = y + (int64_t)col_idx[e] * nv;
-  double acc = 0.0;
-  for (int j = 0; j < nv; ++j) acc += (double)lr[j] * (double)yc[j];
-  abar[e] += coef * acc;
+__device__ __forceinline__ double row_sum(double s, int lane, int q, int L) {
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+    const double t = __shfl(s, (lane + off) & 63);
+    if (q < off && q + off < L) s += t;
+  }
+  return s;  // the row's total, in its lane q == 0
 }
 
-__global__ void __launch_bounds__(256) row_of_kernel(int64_t n, const int32_t* __restrict__ row_ptr,
-                                                     int32_t* __restrict__ row_of) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  for (int p = row_ptr[r]; p < row_ptr[r + 1]; ++p) row_of[p] = (int32_t)r;
+template <typename T, typename V>
+__global__ void __launch_bounds__(256) reverse_step_kernel(int64_t n, int L, int R, int64_t nblocks, int64_t per_xcd,
+                                                           const int32_t* __restrict__ row_ptr,
+                                                           const int32_t* __restrict__ col_idx,
+                                                           const T* __restrict__ val, T a, T b, T c,
+                                                           const V* __restrict__ x, const V* __restrict__ xprev,
+                                                           const V* __restrict__ d, V* __restrict__ out,
+                                                           const V* __restrict__ y, double coef,
+                                                           double* __restrict__ abar) {
+  const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lblock >= nblocks) return;  // uniform over the workgroup
+  const int lane = threadIdx.x & 63;
+  const int g = lane / L;
+  const int q = lane - g * L;
+  const int64_t r = (lblock * 4 + (threadIdx.x >> 6)) * R + g;
+  const bool active = g < R && r < n;
+  const int64_t rs = active ? r : 0;  // idle lanes read row 0 and write nothing
+  const int p0 = row_ptr[rs];
+  const int len = active ? row_ptr[rs + 1] - p0 : 0;
+  const int64_t own = rs * L + q;
+  V res;
+  if (x) {
+    V acc = (V)(T)0;
+    for (int p = 0; p < len; p += 8) {
+      int cols[8];
+      T vals[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = p + j < len;
+        cols[j] = ok ? col_idx[p0 + p + j] : (int)rs;
+        vals[j] = ok ? val[p0 + p + j] : (T)0;
+      }
+      V gv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) gv[j] = x[(int64_t)cols[j] * L + q];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += vals[j] * gv[j];
+    }
+    res = a * acc + b * x[own];
+    if (xprev) res += c * xprev[own];
+    res += d[own];
+  } else {
+    res = d[own];
+  }
+  if (active) out[own] = res;
+  // every lane of the wave runs the permutes: the loop bound is the wave's longest row
+  for (int j = 0; __any(j < len); j += 4) {
+    int cols[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cols[u] = (j + u < len) ? col_idx[p0 + j + u] : (int)rs;
+    V yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yv[u] = y[(int64_t)cols[u] * L + q];
+    double sum[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double t = (double)res.x * (double)yv[u].x;
+      t += (double)res.y * (double)yv[u].y;
+      t += (double)res.z * (double)yv[u].z;
+      t += (double)res.w * (double)yv[u].w;
+      sum[u] = row_sum(t, lane, q, L);
+    }
+    if (q == 0 && active) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j + u < len) abar[p0 + j + u] += coef * sum[u];
+    }
+  }
 }
 
 // ct[i*ldct + k] = c[k*ldc + i] (FP64 and FP32 copies), zero padded to ldct
@@ -144,7 +214,35 @@ hipError_t launch_zbar_t(int is_f32, int64_t n, int nv, int ntb, const void* w, 
   return hipGetLastError();
 }
 
+// Split tables of the transposed sweep: rows k, columns the sweep points i,
+// chi[k*ldk + i] = bf16(c[k][i]), clo = bf16(c[k][i] - chi), each rounded once from
+// the FP64 value (ties to even); zero padding up to ldk.
+__global__ void __launch_bounds__(256) split_rows_kernel(const double* __restrict__ c, int64_t ldc, int nt, int m1,
+                                                         __bf16* __restrict__ chi, __bf16* __restrict__ clo,
+                                                         int64_t ldk) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)m1 * ldk) return;
+  const int k = (int)(gid / ldk);
+  const int i = (int)(gid - (int64_t)k * ldk);
+  __bf16 hi = (__bf16)0.f, lo = (__bf16)0.f;
+  if (i < nt) {
+    const double v = c[(int64_t)k * ldc + i];
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (double)hi);
+  }
+  chi[gid] = hi;
+  clo[gid] = lo;
+}
+
 }  // namespace
+
+hipError_t launch_split_rows(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo, int64_t ldk,
+                             hipStream_t stream) {
+  const int64_t total = (int64_t)m1 * ldk;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, c, ldc, nt, m1,
+                     chi, clo, ldk);
+  return hipGetLastError();
+}
 
 hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kw_bar,
                        const double* kz_bar, hipStream_t stream) {
@@ -159,20 +257,20 @@ hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, vo
   }
 }
 
-hipError_t launch_sddmm(int is_f32, int64_t nnz, int nv, const int32_t* row_of, const int32_t* col_idx,
-                        const void* lam, const void* y, double coef, double* abar, hipStream_t stream) {
-  const unsigned blocks = (unsigned)((nnz + 255) / 256);
-  if (is_f32)
-    hipLaunchKernelGGL(sddmm_kernel<float>, dim3(blocks), dim3(256), 0, stream, nnz, nv, row_of, col_idx,
-                       (const float*)lam, (const float*)y, coef, abar);
-  else
-    hipLaunchKernelGGL(sddmm_kernel<double>, dim3(blocks), dim3(256), 0, stream, nnz, nv, row_of, col_idx,
-                       (const double*)lam, (const double*)y, coef, abar);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_of(int64_t n, const int32_t* row_ptr, int32_t* row_of, hipStream_t stream) {
-  hipLaunchKernelGGL(row_of_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, row_ptr, row_of);
+template <typename T, typename V>
+hipError_t launch_reverse_t(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx, const T* val, T a,
+                            T b, T c, const void* x, const void* xprev, const void* d, void* out, const void* y,
+                            double coef, double* abar, hipStream_t stream) {
+  const int L = nv / 4;
+  if (L < 1 || L > 32 || nv % 4) return hipErrorInvalidValue;
+  const int R = 64 / L;
+  const int64_t rows_per_block = 4 * (int64_t)R;
+  const int64_t nblocks = (n + rows_per_block - 1) / rows_per_block;
+  const int64_t per_xcd = (nblocks + 7) / 8;
+  if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((reverse_step_kernel<T, V>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, L, R,
+                     nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
+                     (V*)out, (const V*)y, coef, abar);
   return hipGetLastError();
 }
 
@@ -184,5 +282,20 @@ hipError_t launch_transpose_coefficients(const double* c, int64_t ldc, int nt, i
   return hipGetLastError();
 }
 
+hipError_t launch_reverse_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                   const double* val, double a, double b, double c, const double* x,
+                                   const double* xprev, const double* d, double* out, const double* y, double coef,
+                                   double* abar, hipStream_t stream) {
+  return launch_reverse_t<double, f64x4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, y, coef, abar,
+                                         stream);
+}
+
+hipError_t launch_reverse_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                   const float* val, float a, float b, float c, const float* x, const float* xprev,
+                                   const float* d, float* out, const float* y, double coef, double* abar,
+                                   hipStream_t stream) {
+  return launch_reverse_t<float, f32x4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, y, coef, abar,
+                                        stream);
+}
 
 }  // namespace ssm

@@ -75,6 +75,7 @@ ssm_status check_params(const ssm_params* p) {
   if (p->nt < 1) return fail(SSM_ERR_ARG, "nt must be >= 1");
   if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16X3)
     return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
+  if (p->ckpt_every != 0 && p->ckpt_every < 4) return fail(SSM_ERR_ARG, "ckpt_every must be 0 or >= 4");
   return SSM_OK;
 }
 
@@ -83,10 +84,15 @@ double eff_rho(const ssm_params* p) { return p->range_slack >= 0 ? p->range_slac
 
 struct Plan {
   int passes = 1, chunk = 1, batch = 1, nseg = 1;
+  int ckpt = 0;  // checkpoint interval s when the ring holds fewer than M+1 blocks, else 0
   int64_t ldc = 4, ldk = 8;
   size_t off_t = 0, off_c64 = 0, off_c32 = 0, off_chi = 0, off_clo = 0, off_w = 0, off_y = 0, off_z = 0, off_kw = 0, off_kz = 0,
-         off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, total = 0;
+         off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, off_ckpt = 0, total = 0;
 };
+
+// Checkpoint pairs: (Y_0, Y_1), then (Y_{js-1}, Y_{js}) for 1 <= j <= M/s.
+int ckpt_pairs(int degree, int s) { return degree / s + 1; }
+int ckpt_first(int j, int s) { return j == 0 ? 0 : j * s - 1; }
 
 // Row segments of the Gram: enough (point, segment) workgroups to cover the 256 CUs a few
 // times, each wave keeping at least 64 rows.
@@ -122,6 +128,8 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * pl.batch * 2 * nn * 8);
   pl.off_z = take((size_t)pl.batch * e * es);
   pl.off_y = take((size_t)pl.chunk * e * es);
+  pl.ckpt = (p->ckpt_every > 0 && pl.chunk < p->degree + 1) ? p->ckpt_every : 0;
+  pl.off_ckpt = take(pl.ckpt ? (size_t)2 * ckpt_pairs(p->degree, pl.ckpt) * e * es : 0);
   pl.total = o;
 }
 
@@ -135,6 +143,7 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
   double best_cost = -1.0;
   const int m1 = p->degree + 1;
   for (int passes = 1; passes <= p->nt; ++passes) {
+    if (p->ckpt_every > 0 && passes > 1) break;  // the adjoint needs every Z_i resident: one pass only
     int batch = (p->nt + passes - 1) / passes;
     if (passes > 1) batch = (batch + 3) / 4 * 4;  // batch starts stay 16-byte aligned in the coefficient table
     if ((p->nt + batch - 1) / batch != passes) continue;  // same batch as a smaller pass count
@@ -158,6 +167,7 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
       }
       if (chunk < m1) chunk -= chunk % kMinChunk;  // chunk starts stay 16-byte aligned in the split tables
       if (chunk < std::min(m1, kMinChunk)) continue;
+      if (p->ckpt_every > 0 && chunk < std::min(m1, p->ckpt_every)) continue;  // the ring holds a segment
     }
     pl.chunk = chunk;
     layout(pl, a, p, own_w);
@@ -192,6 +202,7 @@ struct ssm_ctx {
   void* w = nullptr;
   void* y = nullptr;
   void* z = nullptr;
+  char* ckpt = nullptr;  // checkpoint pairs (plan.ckpt > 0)
   double* kw = nullptr;
   double* kz = nullptr;
   double* gpart = nullptr;
@@ -269,6 +280,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->w = own_w ? (void*)(c->ws + pl.off_w) : const_cast<void*>(w_dev);
   c->y = c->ws + pl.off_y;
   c->z = c->ws + pl.off_z;
+  c->ckpt = pl.ckpt ? c->ws + pl.off_ckpt : nullptr;
   c->kw = (double*)(c->ws + pl.off_kw);
   c->kz = (double*)(c->ws + pl.off_kz);
   c->gpart = (double*)(c->ws + pl.off_gpart);
@@ -382,6 +394,15 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
           ++spmm_launches;
         }
         if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
+        if (pl.ckpt && pass == 0) {  // keep the checkpoint pairs for the adjoint
+          const int j = (k + 1) / pl.ckpt;
+          const int first = ckpt_first(j, pl.ckpt);
+          if ((k == first || k == first + 1) && j < ckpt_pairs(m, pl.ckpt)) {
+            err = hipMemcpyAsync(c->ckpt + (size_t)(2 * j + (k - first)) * e * es, out, e * es,
+                                 hipMemcpyDeviceToDevice, st);
+            if (err != hipSuccess) return hip_fail(err, "checkpoint copy");
+          }
+        }
       }
       rs.en = mark();
       SSM_HIP(hipEventRecord(c->events[rs.en], st), "hipEventRecord");
@@ -473,11 +494,11 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kBackwardSegment = 64;  // Ybar blocks formed per transposed-sweep launch
+constexpr int kBackwardSegment = 256;  // Ybar blocks formed per transposed-sweep launch (no checkpoints)
 
 struct BackwardLayout {
-  size_t phibar, kwb, kzb, gescr, row_of, ct64, ct32, lam, ybar, total;
-  int64_t ldct;
+  size_t phibar, kwb, kzb, gescr, ct64, ct32, chit, clot, lam, ybar, total;
+  int64_t ldct, ldkt;
   int seg;
 };
 
@@ -489,7 +510,8 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   const int m1 = p.degree + 1;
   BackwardLayout L{};
   L.ldct = (m1 + 3) / 4 * 4;
-  L.seg = std::min(kBackwardSegment, m1);
+  L.ldkt = (p.nt + 7) / 8 * 8;
+  L.seg = c->pl.ckpt ? c->pl.ckpt : std::min(kBackwardSegment, m1);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -500,11 +522,12 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   L.kwb = take(p.nt * nn * 8);
   L.kzb = take(p.nt * nn * 8);
   L.gescr = take(3 * p.nt * nn * 8);
-  L.row_of = take((size_t)c->a.nnz * 4);
   L.ct64 = take(p.precision == SSM_FP64 ? (size_t)p.nt * L.ldct * 8 : 0);
-  L.ct32 = take(p.precision != SSM_FP64 ? (size_t)p.nt * L.ldct * 4 : 0);
+  L.ct32 = take(p.precision == SSM_FP32 || p.precision == SSM_FP32_BF16SWEEP ? (size_t)p.nt * L.ldct * 4 : 0);
+  L.chit = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);
+  L.clot = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);
   L.lam = take(3 * e * es);
-  L.ybar = take((size_t)L.seg * e * es);
+  L.ybar = take((size_t)(L.seg + 3) * e * es);  // + 3: a segment's rows start at a multiple of 4
   L.total = o;
   return L;
 }
@@ -528,8 +551,9 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
   const int m = p.degree, m1 = m + 1;
-  if (pl.passes != 1 || pl.chunk != m1)
-    return fail(SSM_ERR_UNSUPPORTED, "the adjoint needs the single-pass plan (all T_k(A~)W and Z resident)");
+  if (pl.passes != 1 || (pl.chunk != m1 && !pl.ckpt))
+    return fail(SSM_ERR_UNSUPPORTED,
+                "the adjoint needs a single-pass plan holding every T_k(A~)W, or one made with ckpt_every > 0");
   if (!c->have_dos || !c->z_valid) return fail(SSM_ERR_STATE, "ssm_backward needs a preceding ssm_dos");
   for (int i = 0; i < p.nt; ++i)
     if (!std::isfinite(dos_bar_host[i])) return fail(SSM_ERR_ARG, "dos_bar[%d] is not finite", i);
@@ -550,20 +574,28 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   double* kwb = (double*)(ws + L.kwb);
   double* kzb = (double*)(ws + L.kzb);
   double* gescr = (double*)(ws + L.gescr);
-  int32_t* row_of = (int32_t*)(ws + L.row_of);
   char* lam = ws + L.lam;
   char* ybar = ws + L.ybar;
   auto lam_slot = [&](int k) { return lam + (size_t)(k % 3) * e * es; };
-  auto y_slot = [&](int k) -> const char* { return (const char*)c->y + (size_t)k * e * es; };
+  auto cheb = [&](const void* x, const void* xp, const void* d, void* out) {
+    if (f64)
+      return ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
+                                       2 * beta, xp ? -1.0 : 0.0, (const double*)x, (const double*)xp,
+                                       (const double*)d, (double*)out, st);
+    return ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)(2 * alpha),
+                                     (float)(2 * beta), xp ? -1.0f : 0.0f, (const float*)x, (const float*)xp,
+                                     (const float*)d, (float*)out, st);
+  };
 
-  hipEvent_t ev[6];
-  for (auto& x : ev) SSM_HIP(hipEventCreate(&x), "hipEventCreate");
+  hipEvent_t ev[7] = {};
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 7; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } guard{ev};
+  for (auto& x : ev) SSM_HIP(hipEventCreate(&x), "hipEventCreate");
   SSM_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
   SSM_HIP(hipMemcpyAsync(phibar, dos_bar_host, sizeof(double) * p.nt, hipMemcpyHostToDevice, st), "copy dos_bar");
   hipError_t err = ssm::launch_geneig_backward(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, phibar, kwb, kzb,
@@ -574,71 +606,105 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   if (err != hipSuccess) return hip_fail(err, "Zbar kernel");
   c->z_valid = false;
   SSM_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
-  // transposed coefficient table for Ybar = C Zbar
-  err = ssm::launch_transpose_coefficients(c->c64, pl.ldc, p.nt, m1, f64 ? (double*)(ws + L.ct64) : nullptr,
+  // transposed coefficient tables for Ybar = C Zbar
+  if (p.precision == SSM_FP32_BF16X3)
+    err = ssm::launch_split_rows(c->c64, pl.ldc, p.nt, m1, (__bf16*)(ws + L.chit), (__bf16*)(ws + L.clot), L.ldkt, st);
+  else
+    err = ssm::launch_transpose_coefficients(c->c64, pl.ldc, p.nt, m1, f64 ? (double*)(ws + L.ct64) : nullptr,
                                              f64 ? nullptr : (float*)(ws + L.ct32), L.ldct, st);
-  if (err == hipSuccess) err = ssm::launch_row_of(n, c->a.row_ptr, row_of, st);
   if (err != hipSuccess) return hip_fail(err, "adjoint set-up kernels");
   SSM_HIP(hipMemsetAsync(grad_dev, 0, sizeof(double) * c->a.nnz, st), "clear gradient");
 
-  float ms_ybar = 0.f, ms_rev = 0.f;
-  const int nseg = (m1 + L.seg - 1) / L.seg;
-  for (int sidx = nseg - 1; sidx >= 0; --sidx) {
-    const int k_lo = sidx * L.seg;
+  // Segments [k_lo, k_hi] = [j seg, min((j+1) seg - 1, M)], last first.  Each: the seeds
+  // Ybar_{a_lo..k_hi} (a_lo = k_lo rounded down to a multiple of 4), with checkpoints the
+  // blocks Y_{b0+2..k_hi-1}, then Lambda_k and the SDDMM with Y_{k-1} for k = k_hi..max(k_lo, 1).
+  float ms_ybar = 0.f, ms_rc = 0.f, ms_rev = 0.f;
+  int recomputed = 0;
+  const int nseg = m / L.seg + 1;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int k_lo = j * L.seg;
     const int k_hi = std::min(m, k_lo + L.seg - 1);
-    const int len = k_hi - k_lo + 1;
+    const int a_lo = k_lo & ~3;
+    const int len = k_hi - a_lo + 1;
     SSM_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
     if (p.precision == SSM_FP64)
-      err = ssm::launch_sweep_f64(e, p.nt, len, (const double*)(ws + L.ct64) + k_lo, L.ldct, L.ldct - k_lo,
+      err = ssm::launch_sweep_f64(e, p.nt, len, (const double*)(ws + L.ct64) + a_lo, L.ldct, L.ldct - a_lo,
                                   (const double*)c->z, (double*)ybar, 0, st);
-    else if (p.precision == SSM_FP32_BF16SWEEP)
-      err = ssm::launch_sweep_bf16(e, p.nt, len, (const float*)(ws + L.ct32) + k_lo, L.ldct, L.ldct - k_lo,
-                                   (const float*)c->z, (float*)ybar, 0, st);
-    else  // FP32, and the split-BF16 mode: its transposed sweep runs in FP32 (see the header)
-      err = ssm::launch_sweep_f32(e, p.nt, len, (const float*)(ws + L.ct32) + k_lo, L.ldct, L.ldct - k_lo,
+    else if (p.precision == SSM_FP32)
+      err = ssm::launch_sweep_f32(e, p.nt, len, (const float*)(ws + L.ct32) + a_lo, L.ldct, L.ldct - a_lo,
                                   (const float*)c->z, (float*)ybar, 0, st);
+    else if (p.precision == SSM_FP32_BF16SWEEP)
+      err = ssm::launch_sweep_bf16(e, p.nt, len, (const float*)(ws + L.ct32) + a_lo, L.ldct, L.ldct - a_lo,
+                                   (const float*)c->z, (float*)ybar, 0, st);
+    else
+      err = ssm::launch_sweep_bf16x3(e, p.nt, len, (const __bf16*)(ws + L.chit) + (int64_t)a_lo * L.ldkt,
+                                     (const __bf16*)(ws + L.clot) + (int64_t)a_lo * L.ldkt, L.ldkt, m1 - a_lo,
+                                     (const float*)c->z, (float*)ybar, 0, st);
     if (err != hipSuccess) return hip_fail(err, "transposed sweep");
     SSM_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
-    for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
-      const char* yb = ybar + (size_t)(k - k_lo) * e * es;
-      char* out = lam_slot(k);
-      if (k == m) {
-        err = hipMemcpyAsync(out, yb, e * es, hipMemcpyDeviceToDevice, st);
-      } else {
-        const void* x = lam_slot(k + 1);
-        const void* xp = (k + 2 <= m) ? (const void*)lam_slot(k + 2) : nullptr;
-        if (f64)
-          err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
-                                          2 * beta, xp ? -1.0 : 0.0, (const double*)x, (const double*)xp,
-                                          (const double*)yb, (double*)out, st);
-        else
-          err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
-                                          (float)(2 * alpha), (float)(2 * beta), xp ? -1.0f : 0.0f, (const float*)x,
-                                          (const float*)xp, (const float*)yb, (float*)out, st);
+    if (pl.ckpt) {
+      const int seg_first = ckpt_first(j, pl.ckpt);
+      // the pair of this segment sits at checkpoint slots 2j, 2j+1; Y_b (b >= seg_first + 2)
+      // goes to ring slot b - seg_first - 2
+      char* pair = c->ckpt + (size_t)(2 * j) * e * es;
+      auto yb = [&](int b) -> const char* {
+        if (b == seg_first) return pair;
+        if (b == seg_first + 1) return pair + (size_t)e * es;
+        return (const char*)c->y + (size_t)(b - seg_first - 2) * e * es;
+      };
+      for (int b = seg_first + 2; b <= k_hi - 1; ++b) {
+        err = cheb(yb(b - 1), yb(b - 2), nullptr, (void*)yb(b));
+        if (err != hipSuccess) return hip_fail(err, "recomputation of T_k(A~)W");
+        ++recomputed;
       }
-      if (err != hipSuccess) return hip_fail(err, "reverse recurrence");
-      err = ssm::launch_sddmm(!f64, c->a.nnz, nv, row_of, c->a.col_idx, out, y_slot(k - 1),
-                              (k == 1 ? 1.0 : 2.0) * alpha, grad_dev, st);
-      if (err != hipSuccess) return hip_fail(err, "gradient SDDMM");
     }
     SSM_HIP(hipEventRecord(ev[5], st), "hipEventRecord");
-    SSM_HIP(hipEventSynchronize(ev[5]), "hipEventSynchronize");
-    float a1 = 0.f, a2 = 0.f;
+    for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
+      const char* ybk = ybar + (size_t)(k - a_lo) * e * es;
+      const void* x = k < m ? (const void*)lam_slot(k + 1) : nullptr;
+      const void* xp = k + 2 <= m ? (const void*)lam_slot(k + 2) : nullptr;
+      const char* yk1 = (const char*)c->y + (size_t)(k - 1) * e * es;
+      if (pl.ckpt) {
+        const int b = k - 1, first = ckpt_first(j, pl.ckpt);
+        const char* pair = c->ckpt + (size_t)(2 * j) * e * es;
+        yk1 = b == first ? pair : b == first + 1 ? pair + (size_t)e * es
+                                                 : (const char*)c->y + (size_t)(b - first - 2) * e * es;
+      }
+      const double coef = (k == 1 ? 1.0 : 2.0) * alpha;
+      if (f64)
+        err = ssm::launch_reverse_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
+                                           2 * beta, -1.0, (const double*)x, (const double*)xp, (const double*)ybk,
+                                           (double*)lam_slot(k), (const double*)yk1, coef, grad_dev, st);
+      else
+        err = ssm::launch_reverse_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
+                                           (float)(2 * alpha), (float)(2 * beta), -1.0f, (const float*)x,
+                                           (const float*)xp, (const float*)ybk, (float*)lam_slot(k),
+                                           (const float*)yk1, coef, grad_dev, st);
+      if (err != hipSuccess) return hip_fail(err, "reverse recurrence step");
+    }
+    SSM_HIP(hipEventRecord(ev[6], st), "hipEventRecord");
+    SSM_HIP(hipEventSynchronize(ev[6]), "hipEventSynchronize");
+    float a1 = 0.f, a2 = 0.f, a3 = 0.f;
     SSM_HIP(hipEventElapsedTime(&a1, ev[3], ev[4]), "hipEventElapsedTime");
     SSM_HIP(hipEventElapsedTime(&a2, ev[4], ev[5]), "hipEventElapsedTime");
+    SSM_HIP(hipEventElapsedTime(&a3, ev[5], ev[6]), "hipEventElapsedTime");
     ms_ybar += a1;
-    ms_rev += a2;
+    ms_rc += a2;
+    ms_rev += a3;
   }
   SSM_HIP(hipStreamSynchronize(st), "ssm_backward sync");
   float t_all = 0.f, t_ge = 0.f, t_zb = 0.f;
   SSM_HIP(hipEventElapsedTime(&t_ge, ev[0], ev[1]), "hipEventElapsedTime");
   SSM_HIP(hipEventElapsedTime(&t_zb, ev[1], ev[2]), "hipEventElapsedTime");
-  SSM_HIP(hipEventElapsedTime(&t_all, ev[0], ev[5]), "hipEventElapsedTime");
+  SSM_HIP(hipEventElapsedTime(&t_all, ev[0], ev[6]), "hipEventElapsedTime");
   c->bstats.ms_total = t_all;
   c->bstats.ms_geneig = t_ge;
   c->bstats.ms_zbar = t_zb;
   c->bstats.ms_ybar = ms_ybar;
+  c->bstats.ms_recompute = ms_rc;
   c->bstats.ms_reverse = ms_rev;
+  c->bstats.segments = nseg;
+  c->bstats.recomputed = recomputed;
   return SSM_OK;
 }
 

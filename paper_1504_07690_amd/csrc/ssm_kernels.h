@@ -26,9 +26,20 @@ hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const
 // Adjoint (adjoint.hip).
 hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kw_bar,
                        const double* kz_bar, hipStream_t stream);
-hipError_t launch_sddmm(int is_f32, int64_t nnz, int nv, const int32_t* row_of, const int32_t* col_idx,
-                        const void* lam, const void* y, double coef, double* abar, hipStream_t stream);
-hipError_t launch_row_of(int64_t n, const int32_t* row_ptr, int32_t* row_of, hipStream_t stream);
+// Reverse recurrence step fused with the gradient on the pattern of A:
+// out = a (A x) + b x + c xprev + d (x NULL: out = d), then
+// abar[p] += coef * out[r] . y[col[p]] for each stored entry p of each row r.
+hipError_t launch_reverse_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                   const double* val, double a, double b, double c, const double* x,
+                                   const double* xprev, const double* d, double* out, const double* y, double coef,
+                                   double* abar, hipStream_t stream);
+hipError_t launch_reverse_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
+                                   const float* val, float a, float b, float c, const float* x, const float* xprev,
+                                   const float* d, float* out, const float* y, double coef, double* abar,
+                                   hipStream_t stream);
+// chi[k*ldk + i] / clo: the BF16 split of c[k*ldc + i] (rows k < m1, points i < nt)
+hipError_t launch_split_rows(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo, int64_t ldk,
+                             hipStream_t stream);
 hipError_t launch_transpose_coefficients(const double* c, int64_t ldc, int nt, int m1, double* ct64, float* ct32,
                                          int64_t ldct, hipStream_t stream);
 // Sum of squares of `count` elements, two deterministic stages (reduce.hip).

@@ -94,6 +94,42 @@ def test_workspace_budget_forces_more_passes_or_chunks(A):
         A.SSM_ERR_WORKSPACE
 
 
+@pytest.mark.parametrize("s", [-1, 1, 2, 3])
+def test_checkpoint_interval_validated(A, s):
+    out = C.c_size_t(0)
+    st = A.lib.ssm_workspace_size(C.byref(_dummy_csr(A)), C.byref(_params(A, ckpt_every=s)), 0, C.byref(out))
+    assert st == A.SSM_ERR_ARG
+
+
+def test_checkpoint_plan_keeps_one_pass(A):
+    """ckpt_every > 0 keeps every Z_i resident (one recurrence pass) and, when the
+    blocks T_k W do not all fit, stores 2 (M/s + 1) checkpoint blocks beside a ring of
+    at least s blocks; without checkpoints the same budget gives a multi-pass plan."""
+    n, nv, m, nt, s = 100000, 8, 200, 64, 20
+    csr = _dummy_csr(A, n)
+    e = n * nv * 4
+    full = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(_params(A, nv=nv, degree=m, nt=nt)), 0,
+                                    C.byref(full)) == 0
+    fixed = full.value - (m + 1 + nt) * e  # everything but the ring and Z
+    pairs = m // s + 1
+    budget = fixed + (nt + 2 * pairs + 48) * e + (1 << 20)
+    got = C.c_size_t(0)
+    p = _params(A, nv=nv, degree=m, nt=nt, ckpt_every=s)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), budget, C.byref(got)) == 0
+    assert got.value <= budget
+    ring = (got.value - fixed - (nt + 2 * pairs) * e) / e
+    assert s <= ring <= 48 + 1
+    # a budget that holds Z but not Z + checkpoints + a ring of s blocks
+    tight = fixed + (nt + s) * e
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), tight, C.byref(got)) == A.SSM_ERR_WORKSPACE
+    p0 = _params(A, nv=nv, degree=m, nt=nt)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p0), tight, C.byref(got)) == 0
+    # with room for every block no checkpoint is kept
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(got)) == 0
+    assert got.value == full.value
+
+
 def test_create_validates_before_device_work(A):
     ctx = C.c_void_p(0)
     t = (C.c_double * 20)(*np.linspace(-0.9, 0.9, 20))

@@ -129,3 +129,73 @@ def test_fullsize_fp32_matches_golden_and_stages(setup):
     ctx.close()
     del ctx, v, y, z
     _free()
+
+
+_GRAD64 = {}
+
+
+def test_fullsize_fp64_adjoint_directional_derivative(setup):
+    """The FP64 adjoint at full size with checkpoints every 50 degrees (the ring cannot
+    hold all 1001 FP64 blocks beside Z): the gradient along symmetric directions E
+    against central differences of the device's own FP64 DOS, A +- h E (h = 1e-6 max|a|),
+    where the truncation sets of Algorithm 4 are the same at both ends.  dos_bar weights
+    the resolved points (estimate above 1e-2 of its maximum) only."""
+    from test_oracle_pins import _sym_direction
+    S, wl, g = setup
+    free, _ = torch.cuda.mem_get_info()
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=DEV)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision="fp64",
+                seed=wl.seed, budget=int(free - 20 * (1 << 30)), ckpt_every=50, device=DEV)
+    st = ctx.stats()
+    dos, _, _ = ctx.dos()
+    keep = dos > 1e-2 * dos.max()  # resolved points only (see test_gpu_adjoint.resolved)
+    dos_bar = np.random.default_rng(5).uniform(0.0, 1.0, wl.nt) * keep
+    grad = ctx.backward(dos_bar).cpu().numpy()
+    bs = ctx.backward_stats()
+    print(f"fp64 adjoint: chunk {st['chunk']}, {bs['segments']} segments, {bs['recomputed']} recomputed, "
+          f"{bs['ms_total']:.0f} ms")
+    assert np.all(np.isfinite(grad))
+    _GRAD64["grad"], _GRAD64["dos_bar"] = grad, dos_bar
+    base = csr.values.clone()
+    h = 1e-6 * np.abs(wl.a.values).max()
+    checked = 0
+    for seed in range(3):
+        e = _sym_direction(wl.a, seed)
+        ed = torch.tensor(e, dtype=torch.float64, device=DEV)
+        csr.values.copy_(base + h * ed)
+        lp, rp1, rp2 = ctx.dos()
+        csr.values.copy_(base - h * ed)
+        lm, rm1, rm2 = ctx.dos()
+        csr.values.copy_(base)
+        if not (np.array_equal(rp1[keep], rm1[keep]) and np.array_equal(rp2[keep], rm2[keep])):
+            print(f"direction {seed}: a truncation set of a weighted point changes inside [-h, h], skipped")
+            continue
+        fd = dos_bar @ (lp - lm) / (2 * h)
+        ad = grad @ e
+        print(f"direction {seed}: adjoint {ad:.12e}  central difference {fd:.12e}")
+        assert abs(ad - fd) <= 1e-5 * abs(fd)
+        checked += 1
+    ctx.close()
+    del ctx, csr
+    _free()
+    assert checked >= 1
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("bf16x3", 1e-3)])
+def test_fullsize_mixed_adjoint_against_fp64(setup, precision, tol):
+    """The benchmark's mixed-precision adjoints (every block resident) against the FP64
+    adjoint of the same W and dos_bar."""
+    S, wl, g = setup
+    if "grad" not in _GRAD64:
+        pytest.skip("needs the FP64 full-size adjoint of the previous test")
+    ctx = _ctx(S, wl, precision)
+    ctx.dos()
+    grad = ctx.backward(_GRAD64["dos_bar"]).cpu().numpy()
+    bs = ctx.backward_stats()
+    ctx.close()
+    del ctx
+    _free()
+    ref = _GRAD64["grad"]
+    err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    print(f"{precision} adjoint at full size: {bs['ms_total']:.0f} ms, relative error vs FP64 {err:.3e}")
+    assert err <= tol
