@@ -349,13 +349,20 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
 // is written as hi + lo with hi = bf16(x), lo = bf16(x - hi) (both round to nearest
 // even), and C^T Y ~= Chi^T Yhi + Chi^T Ylo + Clo^T Yhi on v_mfma_f32_32x32x16_bf16
 // with FP32 accumulation: about 16 mantissa bits per product at BF16 matrix rate.
-// The coefficients arrive pre-split in k-contiguous tables chi/clo [i][ldk]; the Y
-// tile is split in registers while being transposed: a thread reads 8 consecutive
-// k of 2 elements (8 float2) and writes, per element, 8 k of hi and of lo as two
-// 16-byte LDS stores.  Tile 256 points x 256 elements x 16 k; four waves in 2 x 2,
-// each 128 x 128 = 4 x 4 MFMA blocks (256 accumulators).
+//
+// Tile 256 points x 256 elements x 32 k, eight waves (2 x 4), each 128 x 64 = 4 x 2
+// MFMA blocks (128 accumulators, so two waves share a SIMD).  The coefficients
+// arrive pre-split in k-contiguous tables chi/clo [i][ldk]; the Y tile is split in
+// registers while being transposed (a thread reads 8 consecutive k of 2 elements and
+// writes, per element, 8 k of hi and of lo as 16-byte LDS stores).  LDS holds two
+// stages of the four 256 x 32 BF16 tiles (128 KB); rows are 64 bytes and the 16-byte
+// k-chunk c of row r sits at chunk c ^ ((r >> 2) & 3), so that the 16 rows read by
+// a quarter-wave fall in distinct banks.  One barrier per k-step: the next tile's
+// global loads are issued right after it, and stored to the other stage after the
+// MFMAs of the current one.
 // ---------------------------------------------------------------------------
-constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 16, X3_LDK = X3_BK + 8;
+constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 32;
+constexpr int X3_TILE = 256 * X3_BK;  // bf16 per LDS tile
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -365,17 +372,18 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(256) sweep_bf16x3_kernel(int64_t e, int kc, int ntb,
+// element offset of 16-byte chunk c (0..3) of row r in a 256 x 32 tile
+__device__ __forceinline__ int x3_off(int r, int c) { return r * X3_BK + ((c ^ ((r >> 2) & 3)) << 3); }
+
+__global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, int ntb,
                                                            const __bf16* __restrict__ chi,
                                                            const __bf16* __restrict__ clo, int64_t ldk,
                                                            int64_t arows, const float* __restrict__ y,
                                                            float* __restrict__ z, int accumulate, int mt,
                                                            int nt_tiles) {
   extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
-  __bf16(*Ahi)[X3_LDK] = (__bf16(*)[X3_LDK])x3_lds;
-  __bf16(*Alo)[X3_LDK] = Ahi + X3_BM;
-  __bf16(*Bhi)[X3_LDK] = Alo + X3_BM;
-  __bf16(*Blo)[X3_LDK] = Bhi + X3_BN;
+  // stage s: Ahi, Alo, Bhi, Blo at (4 s + 0..3) * X3_TILE
+  __bf16* lds = (__bf16*)x3_lds;
   int m_tile, n_tile;
   tile_coords(mt, nt_tiles, m_tile, n_tile);
   if (n_tile < 0) return;
@@ -384,21 +392,19 @@ __global__ void __launch_bounds__(256) sweep_bf16x3_kernel(int64_t e, int kc, in
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 2, wn = wave & 3;
 
-  // A staging: 256 rows x 16 k of hi and of lo = 2 x 512 16-byte pieces; thread t
-  // moves pieces t and t+256 of each (row = piece/2, k-octet = piece%2)
+  // A staging: 256 rows x 4 chunks per table = 1024 pieces; thread t moves pieces t and
+  // t + 512 of hi and of lo (row = piece / 4, chunk = piece % 4)
   u16x8 ra_hi[2], ra_lo[2];
-  // B staging: elements (tid % 128) * 2 .. +1, k-octet tid / 128
+  // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k)
   f32x2 rb[8];
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int piece = tid + 256 * u;
-      const int row = piece >> 1;
-      const int ko = (piece & 1) * 8;
-      const int64_t i = i0 + row;
-      const int k = k0 + ko;
+      const int piece = tid + 512 * u;
+      const int64_t i = i0 + (piece >> 2);
+      const int k = k0 + (piece & 3) * 8;
       u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
       if (i < arows && k < kc) {
         vh = *(const u16x8*)(chi + i * ldk + k);
@@ -413,24 +419,29 @@ __global__ void __launch_bounds__(256) sweep_bf16x3_kernel(int64_t e, int kc, in
       ra_lo[u] = vl;
     }
     const int c2 = (tid & 127) * 2;
-    const int ko = (tid >> 7) * 8;
+    const int kq = k0 + (tid >> 7) * 8;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = k0 + ko + j;
+      const int k = kq + j;
       f32x2 v = {0.f, 0.f};
       if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
       rb[j] = v;
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](int st) {
+    __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
+    __bf16* alo = lds + (4 * st + 1) * X3_TILE;
+    __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
+    __bf16* blo = lds + (4 * st + 3) * X3_TILE;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int piece = tid + 256 * u;
-      *(u16x8*)&Ahi[piece >> 1][(piece & 1) * 8] = ra_hi[u];
-      *(u16x8*)&Alo[piece >> 1][(piece & 1) * 8] = ra_lo[u];
+      const int piece = tid + 512 * u;
+      const int o = x3_off(piece >> 2, piece & 3);
+      *(u16x8*)(ahi + o) = ra_hi[u];
+      *(u16x8*)(alo + o) = ra_lo[u];
     }
     const int c2 = (tid & 127) * 2;
-    const int ko = (tid >> 7) * 8;
+    const int ch = tid >> 7;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       bf16x8 h, l;
@@ -441,55 +452,66 @@ __global__ void __launch_bounds__(256) sweep_bf16x3_kernel(int64_t e, int kc, in
         h[j] = hh;
         l[j] = ll;
       }
-      *(bf16x8*)&Bhi[c2 + c][ko] = h;
-      *(bf16x8*)&Blo[c2 + c][ko] = l;
+      const int o = x3_off(c2 + c, ch);
+      *(bf16x8*)(bhi + o) = h;
+      *(bf16x8*)(blo + o) = l;
     }
   };
 
-  f32x16 acc[4][4];
+  f32x16 acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
   const int nk = (kc + X3_BK - 1) / X3_BK;
   load_tile(0);
+  store_tile(0);
+  if (nk > 1) load_tile(X3_BK);
+  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    store_tile();
-    __syncthreads();
-    if (kt + 1 < nk) load_tile((kt + 1) * X3_BK);
+    const int st = kt & 1;
+    const __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
+    const __bf16* alo = lds + (4 * st + 1) * X3_TILE;
+    const __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
+    const __bf16* blo = lds + (4 * st + 3) * X3_TILE;
 #pragma unroll
-    for (int kk = 0; kk < X3_BK; kk += 16) {
-      const int kb = kk + 8 * (lane >> 5);
-      bf16x8 bh[4], bl[4];
+    for (int ks = 0; ks < 2; ++ks) {
+      const int ch = 2 * ks + (lane >> 5);
+      bf16x8 bh[2], bl[2];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        bh[b] = *(const bf16x8*)&Bhi[wn * 128 + b * 32 + (lane & 31)][kb];
-        bl[b] = *(const bf16x8*)&Blo[wn * 128 + b * 32 + (lane & 31)][kb];
+      for (int b = 0; b < 2; ++b) {
+        const int o = x3_off(wn * 64 + b * 32 + (lane & 31), ch);
+        bh[b] = *(const bf16x8*)(bhi + o);
+        bl[b] = *(const bf16x8*)(blo + o);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const bf16x8 ah = *(const bf16x8*)&Ahi[wm * 128 + a * 32 + (lane & 31)][kb];
-        const bf16x8 al = *(const bf16x8*)&Alo[wm * 128 + a * 32 + (lane & 31)][kb];
-        // small products first, the three products of one block four MFMAs apart
+        const int o = x3_off(wm * 128 + a * 32 + (lane & 31), ch);
+        const bf16x8 ah = *(const bf16x8*)(ahi + o);
+        const bf16x8 al = *(const bf16x8*)(alo + o);
+        // small products first, the three products of one block two MFMAs apart
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
     }
+    // the other stage was last read before the previous barrier: fill it with tile kt+1
+    if (kt + 1 < nk) store_tile(st ^ 1);
     __syncthreads();
+    if (kt + 2 < nk) load_tile((kt + 2) * X3_BK);
   }
 
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t col = q0 + wn * 128 + b * 32 + (lane & 31);
+    for (int b = 0; b < 2; ++b) {
+      const int64_t col = q0 + wn * 64 + b * 32 + (lane & 31);
       if (col >= e) continue;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -546,7 +568,7 @@ hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t
   return launch_tiles(sweep_f64_kernel, F64_BM, F64_BN, e, kc, ntb, c, ldc, acols, y, z, accumulate, stream);
 }
 
-size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * (X3_BM + X3_BN) * X3_LDK * sizeof(__bf16); }
+size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * 4 * X3_TILE * sizeof(__bf16); }
 
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
                                int64_t arows, const float* y, float* z, int accumulate, hipStream_t stream) {
@@ -559,7 +581,7 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t nt_pad = (ntiles + 7) / 8 * 8;
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(256), lds, stream, e, kc, ntb, chi, clo, ldk,
+  hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo, ldk,
                      arows, y, z, accumulate, mt, (int)ntiles);
   return hipGetLastError();
 }
