@@ -77,7 +77,7 @@ typedef struct ssm_params {
   double sigma;            /* smearing sigma > 0 of g_sigma, Eq. (gaussian), A's units */
   double tau;              /* Algorithm 4 step 2 truncation, keep s_j >= tau max s; <= 0 selects 1e-7 */
   double range_slack;      /* rho: Algorithm 4 step 4 keeps xi in [0, (1+rho) g_max]; < 0 selects 1e-3 */
-  int32_t nv;              /* N_v random vectors: 4 <= nv <= 96 and nv % 4 == 0 in this build */
+  int32_t nv;              /* N_v random vectors: 4 <= nv <= 256 and nv % 4 == 0 in this build */
   int32_t degree;          /* Chebyshev degree M >= 1 (T_0..T_M); M <= 4095 in this build */
   int32_t nt;              /* number of sweep points N_t >= 1 */
   int32_t precision;       /* an ssm_precision */
@@ -277,7 +277,8 @@ ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const
  * keep s_j >= tau max_j s_j (nothing if max s <= 0), B = S~^-1/2 U~^T k_z[i]
  * U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi in [0, (1 + rho) g_max];
  * ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).  Cyclic Jacobi in
- * FP64.  scratch: ntb*nv*nv doubles. */
+ * FP64.  scratch: ntb*nv*nv doubles for nv <= 96, ntb*(nv*nv + 2*nv*(nv+1)) above
+ * (the two Jacobi matrices then live in it instead of LDS). */
 ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max,
                             double tau, double rho, double* dos_dev, int32_t* ranks_dev, double* scratch,
                             void* stream);

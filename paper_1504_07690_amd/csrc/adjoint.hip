@@ -86,6 +86,64 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
   }
 }
 
+// N_v above 96: the stack does not fit in LDS; the same MFMA walk reads [Kbar_W;
+// 2 Kbar_Z] through the cache (one point's stack is shared by all its row blocks),
+// and the 16 x 2 N_v slab is loaded eight k-steps at a time.
+template <int T, typename In>
+__global__ void __launch_bounds__(256) zbar_big_kernel(int64_t n, int nv, const In* __restrict__ w,
+                                                       In* __restrict__ z, const double* __restrict__ kw_bar,
+                                                       const double* __restrict__ kz_bar) {
+  constexpr int NP = 16 * T;
+  constexpr int KQ = 2 * NP / 4;
+  const int i = blockIdx.y;
+  const int64_t nn = (int64_t)nv * nv;
+  const double* kwb = kw_bar + i * nn;
+  const double* kzb = kz_bar + i * nn;
+  In* zi = z + (int64_t)i * n * nv;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r_begin = (int64_t)blockIdx.x * ZB_ROWS_PER_BLOCK;
+  const int64_t r_end = (r_begin + ZB_ROWS_PER_BLOCK < n) ? r_begin + ZB_ROWS_PER_BLOCK : n;
+  for (int64_t r0 = r_begin + 16 * wave; r0 < r_end; r0 += 64) {
+    const int64_t row = r0 + (lane & 15);
+    const bool rok = row < r_end;
+    f64x4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < KQ; s0 += 8) {
+      In av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = 4 * (s0 + u) + (lane >> 4);
+        In v = (In)0;
+        if (rok && q < 2 * nv) v = (q < nv) ? w[row * nv + q] : zi[row * nv + (q - nv)];
+        av[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = 4 * (s0 + u) + (lane >> 4);
+        const double a = (double)av[u];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int c = 16 * t + (lane & 15);
+          double bv = 0.0;
+          if (c < nv && q < 2 * nv) bv = (q < nv) ? kwb[(int64_t)q * nv + c] : 2.0 * kzb[(int64_t)(q - nv) * nv + c];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int col = 16 * t + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t orow = r0 + (lane >> 4) + 4 * r;
+        if (orow < r_end && col < nv) zi[orow * nv + col] = (In)acc[t][r];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One step of the reverse recurrence fused with the gradient on the pattern:
 //
@@ -102,7 +160,7 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double row_sum(double s, int lane, int q, int L) {
 #pragma unroll
-  for (int off = 16; off >= 1; off >>= 1) {
+  for (int off = 32; off >= 1; off >>= 1) {
     const double t = __shfl(s, (lane + off) & 63);
     if (q < off && q + off < L) s += t;
   }
@@ -193,6 +251,19 @@ __global__ void __launch_bounds__(256) transpose_coefficients_kernel(const doubl
 }
 
 template <int T>
+hipError_t launch_zbar_big(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kwb,
+                           const double* kzb, hipStream_t stream) {
+  dim3 grid((unsigned)((n + ZB_ROWS_PER_BLOCK - 1) / ZB_ROWS_PER_BLOCK), ntb);
+  if (is_f32)
+    hipLaunchKernelGGL((zbar_big_kernel<T, float>), grid, dim3(256), 0, stream, n, nv, (const float*)w, (float*)z, kwb,
+                       kzb);
+  else
+    hipLaunchKernelGGL((zbar_big_kernel<T, double>), grid, dim3(256), 0, stream, n, nv, (const double*)w, (double*)z,
+                       kwb, kzb);
+  return hipGetLastError();
+}
+
+template <int T>
 hipError_t launch_zbar_t(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kwb,
                          const double* kzb, hipStream_t stream) {
   const size_t lds = (size_t)2 * nv * 16 * T * sizeof(double);
@@ -253,6 +324,9 @@ hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, vo
     case 4: return launch_zbar_t<4>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
     case 5: return launch_zbar_t<5>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
     case 6: return launch_zbar_t<6>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
+    case 7: case 8: return launch_zbar_big<8>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
+    case 9: case 10: case 11: case 12: return launch_zbar_big<12>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
+    case 13: case 14: case 15: case 16: return launch_zbar_big<16>(is_f32, n, nv, ntb, w, z, kw_bar, kz_bar, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -262,7 +336,7 @@ hipError_t launch_reverse_t(int64_t n, int nv, const int32_t* row_ptr, const int
                             T b, T c, const void* x, const void* xprev, const void* d, void* out, const void* y,
                             double coef, double* abar, hipStream_t stream) {
   const int L = nv / 4;
-  if (L < 1 || L > 32 || nv % 4) return hipErrorInvalidValue;
+  if (L < 1 || L > 64 || nv % 4) return hipErrorInvalidValue;
   const int R = 64 / L;
   const int64_t rows_per_block = 4 * (int64_t)R;
   const int64_t nblocks = (n + rows_per_block - 1) / rows_per_block;

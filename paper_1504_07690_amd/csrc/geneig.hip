@@ -12,15 +12,18 @@
 // (Golub & Van Loan, symmetric 2x2 Schur), then the rows of every pair are rotated,
 // then the columns (and the eigenvector columns).  The pivot entries are set to
 // exactly zero.  A sweep starts only while off(A)_F > 1e-14 ||A||_F.
-// The matrix and its eigenvectors live in LDS (N_v <= 96: 2 * 96 * 97 doubles);
-// the N_v x r1 product Z^T Z U~ S~^-1/2 goes through a per-point global scratch.
+// The matrix and its eigenvectors live in LDS for N_v <= 96 (2 * 96 * 97 doubles)
+// and in the point's global scratch above that (N_v <= 256); the N_v x r1 product
+// Z^T Z U~ S~^-1/2 goes through the same per-point scratch.
 #include "ssm_kernels.h"
 
 namespace ssm {
+
 namespace {
 
 constexpr int GE_THREADS = 256;
-constexpr int GE_MAX_NV = 96;
+constexpr int GE_LDS_NV = 96;   // largest N_v whose two matrices sit in LDS
+constexpr int GE_MAX_NV = 256;
 constexpr int GE_MAX_SWEEPS = 40;
 
 struct GeShared {
@@ -36,6 +39,29 @@ struct GeShared {
   int* kidx;      // kept indices
   int* misc;      // [0] = r1
 };
+
+// Small arrays in LDS; A and V (n x (n+1) each) in LDS too, or at `big` (global).
+__device__ void ge_layout(GeShared& sh, double* lds, int n, double* big) {
+  const int ld = n + 1;
+  double* small = lds;
+  if (big) {
+    sh.A = big;
+    sh.V = big + n * ld;
+  } else {
+    sh.A = lds;
+    sh.V = lds + n * ld;
+    small = sh.V + n * ld;
+  }
+  sh.s = small;
+  sh.scale = sh.s + GE_MAX_NV;
+  sh.cs = sh.scale + GE_MAX_NV;
+  sh.sn = sh.cs + GE_MAX_NV / 2;
+  sh.red = sh.sn + GE_MAX_NV / 2;
+  sh.pp = (int*)(sh.red + GE_THREADS);
+  sh.qq = sh.pp + GE_MAX_NV / 2;
+  sh.kidx = sh.qq + GE_MAX_NV / 2;
+  sh.misc = sh.kidx + GE_MAX_NV;
+}
 
 __device__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
@@ -132,25 +158,14 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
-  GeShared sh;
-  sh.A = lds;
-  sh.V = sh.A + n * ld;
-  sh.s = sh.V + n * ld;
-  sh.scale = sh.s + GE_MAX_NV;
-  sh.cs = sh.scale + GE_MAX_NV;
-  sh.sn = sh.cs + GE_MAX_NV / 2;
-  sh.red = sh.sn + GE_MAX_NV / 2;
-  sh.pp = (int*)(sh.red + GE_THREADS);
-  sh.qq = sh.pp + GE_MAX_NV / 2;
-  sh.kidx = sh.qq + GE_MAX_NV / 2;
-  sh.misc = sh.kidx + GE_MAX_NV;
-
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t nn = (int64_t)n * n;
   const double* kw = k_w + i * nn;
   const double* kz = k_z + i * nn;
-  double* tmat = scratch + i * nn;
+  double* tmat = scratch + i * (int64_t)geneig_scratch_doubles(nv);
+  GeShared sh;
+  ge_layout(sh, lds, n, nv > GE_LDS_NV ? tmat + nn : nullptr);
 
   for (int idx = tid; idx < n * n; idx += GE_THREADS) {
     const int r = idx / n, c = idx - r * n;
@@ -266,28 +281,17 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
-  GeShared sh;
-  sh.A = lds;
-  sh.V = sh.A + n * ld;
-  sh.s = sh.V + n * ld;
-  sh.scale = sh.s + GE_MAX_NV;
-  sh.cs = sh.scale + GE_MAX_NV;
-  sh.sn = sh.cs + GE_MAX_NV / 2;
-  sh.red = sh.sn + GE_MAX_NV / 2;
-  sh.pp = (int*)(sh.red + GE_THREADS);
-  sh.qq = sh.pp + GE_MAX_NV / 2;
-  sh.kidx = sh.qq + GE_MAX_NV / 2;
-  sh.misc = sh.kidx + GE_MAX_NV;
-  double* f = sh.scale;  // F(s_j) for every j (0 when dropped)
-
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t nn = (int64_t)n * n;
   const double* kw = k_w + i * nn;
   const double* kz = k_z + i * nn;
-  double* ug = scratch + (3 * i + 0) * nn;   // U
-  double* ktg = scratch + (3 * i + 1) * nn;  // Kt = U^T K_Z U
-  double* tg = scratch + (3 * i + 2) * nn;   // products
+  double* ug = scratch + i * (int64_t)geneig_backward_scratch_doubles(nv);  // U
+  double* ktg = ug + nn;                                                    // Kt = U^T K_Z U
+  double* tg = ug + 2 * nn;                                                 // products
+  GeShared sh;
+  ge_layout(sh, lds, n, nv > GE_LDS_NV ? ug + 3 * nn : nullptr);
+  double* f = sh.scale;  // F(s_j) for every j (0 when dropped)
   double* kwb = kw_bar + i * nn;
   double* kzb = kz_bar + i * nn;
   const double pb = phibar[i];
@@ -432,7 +436,8 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
 
 size_t geneig_lds_bytes(int nv) {
   const size_t n = (size_t)nv, ld = n + 1;
-  return (2 * n * ld + 2 * GE_MAX_NV + GE_MAX_NV + GE_THREADS) * sizeof(double) +
+  const size_t mats = nv > GE_LDS_NV ? 0 : 2 * n * ld;
+  return (mats + 2 * GE_MAX_NV + GE_MAX_NV + GE_THREADS) * sizeof(double) +
          (GE_MAX_NV + GE_MAX_NV + 4) * sizeof(int);
 }
 

@@ -5,7 +5,7 @@
 // in FP64 on v_mfma_f64_16x16x4_f64.  FP32 inputs are widened to FP64 exactly, so
 // every product is exact and only the FP64 sums round.
 //
-// Work split: one workgroup per (sweep point, row segment); each of its four waves
+// Work split (N_v <= 96): one workgroup per (sweep point, row segment); each of its four waves
 // walks a contiguous quarter of the segment, four rows per MFMA step (the MFMA's
 // k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of W^T Z + Z^T W
 // in registers, so its operands come straight from memory: lane l reads column
@@ -166,6 +166,123 @@ __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, c
     }
 }
 
+// N_v above 96: the block grid is cut into tiles of 4 x 4 column blocks, (ti, tj) with
+// ti <= tj, one tile per blockIdx.z; each wave keeps the 16 Z^T Z and 16 W^T Z + Z^T W
+// blocks of its tile (on a diagonal tile the lower blocks are computed and not stored).
+constexpr int GT_B = 4;
+
+template <typename In>
+struct GramTileStep {
+  In za[GT_B], wa[GT_B], zb[GT_B], wb[GT_B];
+};
+
+template <typename In>
+__device__ __forceinline__ void gram_tile_load(GramTileStep<In>& st, __amdgpu_buffer_rsrc_t rz,
+                                               __amdgpu_buffer_rsrc_t rw, int rel_row, int nv,
+                                               const int (&off_a)[GT_B], const int (&off_b)[GT_B]) {
+  const int base = rel_row * nv * (int)sizeof(In);
+#pragma unroll
+  for (int a = 0; a < GT_B; ++a) {
+    st.za[a] = buffer_load<In>(rz, base + off_a[a]);
+    st.wa[a] = buffer_load<In>(rw, base + off_a[a]);
+    st.zb[a] = buffer_load<In>(rz, base + off_b[a]);
+    st.wb[a] = buffer_load<In>(rw, base + off_b[a]);
+  }
+}
+
+template <typename In>
+__global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int ntb, const In* __restrict__ w,
+                                                         const In* __restrict__ z, int64_t rows_per_seg, int ntile,
+                                                         double* __restrict__ part) {
+  const int i = blockIdx.x;
+  const int seg = blockIdx.y;
+  // tile index -> (ti, tj), ti <= tj, row by row
+  int ti = 0, rem = blockIdx.z;
+  while (rem >= ntile - ti) {
+    rem -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t s_begin = (int64_t)seg * rows_per_seg;
+  const int64_t s_end = (s_begin + rows_per_seg < n) ? s_begin + rows_per_seg : n;
+  int64_t q = (s_end - s_begin + GR_WAVES - 1) / GR_WAVES;
+  q = (q + 3) / 4 * 4;
+  const int64_t r_begin = s_begin + wave * q;
+  const int64_t r_end = (r_begin + q < s_end) ? r_begin + q : s_end;
+  const In* zi = z + (int64_t)i * n * nv;
+  const int rows = (int)((r_end > r_begin) ? r_end - r_begin : 0);
+  const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(zi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(w + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+  int off_a[GT_B], off_b[GT_B];
+#pragma unroll
+  for (int a = 0; a < GT_B; ++a) {
+    off_a[a] = ((lane >> 4) * nv + 16 * (GT_B * ti + a) + (lane & 15)) * (int)sizeof(In);
+    off_b[a] = ((lane >> 4) * nv + 16 * (GT_B * tj + a) + (lane & 15)) * (int)sizeof(In);
+  }
+  f64x4 acc_zz[GT_B * GT_B], acc_wz[GT_B * GT_B];
+#pragma unroll
+  for (int p = 0; p < GT_B * GT_B; ++p) {
+    acc_zz[p] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    acc_wz[p] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  }
+  GramTileStep<In> buf0, buf1;
+  gram_tile_load<In>(buf0, rz, rw, 0, nv, off_a, off_b);
+  __builtin_amdgcn_sched_barrier(0);
+  gram_tile_load<In>(buf1, rz, rw, 4, nv, off_a, off_b);
+  __builtin_amdgcn_sched_barrier(0);
+  auto step = [&](GramTileStep<In>& b, int rr) {
+    double za[GT_B], wa[GT_B], zb[GT_B], wb[GT_B];
+#pragma unroll
+    for (int a = 0; a < GT_B; ++a) {
+      za[a] = (double)b.za[a];
+      wa[a] = (double)b.wa[a];
+      zb[a] = (double)b.zb[a];
+      wb[a] = (double)b.wb[a];
+    }
+    gram_tile_load<In>(b, rz, rw, rr + 8, nv, off_a, off_b);
+#pragma unroll
+    for (int a = 0; a < GT_B; ++a)
+#pragma unroll
+      for (int bb = 0; bb < GT_B; ++bb) {
+        const int p = a * GT_B + bb;
+        acc_zz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], zb[bb], acc_zz[p], 0, 0, 0);
+        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[a], zb[bb], acc_wz[p], 0, 0, 0);
+        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], wb[bb], acc_wz[p], 0, 0, 0);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+#pragma clang loop unroll(disable)
+  for (int rr = 0; rr < rows; rr += 8) {
+    step(buf0, rr);
+    step(buf1, rr + 4);
+  }
+  const int64_t nn = (int64_t)nv * nv;
+  const int slot = seg * GR_WAVES + wave;
+  double* pz = part + ((int64_t)slot * ntb + i) * 2 * nn;
+  double* pw = pz + nn;
+#pragma unroll
+  for (int a = 0; a < GT_B; ++a)
+#pragma unroll
+    for (int bb = 0; bb < GT_B; ++bb) {
+      const int ab = GT_B * ti + a, bbl = GT_B * tj + bb;
+      if (ab > bbl) continue;  // lower blocks of a diagonal tile
+      const int p = a * GT_B + bb;
+      const int col = 16 * bbl + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ab + (lane >> 4) + 4 * r;
+        if (row < nv && col < nv) {
+          pz[(int64_t)row * nv + col] = acc_zz[p][r];
+          pw[(int64_t)row * nv + col] = acc_wz[p][r];
+        }
+      }
+    }
+}
+
 // K(i)[r][c] = sum over segments of the stored upper block entry; the lower blocks
 // mirror the upper ones; the diagonal blocks are averaged with their transpose.
 __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int nseg, const double* __restrict__ part,
@@ -231,7 +348,18 @@ hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, co
     case 4: err = launch_t<4>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
     case 5: err = launch_t<5>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
     case 6: err = launch_t<6>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    default: return hipErrorInvalidValue;
+    default: {
+      if (t > 16) return hipErrorInvalidValue;
+      const int ntile = (t + GT_B - 1) / GT_B;
+      dim3 grid(ntb, segs, ntile * (ntile + 1) / 2);
+      if (is_f32)
+        hipLaunchKernelGGL(gram_tiled_kernel<float>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
+                           (const float*)w, (const float*)z, rps, ntile, scratch);
+      else
+        hipLaunchKernelGGL(gram_tiled_kernel<double>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
+                           (const double*)w, (const double*)z, rps, ntile, scratch);
+      err = hipGetLastError();
+    }
   }
   if (err != hipSuccess) return err;
   const int64_t total = (int64_t)ntb * nv * nv;

@@ -40,7 +40,7 @@ ssm_status hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kMaxNv = 96;
+constexpr int kMaxNv = 256;
 constexpr int kMaxDegree = 4095;
 constexpr int kMinChunk = 16;
 
@@ -121,7 +121,7 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_w = take(own_w ? e * es : 0);
   pl.off_kw = take((size_t)p->nt * nn * 8);
   pl.off_kz = take((size_t)p->nt * nn * 8);
-  pl.off_escr = take((size_t)p->nt * nn * 8);
+  pl.off_escr = take((size_t)p->nt * ssm::geneig_scratch_doubles(p->nv) * 8);
   pl.off_dos = take(p->nt * 8);
   pl.off_ranks = take(2 * (size_t)p->nt * 4);
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
@@ -521,7 +521,7 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   L.phibar = take(p.nt * 8);
   L.kwb = take(p.nt * nn * 8);
   L.kzb = take(p.nt * nn * 8);
-  L.gescr = take(3 * p.nt * nn * 8);
+  L.gescr = take((size_t)p.nt * ssm::geneig_backward_scratch_doubles(p.nv) * 8);
   L.ct64 = take(p.precision == SSM_FP64 ? (size_t)p.nt * L.ldct * 8 : 0);
   L.ct32 = take(p.precision == SSM_FP32 || p.precision == SSM_FP32_BF16SWEEP ? (size_t)p.nt * L.ldct * 4 : 0);
   L.chit = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);

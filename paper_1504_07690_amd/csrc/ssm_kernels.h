@@ -72,6 +72,16 @@ hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, co
                        double* k_z, int nseg, double* scratch, hipStream_t stream);
 
 // Algorithm 4 + trace (geneig.hip).
+// Per-point FP64 scratch of launch_geneig_trace / launch_geneig_backward: the
+// products, plus the two Jacobi matrices when N_v > 96 (they no longer fit in LDS).
+__host__ __device__ inline int64_t geneig_scratch_doubles(int nv) {
+  const int64_t n = nv;
+  return n * n + (nv > 96 ? 2 * n * (n + 1) : 0);
+}
+__host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
+  const int64_t n = nv;
+  return 3 * n * n + (nv > 96 ? 2 * n * (n + 1) : 0);
+}
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max,
                                double tau, double rho, double* dos, int32_t* ranks, double* scratch,
                                hipStream_t stream);

@@ -281,7 +281,8 @@ def geneig_trace(k_w: torch.Tensor, k_z: torch.Tensor, g_max, tau, rho, dos: tor
                  ranks: torch.Tensor | None = None):
     _require_cuda(k_w, k_z, dos, ranks)
     ntb, nv, _ = k_w.shape
-    scratch = torch.empty(ntb * nv * nv, dtype=torch.float64, device=k_w.device)
+    per = nv * nv + (2 * nv * (nv + 1) if nv > 96 else 0)
+    scratch = torch.empty(ntb * per, dtype=torch.float64, device=k_w.device)
     A.check(A.lib.ssm_geneig_trace(int(nv), int(ntb), _ptr(k_w), _ptr(k_z), float(g_max), float(tau), float(rho),
                                    _ptr(dos), _ptr(ranks), _ptr(scratch), _stream()), "ssm_geneig_trace")
     return scratch

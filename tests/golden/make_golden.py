@@ -1,9 +1,12 @@
-"""Write tests/golden/anderson64_fp64_oracle.json: the oracle's SS-DGC estimate at a
-strided subset of sweep points of the 64^3 Anderson workload (N = 262144,
-N_v = 80, M = 1000, N_t = 1000, sigma^ = 0.01), with the shared seeded inputs.
+"""Write the oracle's SS-DGC estimate at a strided subset of sweep points of a
+full-size workload, with the shared seeded inputs:
 
-Calls only the oracle (and the input generators).  Run from the repository root:
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            # 64^3 Anderson (N = 262144, N_v = 80,
+                                                  # M = 1000, N_t = 1000, sigma^ = 0.01)
+    python tests/golden/make_golden.py 4          # the shifted SPD Anderson lattice
+                                                  # (M = 1500, N_t = 1500, sigma^ = 1/150)
+
+Calls only the oracle (and the input generators).  Run from the repository root.
 """
 import json
 import os
@@ -19,13 +22,18 @@ from oracle import ssm_oracle as O  # noqa: E402
 from paper_1504_07690_amd import workloads as WL  # noqa: E402
 
 
-def main(stride=100, out="anderson64_fp64_oracle.json"):
-    wl = WL.make_workload(2)
+OUT = {2: "anderson64_fp64_oracle.json", 4: "anderson64_spd_fp64_oracle.json"}
+
+
+def main(cfg=2, out=None):
+    wl = WL.make_workload(cfg)
+    stride = wl.nt // 10
+    out = out or OUT[cfg]
     points = np.arange(stride // 2, wl.nt, stride)
     t0 = time.time()
     res = O.ss_dgc(wl.a, wl.w(), wl.t, wl.degree, wl.sigma, wl.lo, wl.hi, points=points)
     rec = {
-        "about": "oracle SS-DGC (FP64) on the 64^3 Anderson workload, strided sweep points",
+        "about": "oracle SS-DGC (FP64) on a full-size workload, strided sweep points",
         "workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv, "degree": wl.degree, "nt": wl.nt,
         "sigma_hat": wl.sigma_hat, "lo": wl.lo, "hi": wl.hi, "sigma": wl.sigma, "seed": wl.seed,
         "points": points.tolist(), "dos": res["dos"].tolist(), "r1": res["r1"].tolist(),
@@ -37,4 +45,4 @@ def main(stride=100, out="anderson64_fp64_oracle.json"):
 
 
 if __name__ == "__main__":
-    main()
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)

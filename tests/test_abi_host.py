@@ -52,7 +52,7 @@ def _params(A, **kw):
 
 @pytest.mark.parametrize("bad,status", [
     (dict(lo=1.0, hi=-1.0), 1), (dict(hi=float("nan")), 1), (dict(sigma=0.0), 1), (dict(sigma=-1.0), 1),
-    (dict(nv=6), 1), (dict(nv=0), 1), (dict(nv=128), 7), (dict(degree=0), 1), (dict(degree=5000), 7),
+    (dict(nv=6), 1), (dict(nv=0), 1), (dict(nv=260), 7), (dict(degree=0), 1), (dict(degree=5000), 7),
     (dict(nt=0), 1), (dict(precision=7), 1), (dict(tau=2.0), 1),
 ])
 def test_workspace_size_rejects_bad_params(A, bad, status):
@@ -157,7 +157,7 @@ def test_stage_calls_validate(A):
     assert A.lib.ssm_sweep(1, 100, 4, 8, None, 8, None, None, 0, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_sweep(1, 102, 4, 8, 1, 8, 1, 1, 0, None) == A.SSM_ERR_ARG    # e not a multiple of 4
     assert A.lib.ssm_sweep(1, 100, 4, 8, 1, 6, 1, 1, 0, None) == A.SSM_ERR_ARG    # ldc < ntb
-    assert A.lib.ssm_gram(1, 100, 100, 4, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_UNSUPPORTED
+    assert A.lib.ssm_gram(1, 100, 260, 4, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_UNSUPPORTED
     assert A.lib.ssm_geneig_trace(8, 4, 1, 1, -1.0, 1e-7, 1e-3, 1, None, 1, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_coefficients(1.0, -1.0, 0.1, 10, 1, 4, 10, 1, None, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_gaussian_block(1, 10, 8, 3, 1, None) == A.SSM_ERR_ARG

@@ -1,0 +1,194 @@
+"""Full-size parity for the other workloads, in the planner's own launch configuration:
+
+* er_graph_laplacian_2p20_deg16 (N = 2^20, nnz 17.8M, N_v = 128, M = 2000) and
+  stencil27_128cube_lognormal (N = 2^21, nnz 56.6M, N_v = 256, M = 4000): the oracle
+  cannot run these in a test (hours on the host), so a strided subset of the sweep
+  points runs at full N, N_v and M, and the oracle checks sampled outputs one by one:
+  Chebyshev steps of the last ring chunk on sampled rows, sampled entries of the Gram
+  matrices, and Algorithm 4 on every point from the device's Gram matrices; the DOS
+  obeys 0 <= phi <= N_v (1 + rho) g_max and r2 <= r1 <= N_v.
+* anderson3d_64cube_W4_shifted_spd (N = 262144, N_v = 80, M = 1500, N_t = 1500): the
+  FP32 and split-BF16 DOS against stored oracle values at ten strided points
+  (tests/golden/anderson64_spd_fp64_oracle.json, written by make_golden.py from the
+  oracle only), and the adjoint with checkpoints every 50 degrees against the resident
+  adjoint and central differences.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssm_oracle as O
+from paper_1504_07690_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "anderson64_spd_fp64_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1504_07690_amd import ssm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return ssm
+
+
+def _free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _budget(reserve_gib=24):
+    _free()
+    free, _ = torch.cuda.mem_get_info()
+    return int(free - reserve_gib * (1 << 30))
+
+
+def _ctx(S, wl, precision, t, budget=0, ckpt_every=0):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=t, precision=precision,
+                seed=wl.seed, budget=budget, ckpt_every=ckpt_every, device=DEV)
+    return csr, ctx
+
+
+def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
+    """Stage outputs of a finished ssm_dos against the oracle's arithmetic, sampled."""
+    a = wl.a
+    n, nv, m = a.n, wl.nv, wl.degree
+    v = ctx.views()
+    chunk = v["chunk"]
+    y = v["y"]
+    alpha = 2.0 / (wl.hi - wl.lo)
+    beta = -(wl.hi + wl.lo) / (wl.hi - wl.lo)
+    gmax = O.range_bound(wl.sigma, n)
+    # invariants of the estimate
+    assert np.all(np.isfinite(dos)) and np.all(dos >= 0) and np.all(dos <= nv * (1 + 1e-3) * gmax)
+    assert np.all(r2 <= r1) and np.all(r1 <= nv)
+    # (1) Chebyshev steps of the last ring chunk, on sampled rows
+    k_first = (m // chunk) * chunk
+    ks = [k for k in (m, m - 1, k_first + 2) if k >= max(k_first + 2, 2)]
+    rows = rng.integers(0, n, 5)
+    for k in sorted(set(ks)):
+        for r in rows:
+            cols = a.col_idx[a.row_ptr[r]:a.row_ptr[r + 1]]
+            vals = a.values[a.row_ptr[r]:a.row_ptr[r + 1]]
+            ym1 = y[(k - 1) % chunk][torch.as_tensor(cols, device=DEV)].double().cpu().numpy()
+            ym1_r = y[(k - 1) % chunk][int(r)].double().cpu().numpy()
+            ym2_r = y[(k - 2) % chunk][int(r)].double().cpu().numpy()
+            pred = 2 * (alpha * (vals @ ym1) + beta * ym1_r) - ym2_r
+            got = y[k % chunk][int(r)].double().cpu().numpy()
+            mag = 2 * (alpha * (np.abs(vals) @ np.abs(ym1)) + abs(beta) * np.abs(ym1_r)) + np.abs(ym2_r)
+            assert np.all(np.abs(got - pred) <= 64 * 2.0 ** -24 * mag + 1e-30), (k, r)
+    # (2) sampled Gram entries of two points: K_Z[p][q] = z_p . z_q, K_W = (w_p . z_q + z_p . w_q)/2
+    z = v["z"]
+    w = v["w"]
+    for i in (0, len(t) - 1):
+        for (p, q) in ((0, 0), (0, nv - 1), (nv // 2, nv // 3), (nv - 1, nv - 1)):
+            zp = z[i, :, p].double().cpu().numpy()
+            zq = z[i, :, q].double().cpu().numpy()
+            wp = w[:, p].double().cpu().numpy()
+            wq = w[:, q].double().cpu().numpy()
+            tol = (n + 4) * 2.0 ** -53
+            kz = v["k_z"][i, p, q].item()
+            kw = v["k_w"][i, p, q].item()
+            assert abs(kz - zp @ zq) <= tol * (np.abs(zp) @ np.abs(zq)) + 1e-300
+            ref_w = 0.5 * (wp @ zq + zp @ wq)
+            mag_w = 0.5 * (np.abs(wp) @ np.abs(zq) + np.abs(zp) @ np.abs(wq))
+            assert abs(kw - ref_w) <= tol * mag_w + 1e-300
+    # (3) Algorithm 4 on every point from the device's Gram matrices
+    kw = v["k_w"].cpu().numpy()
+    kz = v["k_z"].cpu().numpy()
+    ref = np.array([O.geneig_trace(kw[i], kz[i], gmax)[0] for i in range(len(t))])
+    bad = np.abs(dos - ref) > 1e-9 * gmax
+    assert bad.sum() <= 1, np.nonzero(bad)
+
+
+@pytest.mark.parametrize("cfg,precision", [(3, "bf16x3"), (3, "bf16"), (5, "bf16x3")])
+def test_large_workload_sampled_stages(S, cfg, precision):
+    wl = WL.make_workload(cfg)
+    t = wl.t[wl.nt // 16::wl.nt // 8]  # 8 strided sweep points
+    csr, ctx = _ctx(S, wl, precision, t, budget=_budget())
+    dos, r1, r2 = ctx.dos()
+    st = ctx.stats()
+    print(f"{wl.name} {precision}: plan {st['passes']} pass(es), ring {st['chunk']}, "
+          f"{st['ms_total']:.0f} ms (recurrence {st['ms_recurrence']:.0f}, sweep {st['ms_sweep']:.0f}, "
+          f"Gram {st['ms_gram']:.0f}, Alg. 4 {st['ms_geneig']:.0f}); r1 {r1.tolist()}")
+    _check_sampled_stages(wl, ctx, t, dos, r1, r2, np.random.default_rng(cfg))
+    ctx.close()
+    del ctx, csr
+    _free()
+
+
+
+@pytest.fixture(scope="module")
+def golden4():
+    if not os.path.exists(GOLDEN4):
+        pytest.skip("stored oracle values of the shifted SPD workload are not present")
+    with open(GOLDEN4) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_spd_workload_against_stored_oracle(S, golden4, precision):
+    g = golden4
+    wl = WL.make_workload(4)
+    assert wl.a.n == g["n"] and wl.a.nnz == g["nnz"] and abs(wl.lo - g["lo"]) < 1e-12
+    csr, ctx = _ctx(S, wl, precision, wl.t)
+    dos, r1, r2 = ctx.dos()
+    ctx.close()
+    del ctx, csr
+    _free()
+    pts = np.array(g["points"])
+    ref = np.array(g["dos"])
+    l1 = np.abs(dos[pts] - ref).sum() / np.abs(ref).sum()
+    print(f"shifted SPD {precision}: L1 vs the stored oracle values {l1:.2e}")
+    assert l1 <= 1e-3
+
+
+def test_spd_workload_checkpointed_adjoint(S):
+    """The adjoint with checkpoints every 50 degrees, as the workload asks: equal to the
+    resident adjoint up to the rounding of the chunked forward sweep, and along a
+    symmetric direction close to central differences of the FP32 DOS."""
+    from test_oracle_pins import _sym_direction
+    wl = WL.make_workload(4)
+    csr, ctx = _ctx(S, wl, "fp32", wl.t)
+    dos, _, _ = ctx.dos()
+    dos_bar = np.random.default_rng(9).uniform(0.0, 1.0, wl.nt) * (dos > 1e-2 * dos.max())
+    g_res = ctx.backward(dos_bar).cpu().numpy()
+    ctx.close()
+    del ctx, csr
+    _free()
+    e = wl.a.n * wl.nv * 4
+    full = _budget(40)
+    budget = min(full, int((wl.nt + 2 * (wl.degree // 50 + 1) + 200) * e * 1.02) + (2 << 30))
+    csr, ctx = _ctx(S, wl, "fp32", wl.t, budget=budget, ckpt_every=50)
+    st = ctx.stats()
+    assert st["passes"] == 1 and 50 <= st["chunk"] < wl.degree + 1, st
+    ctx.dos()
+    g = ctx.backward(dos_bar).cpu().numpy()
+    bs = ctx.backward_stats()
+    rel = np.linalg.norm(g - g_res) / np.linalg.norm(g_res)
+    print(f"shifted SPD adjoint: ring {st['chunk']}, {bs['segments']} segments, {bs['recomputed']} blocks "
+          f"recomputed, {bs['ms_total']:.0f} ms; vs resident {rel:.2e}")
+    assert rel <= 1e-3
+    base = csr.values.clone()
+    h = 1e-3 * np.abs(wl.a.values).max()
+    ed = torch.tensor(_sym_direction(wl.a, 0), dtype=torch.float32, device=DEV)
+    csr.values.copy_(base + h * ed)
+    lp, p1, p2 = ctx.dos()
+    csr.values.copy_(base - h * ed)
+    lm, m1, m2 = ctx.dos()
+    csr.values.copy_(base)
+    keep = dos_bar != 0
+    fd = dos_bar @ (lp - lm) / (2 * h)
+    ad = g @ ed.double().cpu().numpy()
+    print(f"direction 0: adjoint {ad:.6e}  central difference (FP32 DOS) {fd:.6e}; kept sets "
+          f"{'unchanged' if np.array_equal(p1[keep], m1[keep]) and np.array_equal(p2[keep], m2[keep]) else 'changed'}")
+    if np.array_equal(p1[keep], m1[keep]) and np.array_equal(p2[keep], m2[keep]):
+        assert abs(ad - fd) <= 1e-2 * abs(fd)
+    ctx.close()
+    del ctx, csr
+    _free()

@@ -201,7 +201,8 @@ def test_sweep_split_bf16(S, kc, ntb, m1, n, nv):
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("n,nv,ntb,nseg", [(1000, 40, 5, 1), (1000, 80, 3, 3), (97, 8, 2, 1), (4000, 96, 4, 5),
-                                           (33, 4, 1, 1), (2048, 64, 2, 7)])
+                                           (33, 4, 1, 1), (2048, 64, 2, 7), (3000, 128, 2, 3), (1500, 256, 2, 2),
+                                           (501, 200, 1, 1)])
 def test_gram(S, precision, n, nv, ntb, nseg):
     rng = _rng(n + nv)
     dt = torch.float64 if precision == "fp64" else torch.float32
@@ -228,7 +229,8 @@ def _geneig_cases():
     cases = []
     rng = _rng(5)
     # Theorem 3 pencils: exact low rank PSD P, W Gaussian
-    for (n, r, nv) in ((300, 10, 24), (300, 40, 44), (500, 3, 8), (400, 90, 96), (200, 30, 32)):
+    for (n, r, nv) in ((300, 10, 24), (300, 40, 44), (500, 3, 8), (400, 90, 96), (200, 30, 32), (600, 100, 128),
+                       (800, 50, 256), (400, 150, 200)):
         u, _ = np.linalg.qr(rng.standard_normal((n, r)))
         s = rng.uniform(0.001, 0.01, r)
         w = rng.standard_normal((n, nv))
@@ -381,3 +383,20 @@ def test_nan_values_reported(S):
     with pytest.raises(SSMError) as ei:
         _run(S, wl, "fp32")
     assert ei.value.status == SSM_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("nx,nv,degree,nt", [(24, 128, 120, 24), (32, 256, 80, 16)])
+def test_end_to_end_large_nv(S, nx, nv, degree, nt):
+    """N_v above 96 (the Jacobi matrices in global scratch, the tiled Gram): FP64 against
+    the oracle to 1e-9 of g_max, FP32 within 1e-3 relative L1."""
+    rng = _rng(nx + nv)
+    a = WL.laplacian_2d_dirichlet(nx, rng.uniform(-1, 1, nx * nx))
+    wl = WL.make_workload(1, a=a, nv=nv, degree=degree, nt=nt, sigma_hat=0.05)
+    ref = O.ss_dgc(a, wl.w(), wl.t, wl.degree, wl.sigma, wl.lo, wl.hi)
+    gmax = O.range_bound(wl.sigma, a.n)
+    dos, r1, r2, _ = _run(S, wl, "fp64", w=wl.w())
+    assert np.abs(dos - ref["dos"]).max() <= 1e-9 * gmax
+    assert np.array_equal(r1, ref["r1"]) and np.array_equal(r2, ref["r2"])
+    dos32, *_ = _run(S, wl, "fp32", w=wl.w().astype(np.float32))
+    print(f"nv={nv}: fp32 L1 {_l1(dos32, ref['dos']):.2e}")
+    assert _l1(dos32, ref["dos"]) <= 1e-3
