@@ -201,8 +201,10 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = pmc_traffic(roof["kernel"])
     if args.precision == "bf16x3" and dom == "sweep":
-        # achieved counts the algorithmic flops once; the matrix cores run three BF16 products each
-        roof["mfma_issue_frac"] = 3.0 * roof["frac"]
+        # achieved counts the algorithmic flops once; the matrix cores run three BF16 products
+        # on the degrees below split_k3 (rounded up to 32) and one on the rest
+        k3r = min(m + 1, -(-st["split_k3"] // 32) * 32)
+        roof["mfma_issue_frac"] = roof["frac"] * (3.0 * k3r + (m + 1 - k3r)) / (m + 1)
 
     out = {
         "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -214,7 +216,8 @@ def main():
                    "plan": {"passes": st["passes"], "chunk": st["chunk"], "batch": st["batch"]}},
         "spmm": {"GBps": spmm_gbps, "frac_hbm": spmm_gbps / HBM_PEAK_GBPS, "bytes_per_launch": spmm_bytes,
                  "us_per_launch": spmm_us, "launches": st["spmm_launches"]},
-        "sweep": {"TFLOPs": sweep_tflops, "frac_mfma": sweep_tflops / MFMA_PEAK_TFLOPS[args.precision]},
+        "sweep": {"TFLOPs": sweep_tflops, "frac_mfma": sweep_tflops / MFMA_PEAK_TFLOPS[args.precision],
+                  "three_product_degrees": st["split_k3"] if args.precision == "bf16x3" else None},
         "phases_ms": phases,
         "roofline": roof,
     }

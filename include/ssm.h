@@ -103,6 +103,7 @@ typedef struct ssm_stats {
   int32_t chunk;           /* K_c: Chebyshev blocks held at once */
   int32_t batch;           /* N_t^b: sweep points per batch */
   int32_t gram_segments;   /* row segments of the Gram partial sums */
+  int32_t split_k3;        /* SSM_FP32_BF16X3: degrees below this take three products (else 0) */
 } ssm_stats;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -259,9 +260,16 @@ ssm_status ssm_split_coefficients(const double* c, int64_t ldc, int32_t nt, int3
 /* The sweep of ssm_sweep in the SSM_FP32_BF16X3 arithmetic:
  * z[i*e + q] (+)= sum_{k<kc} c[k][i] y[k*e + q] with c given by its split tables
  * (row i at chi + i*ldk, k = 0..kc-1 from the pointer; ldk % 8 == 0, pointers
- * 16-byte aligned); y and z float, e % 4 == 0. */
+ * 16-byte aligned); y and z float, e % 4 == 0.
+ * k3: degrees k < k3 (rounded up to a multiple of 32) take the three products
+ * Chi^T Yhi + Chi^T Ylo + Clo^T Yhi, the others Chi^T Yhi alone; k3 >= kc: three
+ * everywhere.  ssm_dos sets k3 one past the last degree whose coefficients reach
+ * 2^-8 of the table's largest: beyond it the single product's relative rounding
+ * (<= 2^-8) stays under 2^-16 of the largest term, the level the three products
+ * leave on the leading degrees (the Gaussian's coefficients decay like
+ * exp(-(k sigma^)^2/2), so the tail is most of the table). */
 ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, const void* clo, int64_t ldk,
-                           const void* y, void* z, int32_t accumulate, void* stream);
+                           const void* y, void* z, int32_t accumulate, int32_t k3, void* stream);
 
 /* Gram matrices of ntb sweep points (Eq. tracelr, Algorithm 5 step 13):
  * k_w[i] = (W^T Z_i + Z_i^T W)/2,  k_z[i] = Z_i^T Z_i  (nv x nv doubles each),

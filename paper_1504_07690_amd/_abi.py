@@ -38,7 +38,7 @@ class ssm_stats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_recurrence", C.c_double), ("ms_sweep", C.c_double),
                 ("ms_gram", C.c_double), ("ms_geneig", C.c_double), ("spmm_launches", C.c_int64),
                 ("sweep_launches", C.c_int64), ("passes", C.c_int32), ("chunk", C.c_int32),
-                ("batch", C.c_int32), ("gram_segments", C.c_int32)]
+                ("batch", C.c_int32), ("gram_segments", C.c_int32), ("split_k3", C.c_int32)]
 
 
 class ssm_backward_stats(C.Structure):
@@ -80,7 +80,8 @@ _SIGS = {
                                 _P, _P, _P]),
     "ssm_sweep": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, C.c_int64, _P, _P, C.c_int32, _P]),
     "ssm_split_coefficients": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P]),
-    "ssm_sweep_split": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P, _P, C.c_int32, _P]),
+    "ssm_sweep_split": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P, _P, C.c_int32, C.c_int32,
+                                 _P]),
     "ssm_gram": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "ssm_geneig_trace": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P,
                                    _P, _P]),

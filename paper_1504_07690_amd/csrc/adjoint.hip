@@ -21,7 +21,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // v_mfma_f64_16x16x4_f64, T = N_v/16 output blocks per wave.  A wave reads only
 // the rows it writes, and writes them after its last read of them.
 // ---------------------------------------------------------------------------
-constexpr int ZB_ROWS_PER_BLOCK = 1024;
+constexpr int ZB_ROWS_PER_BLOCK = 4096;
 
 template <int T, typename In>
 __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* __restrict__ w, In* __restrict__ z,
@@ -29,15 +29,26 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
                                                    const double* __restrict__ kz_bar) {
   extern __shared__ double kb[];  // [2 nv][16 T]
   constexpr int NP = 16 * T;
+  constexpr int KQ = 2 * NP / 4;  // contraction steps of four
   const int i = blockIdx.y;
   const int64_t nn = (int64_t)nv * nv;
   const double* kwb = kw_bar + i * nn;
   const double* kzb = kz_bar + i * nn;
-  for (int idx = threadIdx.x; idx < 2 * nv * NP; idx += blockDim.x) {
-    const int r = idx / NP, c = idx % NP;
-    double v = 0.0;
-    if (c < nv) v = (r < nv) ? kwb[(int64_t)r * nv + c] : 2.0 * kzb[(int64_t)(r - nv) * nv + c];
-    kb[idx] = v;
+  // stack fill: eight loads in flight per thread before their LDS stores
+  const int total = 2 * nv * NP;
+  for (int base = threadIdx.x; base < total; base += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + 256 * u;
+      const int r = idx / NP, c = idx - (idx / NP) * NP;
+      double x = 0.0;
+      if (idx < total && c < nv) x = (r < nv) ? kwb[(int64_t)r * nv + c] : 2.0 * kzb[(int64_t)(r - nv) * nv + c];
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + 256 * u < total) kb[base + 256 * u] = v[u];
   }
   __syncthreads();
   In* zi = z + (int64_t)i * n * nv;
@@ -45,16 +56,10 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
   const int wave = threadIdx.x >> 6;
   const int64_t r_begin = (int64_t)blockIdx.x * ZB_ROWS_PER_BLOCK;
   const int64_t r_end = (r_begin + ZB_ROWS_PER_BLOCK < n) ? r_begin + ZB_ROWS_PER_BLOCK : n;
-  for (int64_t r0 = r_begin + 16 * wave; r0 < r_end; r0 += 64) {
+  // the 16 x 2 N_v slab of [W | Z] for rows r0 .. r0+15: A[m = lane%16][k = 4 s + lane/16]
+  auto load_slab = [&](int64_t r0, In (&av)[KQ]) {
     const int64_t row = r0 + (lane & 15);
     const bool rok = row < r_end;
-    f64x4 acc[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    // contraction over q < 2 nv (<= 2 NP), four at a time: A[m = lane%16][k = lane/16];
-    // the whole 16 x 2 nv slab is loaded before the MFMAs that use it
-    constexpr int KQ = 2 * NP / 4;
-    In av[KQ];
 #pragma unroll
     for (int s = 0; s < KQ; ++s) {
       const int q = 4 * s + (lane >> 4);
@@ -62,10 +67,20 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
       if (rok && q < 2 * nv) v = (q < nv) ? w[row * nv + q] : zi[row * nv + (q - nv)];
       av[s] = v;
     }
+  };
+  In cur[KQ], nxt[KQ];
+  int64_t r0 = r_begin + 16 * wave;
+  if (r0 < r_end) load_slab(r0, cur);
+  for (; r0 < r_end; r0 += 64) {
+    // the next slab's loads are in flight behind this slab's MFMAs
+    if (r0 + 64 < r_end) load_slab(r0 + 64, nxt);
+    f64x4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < KQ; ++s) {
       const int q = 4 * s + (lane >> 4);
-      const double a = (double)av[s];
+      const double a = (double)cur[s];
 #pragma unroll
       for (int t = 0; t < T; ++t) {
         const double bv = (q < 2 * nv) ? kb[q * NP + 16 * t + (lane & 15)] : 0.0;
@@ -83,6 +98,8 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
         if (orow < r_end && col < nv) zi[orow * nv + col] = (In)acc[t][r];
       }
     }
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) cur[s] = nxt[s];
   }
 }
 

@@ -90,6 +90,24 @@ struct Plan {
          off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, off_ckpt = 0, total = 0;
 };
 
+// Split BF16: one past the last degree whose coefficients reach 2^-8 of the table's
+// largest coefficient (host, from the FP64 table); degrees below it take the three
+// products, the rest one.
+int three_product_degrees(const std::vector<double>& c, int m1, int64_t ldc, int nt) {
+  double cmax = 0.0;
+  std::vector<double> kmax(m1, 0.0);
+  for (int k = 0; k < m1; ++k)
+    for (int i = 0; i < nt; ++i) {
+      const double v = std::fabs(c[(size_t)k * ldc + i]);
+      cmax = std::max(cmax, v);
+      kmax[k] = std::max(kmax[k], v);
+    }
+  int k3 = 0;
+  for (int k = 0; k < m1; ++k)
+    if (kmax[k] >= std::ldexp(cmax, -8)) k3 = k + 1;
+  return k3;
+}
+
 // Checkpoint pairs: (Y_0, Y_1), then (Y_{js-1}, Y_{js}) for 1 <= j <= M/s.
 int ckpt_pairs(int degree, int s) { return degree / s + 1; }
 int ckpt_first(int j, int s) { return j == 0 ? 0 : j * s - 1; }
@@ -199,6 +217,7 @@ struct ssm_ctx {
   float* c32 = nullptr;
   __bf16* chi = nullptr;
   __bf16* clo = nullptr;
+  int k3 = 0;  // split BF16: degrees k < k3 take three products, the rest one
   void* w = nullptr;
   void* y = nullptr;
   void* z = nullptr;
@@ -312,6 +331,13 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
     if ((e = ssm::launch_split_coefficients(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, pl.ldk, p->nt,
                                             c->stream)) != hipSuccess)
       return bail(hip_fail(e, "coefficient split kernel"));
+    const int m1 = p->degree + 1;
+    std::vector<double> table((size_t)m1 * pl.ldc);
+    if ((e = hipMemcpyAsync(table.data(), c->c64, table.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "copy of the coefficient table"));
+    c->k3 = three_product_degrees(table, m1, pl.ldc, p->nt);
   }
   if (own_w) {
     if ((e = ssm::launch_gaussian_block(p->seed, a->n, p->nv, p->precision == SSM_FP64 ? 0 : 1, c->w,
@@ -323,6 +349,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->stats.chunk = pl.chunk;
   c->stats.batch = pl.batch;
   c->stats.gram_segments = pl.nseg;
+  c->stats.split_k3 = c->k3;
   *out = c;
   return SSM_OK;
 }
@@ -417,7 +444,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
       else if (p.precision == SSM_FP32_BF16X3)
         err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
                                        c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0, (const float*)c->y,
-                                       (float*)c->z, ch > 0, st);
+                                       (float*)c->z, ch > 0, c->k3 - k_first, st);
       else if (p.precision == SSM_FP32)
         err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
                                     (const float*)c->y, (float*)c->z, ch > 0, st);
@@ -639,7 +666,7 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
     else
       err = ssm::launch_sweep_bf16x3(e, p.nt, len, (const __bf16*)(ws + L.chit) + (int64_t)a_lo * L.ldkt,
                                      (const __bf16*)(ws + L.clot) + (int64_t)a_lo * L.ldkt, L.ldkt, m1 - a_lo,
-                                     (const float*)c->z, (float*)ybar, 0, st);
+                                     (const float*)c->z, (float*)ybar, 0, p.nt, st);
     if (err != hipSuccess) return hip_fail(err, "transposed sweep");
     SSM_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
     if (pl.ckpt) {
@@ -893,12 +920,12 @@ ssm_status ssm_split_coefficients(const double* c, int64_t ldc, int32_t nt, int3
 }
 
 ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, const void* clo, int64_t ldk,
-                           const void* y, void* z, int32_t accumulate, void* stream) {
+                           const void* y, void* z, int32_t accumulate, int32_t k3, void* stream) {
   if (!chi || !clo || !y || !z) return fail(SSM_ERR_ARG, "chi, clo, y, z must be non-NULL");
   if (e < 1 || kc < 1 || ntb < 1 || ldk < kc || ldk % 8 || e % 4) return fail(SSM_ERR_ARG, "need e % 4 == 0, ldk >= kc, ldk % 8 == 0");
   if (((uintptr_t)chi | (uintptr_t)clo | (uintptr_t)y) % 16) return fail(SSM_ERR_ARG, "pointers must be 16-byte aligned");
   hipError_t err = ssm::launch_sweep_bf16x3(e, kc, ntb, (const __bf16*)chi, (const __bf16*)clo, ldk, ntb,
-                                            (const float*)y, (float*)z, accumulate, (hipStream_t)stream);
+                                            (const float*)y, (float*)z, accumulate, k3, (hipStream_t)stream);
   return err == hipSuccess ? SSM_OK : hip_fail(err, "split sweep GEMM");
 }
 

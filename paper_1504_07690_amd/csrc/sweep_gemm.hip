@@ -16,6 +16,8 @@
 // fastest, so all point tiles that read one Y slice share that XCD's L2.
 #include "ssm_kernels.h"
 
+#include <type_traits>
+
 namespace ssm {
 namespace {
 
@@ -360,6 +362,12 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
 // a quarter-wave fall in distinct banks.  One barrier per k-step: the next tile's
 // global loads are issued right after it, and stored to the other stage after the
 // MFMAs of the current one.
+//
+// Three products on the first k3 degrees of the launch (rounded up to whole k-steps),
+// one (Chi^T Yhi) on the rest: past the last degree whose coefficients reach 2^-8 of
+// the largest, the single product's rounding (at most 2^-8 relative) stays under 2^-16
+// of the largest term, the level the three products leave on the leading degrees.  The
+// two kinds of k-step run as two straight loops over the same accumulators.
 // ---------------------------------------------------------------------------
 constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 32;
 constexpr int X3_TILE = 256 * X3_BK;  // bf16 per LDS tile
@@ -380,7 +388,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
                                                            const __bf16* __restrict__ clo, int64_t ldk,
                                                            int64_t arows, const float* __restrict__ y,
                                                            float* __restrict__ z, int accumulate, int mt,
-                                                           int nt_tiles) {
+                                                           int nt_tiles, int k3) {
   extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
   // stage s: Ahi, Alo, Bhi, Blo at (4 s + 0..3) * X3_TILE
   __bf16* lds = (__bf16*)x3_lds;
@@ -467,11 +475,16 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
   const int nk = (kc + X3_BK - 1) / X3_BK;
+  const int nk3 = k3 <= 0 ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
   load_tile(0);
   store_tile(0);
   if (nk > 1) load_tile(X3_BK);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  // one k-step: MFMAs on stage kt & 1 (three products, or Chi^T Yhi alone), then the
+  // next tile into the other stage (last read before the previous barrier), barrier,
+  // and the loads of the tile after it
+  auto kstep = [&](int kt, auto three) {
+    constexpr bool THREE = decltype(three)::value;
     const int st = kt & 1;
     const __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
     const __bf16* alo = lds + (4 * st + 1) * X3_TILE;
@@ -485,27 +498,33 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       for (int b = 0; b < 2; ++b) {
         const int o = x3_off(wn * 64 + b * 32 + (lane & 31), ch);
         bh[b] = *(const bf16x8*)(bhi + o);
-        bl[b] = *(const bf16x8*)(blo + o);
+        if constexpr (THREE) bl[b] = *(const bf16x8*)(blo + o);
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int o = x3_off(wm * 128 + a * 32 + (lane & 31), ch);
         const bf16x8 ah = *(const bf16x8*)(ahi + o);
-        const bf16x8 al = *(const bf16x8*)(alo + o);
-        // small products first, the three products of one block two MFMAs apart
+        if constexpr (THREE) {
+          const bf16x8 al = *(const bf16x8*)(alo + o);
+          // small products first, the three products of one block two MFMAs apart
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+        }
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
     }
-    // the other stage was last read before the previous barrier: fill it with tile kt+1
     if (kt + 1 < nk) store_tile(st ^ 1);
     __syncthreads();
     if (kt + 2 < nk) load_tile((kt + 2) * X3_BK);
-  }
+  };
+  int kt = 0;
+  for (; kt < nk3; ++kt) kstep(kt, std::true_type{});
+  for (; kt < nk; ++kt) kstep(kt, std::false_type{});
 
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -571,7 +590,8 @@ hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t
 size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * 4 * X3_TILE * sizeof(__bf16); }
 
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
-                               int64_t arows, const float* y, float* z, int accumulate, hipStream_t stream) {
+                               int64_t arows, const float* y, float* z, int accumulate, int k3,
+                               hipStream_t stream) {
   const size_t lds = sweep_bf16x3_lds_bytes();
   hipError_t err = hipFuncSetAttribute((const void*)sweep_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -582,7 +602,7 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo, ldk,
-                     arows, y, z, accumulate, mt, (int)ntiles);
+                     arows, y, z, accumulate, mt, (int)ntiles, k3);
   return hipGetLastError();
 }
 

@@ -255,16 +255,19 @@ def split_coefficients(c: torch.Tensor, nt: int, ldk: int):
     return chi.view(nt, ldk), clo.view(nt, ldk)
 
 
-def sweep_split(chi: torch.Tensor, clo: torch.Tensor, y: torch.Tensor, z: torch.Tensor, kc=None, accumulate=False):
-    """z[i] (+)= sum_{k<kc} c[k, i] y[k] in the bf16x3 arithmetic, c given by its split tables."""
+def sweep_split(chi: torch.Tensor, clo: torch.Tensor, y: torch.Tensor, z: torch.Tensor, kc=None, accumulate=False,
+                k3=None):
+    """z[i] (+)= sum_{k<kc} c[k, i] y[k] in the bf16x3 arithmetic, c given by its split tables;
+    degrees k >= k3 (rounded up to a multiple of 32) take the single product Chi Yhi."""
     _require_cuda(chi, clo, y, z)
     ntb_tab, ldk = chi.shape
     kc = y.shape[0] if kc is None else kc
     ntb = z.shape[0]
     assert ntb <= ntb_tab
     e = y[0].numel()
+    k3 = kc if k3 is None else int(k3)
     A.check(A.lib.ssm_sweep_split(int(e), int(kc), int(ntb), _ptr(chi), _ptr(clo), int(ldk), _ptr(y), _ptr(z),
-                                  int(bool(accumulate)), _stream()), "ssm_sweep_split")
+                                  int(bool(accumulate)), k3, _stream()), "ssm_sweep_split")
 
 
 def gram(precision, w: torch.Tensor, z: torch.Tensor, k_w: torch.Tensor, k_z: torch.Tensor, nseg=1):

@@ -196,6 +196,34 @@ def test_sweep_split_bf16(S, kc, ntb, m1, n, nv):
     assert np.all(np.abs(zd.cpu().numpy() - z0 - full) <= 2.0 ** -14 * fmag + 1e-300)
 
 
+@pytest.mark.parametrize("kc,ntb,n,nv,k3", [(70, 257, 130, 40, 20), (70, 257, 130, 40, 33), (45, 20, 64, 8, 0),
+                                              (16, 5, 33, 4, 1), (100, 9, 40, 8, 64)])
+def test_sweep_split_tail_single_product(S, kc, ntb, n, nv, k3):
+    """bf16x3 sweep with the single product Chi Yhi past the first k3 degrees (k3 rounded
+    up to a multiple of 32) and the three products before."""
+    rng = _rng(kc + 3 * ntb + k3)
+    ldc = (ntb + 3) // 4 * 4
+    m1 = kc
+    ldk = (m1 + 7) // 8 * 8
+    c = rng.standard_normal((m1, ldc))
+    y = rng.standard_normal((kc, n, nv)).astype(np.float32).astype(np.float64)
+    cd = torch.tensor(c, device=DEV)
+    chi, clo = S.split_coefficients(cd, ntb, ldk)
+    hi = bf16_from_f64(c[:, :ntb])
+    lo = bf16_from_f64(c[:, :ntb] - hi)
+    yhi, ylo = bf16_split(y)
+    k3r = min(kc, -(-k3 // 32) * 32)
+    three = (np.arange(kc) < k3r).astype(np.float64)[:, None]  # per degree
+    mu_h, mu_l = hi[:kc], lo[:kc] * three
+    ref = O.sweep(mu_h, iter(yhi)) + O.sweep(mu_h * three, iter(ylo)) + O.sweep(mu_l, iter(yhi))
+    mag = O.sweep(np.abs(mu_h), iter(np.abs(y))) + O.sweep(np.abs(mu_l), iter(np.abs(y)))
+    tol = (3 * kc + 2) * 2.0 ** -24
+    yd = torch.tensor(y, dtype=torch.float32, device=DEV)
+    zd = torch.zeros(ntb, n, nv, dtype=torch.float32, device=DEV)
+    S.sweep_split(chi, clo, yd, zd, kc=kc, k3=k3)
+    assert np.all(np.abs(zd.cpu().numpy() - ref) <= tol * mag + 1e-300)
+
+
 # ----------------------------------------------------------------------------
 # Gram
 # ----------------------------------------------------------------------------
