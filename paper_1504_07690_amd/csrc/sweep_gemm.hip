@@ -367,7 +367,9 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
 // one (Chi^T Yhi) on the rest: past the last degree whose coefficients reach 2^-8 of
 // the largest, the single product's rounding (at most 2^-8 relative) stays under 2^-16
 // of the largest term, the level the three products leave on the leading degrees.  The
-// two kinds of k-step run as two straight loops over the same accumulators.
+// two kinds of k-step run as two straight loops over the same accumulators.  In the
+// transposed sweep the degrees are the output rows: tiles whose rows all lie at or past
+// m3 take the single product throughout.
 // ---------------------------------------------------------------------------
 constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 32;
 constexpr int X3_TILE = 256 * X3_BK;  // bf16 per LDS tile
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
                                                            const __bf16* __restrict__ clo, int64_t ldk,
                                                            int64_t arows, const float* __restrict__ y,
                                                            float* __restrict__ z, int accumulate, int mt,
-                                                           int nt_tiles, int k3) {
+                                                           int nt_tiles, int k3, int m3) {
   extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
   // stage s: Ahi, Alo, Bhi, Blo at (4 s + 0..3) * X3_TILE
   __bf16* lds = (__bf16*)x3_lds;
@@ -407,7 +409,8 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   u16x8 ra_hi[2], ra_lo[2];
   // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k)
   f32x2 rb[8];
-  auto load_tile = [&](int k0) {
+  // lo halves are moved only for k-steps that take the three products
+  auto load_tile = [&](int k0, bool three) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int piece = tid + 512 * u;
@@ -416,7 +419,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
       if (i < arows && k < kc) {
         vh = *(const u16x8*)(chi + i * ldk + k);
-        vl = *(const u16x8*)(clo + i * ldk + k);
+        if (three) vl = *(const u16x8*)(clo + i * ldk + k);
         if (k + 8 > kc) {  // entries past the chunk belong to the next chunk
 #pragma unroll
           for (int j = 0; j < 8; ++j)
@@ -436,7 +439,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       rb[j] = v;
     }
   };
-  auto store_tile = [&](int st) {
+  auto store_tile = [&](int st, bool three) {
     __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
     __bf16* alo = lds + (4 * st + 1) * X3_TILE;
     __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
@@ -446,7 +449,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       const int piece = tid + 512 * u;
       const int o = x3_off(piece >> 2, piece & 3);
       *(u16x8*)(ahi + o) = ra_hi[u];
-      *(u16x8*)(alo + o) = ra_lo[u];
+      if (three) *(u16x8*)(alo + o) = ra_lo[u];
     }
     const int c2 = (tid & 127) * 2;
     const int ch = tid >> 7;
@@ -462,7 +465,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       }
       const int o = x3_off(c2 + c, ch);
       *(bf16x8*)(bhi + o) = h;
-      *(bf16x8*)(blo + o) = l;
+      if (three) *(bf16x8*)(blo + o) = l;
     }
   };
 
@@ -475,10 +478,12 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
   const int nk = (kc + X3_BK - 1) / X3_BK;
-  const int nk3 = k3 <= 0 ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
-  load_tile(0);
-  store_tile(0);
-  if (nk > 1) load_tile(X3_BK);
+  // three products on the first k3 degrees, and only in tiles that hold one of the
+  // first m3 output rows (the transposed sweep's rows are degrees)
+  const int nk3 = (k3 <= 0 || i0 >= m3) ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
+  load_tile(0, 0 < nk3);
+  store_tile(0, 0 < nk3);
+  if (nk > 1) load_tile(X3_BK, 1 < nk3);
   __syncthreads();
   // one k-step: MFMAs on stage kt & 1 (three products, or Chi^T Yhi alone), then the
   // next tile into the other stage (last read before the previous barrier), barrier,
@@ -518,9 +523,9 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
     }
-    if (kt + 1 < nk) store_tile(st ^ 1);
+    if (kt + 1 < nk) store_tile(st ^ 1, kt + 1 < nk3);
     __syncthreads();
-    if (kt + 2 < nk) load_tile((kt + 2) * X3_BK);
+    if (kt + 2 < nk) load_tile((kt + 2) * X3_BK, kt + 2 < nk3);
   };
   int kt = 0;
   for (; kt < nk3; ++kt) kstep(kt, std::true_type{});
@@ -590,7 +595,7 @@ hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t
 size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * 4 * X3_TILE * sizeof(__bf16); }
 
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
-                               int64_t arows, const float* y, float* z, int accumulate, int k3,
+                               int64_t arows, const float* y, float* z, int accumulate, int k3, int m3,
                                hipStream_t stream) {
   const size_t lds = sweep_bf16x3_lds_bytes();
   hipError_t err = hipFuncSetAttribute((const void*)sweep_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -602,7 +607,7 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo, ldk,
-                     arows, y, z, accumulate, mt, (int)ntiles, k3);
+                     arows, y, z, accumulate, mt, (int)ntiles, k3, m3);
   return hipGetLastError();
 }
 
