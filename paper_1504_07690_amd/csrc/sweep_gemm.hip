@@ -356,7 +356,9 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
 // MFMA blocks (128 accumulators, so two waves share a SIMD).  The coefficients
 // arrive pre-split in k-contiguous tables chi/clo [i][ldk]; the Y tile is split in
 // registers while being transposed (a thread reads 8 consecutive k of 2 elements and
-// writes, per element, 8 k of hi and of lo as 16-byte LDS stores).  LDS holds two
+// writes, per element, 8 k of hi and of lo as 16-byte LDS stores; odd lanes store their
+// second element first, so that each store of a wave covers even and odd rows, which fall
+// in different halves of the bank window).  LDS holds two
 // stages of the four 256 x 32 BF16 tiles (128 KB); rows are 64 bytes and the 16-byte
 // k-chunk c of row r sits at chunk c ^ ((r >> 2) & 3), so that the 16 rows read by
 // a quarter-wave fall in distinct banks.  One barrier per k-step: the next tile's
@@ -453,17 +455,19 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
     }
     const int c2 = (tid & 127) * 2;
     const int ch = tid >> 7;
+    const int sw = tid & 1;  // odd lanes store their second element first
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+      const int cc = c ^ sw;
       bf16x8 h, l;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         __bf16 hh, ll;
-        split_bf16(rb[j][c], hh, ll);
+        split_bf16(cc ? rb[j][1] : rb[j][0], hh, ll);
         h[j] = hh;
         l[j] = ll;
       }
-      const int o = x3_off(c2 + c, ch);
+      const int o = x3_off(c2 + cc, ch);
       *(bf16x8*)(bhi + o) = h;
       if (three) *(bf16x8*)(blo + o) = l;
     }
