@@ -406,30 +406,52 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   const int wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;
 
-  // A staging: 256 rows x 4 chunks per table = 1024 pieces; thread t moves pieces t and
-  // t + 512 of hi and of lo (row = piece / 4, chunk = piece % 4)
+  // The k range runs as units: unit u < nk3 is one three-product k-step (32 degrees at
+  // 32 u); each later unit is two single-product k-steps (64 degrees), whose two hi tiles
+  // take the hi and lo slots of a stage, so the tail runs half as many barriers.
+  const int nk = (kc + X3_BK - 1) / X3_BK;
+  // three products on the first k3 degrees, and only in tiles that hold one of the
+  // first m3 output rows (the transposed sweep's rows are degrees)
+  const int nk3 = (k3 <= 0 || i0 >= m3) ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
+  const int nu = nk3 + (nk - nk3 + 1) / 2;
+  auto unit_k0 = [&](int u) { return u < nk3 ? X3_BK * u : X3_BK * nk3 + 2 * X3_BK * (u - nk3); };
+
+  // A staging: 256 rows x 4 chunks per tile = 1024 pieces; thread t moves pieces t and
+  // t + 512 (row = piece / 4, chunk = piece % 4): into ra_hi from chi, into ra_lo from
+  // clo (three-product unit) or from chi 32 degrees on (single-product unit)
   u16x8 ra_hi[2], ra_lo[2];
-  // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k)
-  f32x2 rb[8];
-  // lo halves are moved only for k-steps that take the three products
-  auto load_tile = [&](int k0, bool three) {
+  // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k); rb2
+  // holds the second k-step of a single-product unit
+  f32x2 rb[8], rb2[8];
+  auto load_unit = [&](int u) {
+    const bool three = u < nk3;
+    const int k0 = unit_k0(u);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int piece = tid + 512 * u;
+    for (int h = 0; h < 2; ++h) {
+      const int piece = tid + 512 * h;
       const int64_t i = i0 + (piece >> 2);
       const int k = k0 + (piece & 3) * 8;
+      const int k2 = three ? k : k + X3_BK;
+      const __bf16* tab2 = three ? clo : chi;
       u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
       if (i < arows && k < kc) {
         vh = *(const u16x8*)(chi + i * ldk + k);
-        if (three) vl = *(const u16x8*)(clo + i * ldk + k);
         if (k + 8 > kc) {  // entries past the chunk belong to the next chunk
 #pragma unroll
           for (int j = 0; j < 8; ++j)
-            if (k + j >= kc) { vh[j] = 0; vl[j] = 0; }
+            if (k + j >= kc) vh[j] = 0;
         }
       }
-      ra_hi[u] = vh;
-      ra_lo[u] = vl;
+      if (i < arows && k2 < kc) {
+        vl = *(const u16x8*)(tab2 + i * ldk + k2);
+        if (k2 + 8 > kc) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (k2 + j >= kc) vl[j] = 0;
+        }
+      }
+      ra_hi[h] = vh;
+      ra_lo[h] = vl;
     }
     const int c2 = (tid & 127) * 2;
     const int kq = k0 + (tid >> 7) * 8;
@@ -440,18 +462,28 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
       rb[j] = v;
     }
+    if (!three) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = kq + X3_BK + j;
+        f32x2 v = {0.f, 0.f};
+        if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
+        rb2[j] = v;
+      }
+    }
   };
-  auto store_tile = [&](int st, bool three) {
+  auto store_unit = [&](int st, int u) {
+    const bool three = u < nk3;
     __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
     __bf16* alo = lds + (4 * st + 1) * X3_TILE;
     __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
     __bf16* blo = lds + (4 * st + 3) * X3_TILE;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int piece = tid + 512 * u;
+    for (int h = 0; h < 2; ++h) {
+      const int piece = tid + 512 * h;
       const int o = x3_off(piece >> 2, piece & 3);
-      *(u16x8*)(ahi + o) = ra_hi[u];
-      if (three) *(u16x8*)(alo + o) = ra_lo[u];
+      *(u16x8*)(ahi + o) = ra_hi[h];
+      *(u16x8*)(alo + o) = ra_lo[h];
     }
     const int c2 = (tid & 127) * 2;
     const int ch = tid >> 7;
@@ -465,11 +497,15 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
         __bf16 hh, ll;
         split_bf16(cc ? rb[j][1] : rb[j][0], hh, ll);
         h[j] = hh;
-        l[j] = ll;
+        if (three) {
+          l[j] = ll;
+        } else {
+          l[j] = (__bf16)(cc ? rb2[j][1] : rb2[j][0]);  // hi of the second k-step
+        }
       }
       const int o = x3_off(c2 + cc, ch);
       *(bf16x8*)(bhi + o) = h;
-      if (three) *(bf16x8*)(blo + o) = l;
+      *(bf16x8*)(blo + o) = l;
     }
   };
 
@@ -481,24 +517,9 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  const int nk = (kc + X3_BK - 1) / X3_BK;
-  // three products on the first k3 degrees, and only in tiles that hold one of the
-  // first m3 output rows (the transposed sweep's rows are degrees)
-  const int nk3 = (k3 <= 0 || i0 >= m3) ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
-  load_tile(0, 0 < nk3);
-  store_tile(0, 0 < nk3);
-  if (nk > 1) load_tile(X3_BK, 1 < nk3);
-  __syncthreads();
-  // one k-step: MFMAs on stage kt & 1 (three products, or Chi^T Yhi alone), then the
-  // next tile into the other stage (last read before the previous barrier), barrier,
-  // and the loads of the tile after it
-  auto kstep = [&](int kt, auto three) {
+  // one 32-degree k-step of MFMAs on LDS tiles (ah, al) x (bh, bl)
+  auto mfma_step = [&](const __bf16* ahi, const __bf16* alo, const __bf16* bhi, const __bf16* blo, auto three) {
     constexpr bool THREE = decltype(three)::value;
-    const int st = kt & 1;
-    const __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
-    const __bf16* alo = lds + (4 * st + 1) * X3_TILE;
-    const __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
-    const __bf16* blo = lds + (4 * st + 3) * X3_TILE;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int ch = 2 * ks + (lane >> 5);
@@ -527,13 +548,33 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
     }
-    if (kt + 1 < nk) store_tile(st ^ 1, kt + 1 < nk3);
-    __syncthreads();
-    if (kt + 2 < nk) load_tile((kt + 2) * X3_BK, kt + 2 < nk3);
   };
-  int kt = 0;
-  for (; kt < nk3; ++kt) kstep(kt, std::true_type{});
-  for (; kt < nk; ++kt) kstep(kt, std::false_type{});
+  load_unit(0);
+  store_unit(0, 0);
+  if (nu > 1) load_unit(1);
+  __syncthreads();
+  // one unit: MFMAs on stage u & 1, then the next unit into the other stage (last read
+  // before the previous barrier), barrier, and the loads of the unit after it
+  auto unit = [&](int u, auto three) {
+    constexpr bool THREE = decltype(three)::value;
+    const int st = u & 1;
+    const __bf16* s0 = lds + (4 * st + 0) * X3_TILE;
+    const __bf16* s1 = lds + (4 * st + 1) * X3_TILE;
+    const __bf16* s2 = lds + (4 * st + 2) * X3_TILE;
+    const __bf16* s3 = lds + (4 * st + 3) * X3_TILE;
+    if constexpr (THREE) {
+      mfma_step(s0, s1, s2, s3, std::true_type{});
+    } else {
+      mfma_step(s0, s0, s2, s2, std::false_type{});
+      mfma_step(s1, s1, s3, s3, std::false_type{});
+    }
+    if (u + 1 < nu) store_unit(st ^ 1, u + 1);
+    __syncthreads();
+    if (u + 2 < nu) load_unit(u + 2);
+  };
+  int u = 0;
+  for (; u < nk3; ++u) unit(u, std::true_type{});
+  for (; u < nu; ++u) unit(u, std::false_type{});
 
 #pragma unroll
   for (int a = 0; a < 4; ++a)
