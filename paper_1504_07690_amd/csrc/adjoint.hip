@@ -16,7 +16,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Zbar, in place over Z: one workgroup per (sweep point, run of rows).  The
-// (2 N_v) x N_v stack [Kbar_W; 2 Kbar_Z] sits in LDS as FP64; each wave takes 16
+// stack [Kbar_W; 2 Kbar_Z] sits in LDS as FP64 (two 16T x 16T halves); each wave takes 16
 // rows at a time and multiplies [W | Z] (16 x 2 N_v) by it on
 // v_mfma_f64_16x16x4_f64, T = N_v/16 output blocks per wave.  A wave reads only
 // the rows it writes, and writes them after its last read of them.
@@ -27,7 +27,9 @@ template <int T, typename In>
 __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* __restrict__ w, In* __restrict__ z,
                                                    const double* __restrict__ kw_bar,
                                                    const double* __restrict__ kz_bar) {
-  extern __shared__ double kb[];  // [2 nv][16 T]
+  // [Kbar_W; 2 Kbar_Z] as two NP x NP halves (rows and columns past N_v zero), so that
+  // the contraction index q < 2 NP needs no bounds test
+  extern __shared__ double kb[];
   constexpr int NP = 16 * T;
   constexpr int KQ = 2 * NP / 4;  // contraction steps of four
   const int i = blockIdx.y;
@@ -35,15 +37,16 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
   const double* kwb = kw_bar + i * nn;
   const double* kzb = kz_bar + i * nn;
   // stack fill: eight loads in flight per thread before their LDS stores
-  const int total = 2 * nv * NP;
+  constexpr int total = 2 * NP * NP;
   for (int base = threadIdx.x; base < total; base += 8 * 256) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + 256 * u;
-      const int r = idx / NP, c = idx - (idx / NP) * NP;
+      const int r = idx / NP, c = idx % NP;
+      const int hr = r < NP ? r : r - NP;  // row inside its half
       double x = 0.0;
-      if (idx < total && c < nv) x = (r < nv) ? kwb[(int64_t)r * nv + c] : 2.0 * kzb[(int64_t)(r - nv) * nv + c];
+      if (idx < total && c < nv && hr < nv) x = (r < NP) ? kwb[(int64_t)hr * nv + c] : 2.0 * kzb[(int64_t)hr * nv + c];
       v[u] = x;
     }
 #pragma unroll
@@ -56,16 +59,20 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
   const int wave = threadIdx.x >> 6;
   const int64_t r_begin = (int64_t)blockIdx.x * ZB_ROWS_PER_BLOCK;
   const int64_t r_end = (r_begin + ZB_ROWS_PER_BLOCK < n) ? r_begin + ZB_ROWS_PER_BLOCK : n;
-  // the 16 x 2 N_v slab of [W | Z] for rows r0 .. r0+15: A[m = lane%16][k = 4 s + lane/16]
+  // the 16 x 2 NP slab of [W | Z] for rows r0 .. r0+15: A[m = lane%16][k = 4 s + lane/16];
+  // indices are clamped into the arrays (rows past the range, columns past N_v), and the
+  // values they bring meet zero stack rows or feed rows that are not stored
   auto load_slab = [&](int64_t r0, In (&av)[KQ]) {
-    const int64_t row = r0 + (lane & 15);
-    const bool rok = row < r_end;
+    int64_t row = r0 + (lane & 15);
+    row = row < r_end ? row : r_end - 1;
+    const In* wr = w + row * nv;
+    const In* zr = zi + row * nv;
 #pragma unroll
     for (int s = 0; s < KQ; ++s) {
       const int q = 4 * s + (lane >> 4);
-      In v = (In)0;
-      if (rok && q < 2 * nv) v = (q < nv) ? w[row * nv + q] : zi[row * nv + (q - nv)];
-      av[s] = v;
+      const int c = (q < NP ? q : q - NP);
+      const int cc = c < nv ? c : nv - 1;
+      av[s] = (q < NP) ? wr[cc] : zr[cc];
     }
   };
   In cur[KQ], nxt[KQ];
@@ -77,15 +84,23 @@ __global__ void __launch_bounds__(256) zbar_kernel(int64_t n, int nv, const In* 
     f64x4 acc[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    // the stack operands of step s + 1 are read from LDS behind the MFMAs of step s
+    const double* kbl = kb + (lane >> 4) * NP + (lane & 15);
+    double bcur[T], bnxt[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) bcur[t] = kbl[16 * t];
 #pragma unroll
     for (int s = 0; s < KQ; ++s) {
-      const int q = 4 * s + (lane >> 4);
+      if (s + 1 < KQ) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) bnxt[t] = kbl[4 * (s + 1) * NP + 16 * t];
+      }
       const double a = (double)cur[s];
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const double bv = (q < 2 * nv) ? kb[q * NP + 16 * t + (lane & 15)] : 0.0;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < T; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur[t], acc[t], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < T; ++t) bcur[t] = bnxt[t];
     }
     // result register r of lane l holds D[l/16 + 4r][l%16]; every read of these
     // rows by this wave is complete (the MFMA results depend on all of them)
@@ -283,7 +298,7 @@ hipError_t launch_zbar_big(int is_f32, int64_t n, int nv, int ntb, const void* w
 template <int T>
 hipError_t launch_zbar_t(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kwb,
                          const double* kzb, hipStream_t stream) {
-  const size_t lds = (size_t)2 * nv * 16 * T * sizeof(double);
+  const size_t lds = (size_t)2 * (16 * T) * (16 * T) * sizeof(double);
   dim3 grid((unsigned)((n + ZB_ROWS_PER_BLOCK - 1) / ZB_ROWS_PER_BLOCK), ntb);
   hipError_t err;
   if (is_f32) {
