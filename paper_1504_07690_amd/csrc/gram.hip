@@ -5,14 +5,15 @@
 // in FP64 on v_mfma_f64_16x16x4_f64.  FP32 inputs are widened to FP64 exactly, so
 // every product is exact and only the FP64 sums round.
 //
-// Work split (N_v <= 96): one workgroup per (sweep point, row segment); each of its four waves
-// walks a contiguous quarter of the segment, four rows per MFMA step (the MFMA's
-// k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of W^T Z + Z^T W
-// in registers, so its operands come straight from memory: lane l reads column
-// 16a + l%16 of row r + l/16 for each column block a, for Z_i and W (a 4-row slab
-// is contiguous), two steps ahead of the MFMAs that consume them.  Each wave
-// writes its partial blocks to scratch; a second kernel adds the partials in a
-// fixed order, mirrors the lower triangle and halves K_W (deterministic).
+// Work split (N_v <= 96): one workgroup per (sweep point, row segment); each of its
+// four waves walks a contiguous quarter of the segment, four rows per MFMA step (the
+// MFMA's k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of
+// W^T Z + Z^T W (W^T Z alone on the diagonal) in registers, so its operands come
+// straight from memory: lane l reads column 16a + l%16 of row r + l/16 for each column
+// block a, for Z_i and W (a 4-row slab is contiguous), two steps ahead of the MFMAs
+// that consume them.  Each wave writes its partial blocks to scratch; a second kernel
+// adds the partials in a fixed order, mirrors the lower triangle and halves K_W
+// (deterministic).
 #include "ssm_kernels.h"
 
 namespace ssm {
@@ -128,10 +129,12 @@ __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, c
         const int p = a * T - a * (a - 1) / 2 + (bb - a);
         acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wf[a], zf[bb], acc_wz[p], 0, 0, 0);
       }
+    // Z_a^T W_b only off the diagonal: on a diagonal block it is the transpose of W_a^T Z_a,
+    // and the reduction symmetrises that block instead
 #pragma unroll
     for (int a = 0; a < T; ++a)
 #pragma unroll
-      for (int bb = a; bb < T; ++bb) {
+      for (int bb = a + 1; bb < T; ++bb) {
         const int p = a * T - a * (a - 1) / 2 + (bb - a);
         acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[a], wf[bb], acc_wz[p], 0, 0, 0);
       }
@@ -251,7 +254,8 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
         const int p = a * GT_B + bb;
         acc_zz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], zb[bb], acc_zz[p], 0, 0, 0);
         acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[a], zb[bb], acc_wz[p], 0, 0, 0);
-        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], wb[bb], acc_wz[p], 0, 0, 0);
+        if (ti != tj || a != bb)  // diagonal blocks: W_a^T Z_a alone (symmetrised in the reduction)
+          acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], wb[bb], acc_wz[p], 0, 0, 0);
       }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -284,7 +288,9 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
 }
 
 // K(i)[r][c] = sum over segments of the stored upper block entry; the lower blocks
-// mirror the upper ones; the diagonal blocks are averaged with their transpose.
+// mirror the upper ones; the diagonal blocks are averaged with their transpose.  A
+// diagonal block of the W-part holds W_a^T Z_a alone (an off-diagonal one W_a^T Z_b +
+// Z_a^T W_b), hence its factor 1/2 against 1/4.
 __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int nseg, const double* __restrict__ part,
                                                           double* __restrict__ k_w, double* __restrict__ k_z) {
   const int64_t nn = (int64_t)nv * nv;
@@ -307,7 +313,7 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int n
     sw2 += pw[o2];
   }
   k_z[gid] = 0.5 * (sz1 + sz2);
-  k_w[gid] = 0.25 * (sw1 + sw2);
+  k_w[gid] = ((r >> 4) == (c >> 4) ? 0.5 : 0.25) * (sw1 + sw2);
 }
 
 int64_t rows_per_segment(int64_t n, int nseg) {
