@@ -7,10 +7,11 @@ recurrence, split-BF16 (three BF16 MFMA products, FP32 accumulation) sweep, FP64
 Gram / Algorithm 4; the FP64, FP32 and plain-BF16 paths are timed beside it with
 their DOS L1 against the FP64 path.  One step = one full ssm_dos (coefficients and
 W are set up once, outside the timed region).  The adjoint (ssm_backward) of the
-measured path is timed once after the steps.
+measured path is timed once after the steps, and so is one ssm_dos that also forms the
+DGC estimate of Algorithm 2 from the same recurrence.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
-                    [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint]
+                    [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint] [--no-dgc]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -101,6 +102,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint (ssm_backward)")
+    ap.add_argument("--no-dgc", action="store_true", help="skip the run with the DGC moments (Algorithm 2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -132,11 +134,13 @@ def main():
 
     adjoint = {}
 
-    def run(precision, steps, warmup, budget=0, with_adjoint=False):
+    dgc_out = {}
+
+    def run(precision, steps, warmup, budget=0, with_adjoint=False, dgc=False):
         dt = torch.float64 if precision == "fp64" else torch.float32
         csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=dev)
         ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=wl.t, precision=precision,
-                    seed=wl.seed, budget=budget, device=dev)
+                    seed=wl.seed, budget=budget, dgc=dgc, device=dev)
         for _ in range(warmup):
             ctx.dos()
         torch.cuda.synchronize()
@@ -146,6 +150,8 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t_start) * 1e3 / max(steps, 1)
         st = ctx.stats()
+        if dgc:
+            dgc_out["dos"], _ = ctx.dgc()
         if with_adjoint:
             # gradient of sum_i dos_bar_i dos_i w.r.t. the nnz values, dos_bar weighting the
             # resolved points (estimate above 1e-2 of its maximum): one warm-up, one timed
@@ -235,6 +241,15 @@ def main():
                 mso, doso, *_ = run(other, 1, 1, budget=0)
                 comparisons[other] = {"s_per_dos": mso / 1e3,
                                       "dos_l1_vs_fp64": float(np.abs(doso - dos64).sum() / np.abs(dos64).sum())}
+    if not args.no_dgc:
+        # Algorithm 2 on the same recurrence: the moments ride on the steps s <= M/2
+        msd, dosd, _, _, std = run(args.precision, 1, 1, budget=0, dgc=True)
+        keep = dos > 1e-2 * dos.max()
+        comparisons["dgc_by_product"] = {
+            "s_per_dos": msd / 1e3, "ms_recurrence": std["ms_recurrence"],
+            "ms_recurrence_without": st["ms_recurrence"],
+            "ssm_dos_max_rel_change": float(np.abs(dosd - dos).max() / dos.max()),
+            "dgc_vs_ssm_l1_resolved": float(np.abs(dgc_out["dos"][keep] - dosd[keep]).sum() / np.abs(dosd[keep]).sum())}
     out["comparisons"] = comparisons
     if adjoint:
         out["adjoint"] = adjoint

@@ -87,6 +87,8 @@ typedef struct ssm_params {
                               blocks, ssm_dos also keeps the pairs (Y_0, Y_1) and (Y_{js-1},
                               Y_{js}) (Y_k = T_k(A~)W, 1 <= j <= M/s) and the ring keeps >= s
                               blocks, so that the backward recomputes the rest segment by segment */
+  int32_t dgc;             /* nonzero: ssm_dos also forms the DGC estimate of Algorithm 2 from the
+                              same recurrence (same W, M and sweep points); read it with ssm_dgc */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)
@@ -139,6 +141,18 @@ ssm_status ssm_dos(ssm_ctx* ctx, double* dos_host, int32_t* ranks_host);
 /* Sum_i w[i] * dos[i] over the DOS of the last ssm_dos (Algorithm 8, step 4).
  * SSM_ERR_STATE before the first ssm_dos. */
 ssm_status ssm_trace(ssm_ctx* ctx, const double* w_host, double* tr);
+
+/* Algorithm 2 (DGC) on the context's W, degree M and sweep points, formed by the last
+ * ssm_dos of a context made with p->dgc != 0 (SSM_ERR_STATE otherwise):
+ *   zeta_l = Tr[W^T T_l(A~) W] / N_v (l = 0..M),  dgc_host[i] = sum_l mu_l(t_i) zeta_l.
+ * The moments come from inner products the recurrence takes on its way (no extra pass
+ * over W): the step that forms Y_{s+1} = T_{s+1}(A~)W from Y_s also sums <Y_s, Y_s> and
+ * <Y_{s+1}, Y_s> (FP64 sums of the block type's products), and for symmetric A, with
+ * T_s^2 = (T_{2s} + T_0)/2 and T_{s+1} T_s = (T_{2s+1} + T_1)/2,
+ *   N_v zeta_{2s} = 2 <Y_s, Y_s> - N_v zeta_0,  N_v zeta_{2s+1} = 2 <Y_{s+1}, Y_s> - N_v zeta_1,
+ * so only the steps s <= M/2 take them.  dgc_host: nt doubles (A's units);
+ * zeta_host: NULL or M+1 doubles.  Synchronises the stream. */
+ssm_status ssm_dgc(ssm_ctx* ctx, double* dgc_host, double* zeta_host);
 
 ssm_status ssm_get_stats(const ssm_ctx* ctx, ssm_stats* out);
 

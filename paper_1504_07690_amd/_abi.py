@@ -31,7 +31,7 @@ class ssm_csr(C.Structure):
 class ssm_params(C.Structure):
     _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
                 ("range_slack", C.c_double), ("nv", C.c_int32), ("degree", C.c_int32), ("nt", C.c_int32),
-                ("precision", C.c_int32), ("seed", C.c_uint64), ("ckpt_every", C.c_int32)]
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("ckpt_every", C.c_int32), ("dgc", C.c_int32)]
 
 
 class ssm_stats(C.Structure):
@@ -65,6 +65,7 @@ _SIGS = {
                              C.c_size_t, _P, C.POINTER(_P)]),
     "ssm_dos": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "ssm_trace": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ssm_dgc": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ssm_get_stats": (C.c_int, [_P, C.POINTER(ssm_stats)]),
     "ssm_get_views": (C.c_int, [_P, C.POINTER(ssm_views)]),
     "ssm_destroy": (C.c_int, [_P]),

@@ -12,6 +12,8 @@
 // the lanes of a row read the row's CSR entries (the same addresses, merged by
 // the memory pipeline) and gather the neighbours' slices, so every gathered row
 // is read as whole 16-byte pieces of a contiguous N_v*elem segment.
+#include <algorithm>
+
 #include "ssm_kernels.h"
 
 namespace ssm {
@@ -31,18 +33,35 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 //
 // out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null; the reverse
 // recurrence of the adjoint uses d for its direct seed).
-template <typename T, typename V>
+template <typename V>
+__device__ __forceinline__ double vdot(const V& u, const V& v);
+template <>
+__device__ __forceinline__ double vdot<f32x4>(const f32x4& u, const f32x4& v) {
+  return (double)u.x * (double)v.x + (double)u.y * (double)v.y + (double)u.z * (double)v.z + (double)u.w * (double)v.w;
+}
+template <>
+__device__ __forceinline__ double vdot<f64x2>(const f64x2& u, const f64x2& v) {
+  return u.x * v.x + u.y * v.y;
+}
+
+// DOTS: the workgroup also writes dots[2 lblock] = <out, x> and dots[2 lblock + 1] =
+// <x, x> over its slices (FP64 sums of exact products), for the Chebyshev moments of
+// Algorithm 2 by the product identity T_j T_k = (T_{j+k} + T_{|j-k|}) / 2.
+template <typename T, typename V, bool DOTS>
 __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
                                                         const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col_idx,
                                                         const T* __restrict__ val, T a, T b, T c,
                                                         const V* __restrict__ x, const V* __restrict__ xprev,
-                                                        const V* __restrict__ d, V* __restrict__ out) {
+                                                        const V* __restrict__ d, V* __restrict__ out,
+                                                        double* __restrict__ dots) {
   const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (lblock >= nblocks) return;
-  const int64_t gid = lblock * blockDim.x + threadIdx.x;
+  if (lblock >= nblocks) return;  // uniform over the workgroup
+  const int64_t gid0 = lblock * blockDim.x + threadIdx.x;
+  const bool valid = gid0 < n * (int64_t)nvv;
+  if (!DOTS && !valid) return;
+  const int64_t gid = valid ? gid0 : 0;  // idle lanes of a DOTS block recompute slice 0 and store nothing
   const int64_t r = gid / nvv;
-  if (r >= n) return;
   const int q = (int)(gid - r * nvv);
   const int p0 = row_ptr[r];
   const int p1 = row_ptr[r + 1];
@@ -62,22 +81,94 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int6
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
   }
-  V res = a * acc + b * x[gid];
+  const V xo = x[gid];
+  V res = a * acc + b * xo;
   if (xprev) res += c * __builtin_nontemporal_load(&xprev[gid]);
   if (d) res += __builtin_nontemporal_load(&d[gid]);
-  __builtin_nontemporal_store(res, &out[gid]);
+  if (valid) __builtin_nontemporal_store(res, &out[gid]);
+  if constexpr (DOTS) {
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = valid ? vdot<V>(res, xo) : 0.0;
+    red[1][threadIdx.x] = valid ? vdot<V>(xo, xo) : 0.0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + st];
+        red[1][threadIdx.x] += red[1][threadIdx.x + st];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      dots[2 * lblock] = red[0][0];
+      dots[2 * lblock + 1] = red[1][0];
+    }
+  }
+}
+
+// Inner products of a group of recurrence steps from their workgroup partials: workgroup
+// g reduces step s = s0 + g (partials at dots + 2 g nblocks) in a fixed order and writes
+// sums[2 s] = <Y_s, Y_s> and sums[2 s + 1] = <Y_{s+1}, Y_s> (Y_0 = W).
+__global__ void __launch_bounds__(256) moments_kernel(int64_t nblocks, const double* __restrict__ dots, int s0,
+                                                      double* __restrict__ sums) {
+  __shared__ double red[2][256];
+  const double* d = dots + 2 * nblocks * (int64_t)blockIdx.x;
+  double ox = 0.0, xx = 0.0;
+  for (int64_t bidx = threadIdx.x; bidx < nblocks; bidx += 256) {
+    ox += d[2 * bidx];
+    xx += d[2 * bidx + 1];
+  }
+  red[0][threadIdx.x] = ox;
+  red[1][threadIdx.x] = xx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int s = s0 + blockIdx.x;
+    sums[2 * s] = red[1][0];
+    sums[2 * s + 1] = red[0][0];
+  }
+}
+
+// Algorithm 2 from the step inner products: T_s^2 = (T_{2s} + T_0)/2 and T_{s+1} T_s =
+// (T_{2s+1} + T_1)/2 for symmetric A~ give N_v zeta_0 = <W, W>, N_v zeta_1 = <Y_1, W>,
+// N_v zeta_l = 2 sums[l] - N_v zeta_{l mod 2} (l >= 2); then phi(t_i) = sum_l mu_l(t_i)
+// zeta_l in a fixed order.  zeta (m1 doubles) may be NULL.
+__global__ void __launch_bounds__(256) dgc_kernel(const double* __restrict__ c, int64_t ldc, int nt, int m1, int nv,
+                                                  const double* __restrict__ sums, double* __restrict__ out,
+                                                  double* __restrict__ zeta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double z0 = sums[0] / nv;
+  const double z1 = m1 > 1 ? sums[1] / nv : 0.0;
+  auto zl = [&](int l) { return l == 0 ? z0 : l == 1 ? z1 : 2.0 * sums[l] / nv - ((l & 1) ? z1 : z0); };
+  if (zeta)
+    for (int l = i; l < m1; l += gridDim.x * blockDim.x) zeta[l] = zl(l);
+  if (i >= nt) return;
+  double acc = 0.0;
+  for (int l = 0; l < m1; ++l) acc += c[(int64_t)l * ldc + i] * zl(l);
+  out[i] = acc;
 }
 
 template <typename T, typename V, int VEC>
 hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx, const T* val, T a, T b,
-                  T c, const T* x, const T* xprev, const T* d, T* out, hipStream_t stream) {
+                  T c, const T* x, const T* xprev, const T* d, T* out, double* dots, hipStream_t stream) {
   const int nvv = nv / VEC;
   const int64_t threads = n * nvv;
   const int64_t nblocks = (threads + 255) / 256;
   const int64_t per_xcd = (nblocks + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((cheb_step_kernel<T, V>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv, nblocks,
-                     per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out);
+  if (dots)
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv,
+                       nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
+                       (V*)out, dots);
+  else
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, false>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv,
+                       nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
+                       (V*)out, nullptr);
   return hipGetLastError();
 }
 
@@ -85,14 +176,34 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
 
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
-                                const double* xprev, const double* d, double* out, hipStream_t stream) {
-  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, stream);
+                                const double* xprev, const double* d, double* out, hipStream_t stream,
+                                double* dots) {
+  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, stream);
 }
 
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
-                                const float* xprev, const float* d, float* out, hipStream_t stream) {
-  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, stream);
+                                const float* xprev, const float* d, float* out, hipStream_t stream,
+                                double* dots) {
+  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, stream);
+}
+
+int64_t cheb_step_blocks(int64_t n, int nv, int is_f32) {
+  const int nvv = nv / (is_f32 ? 4 : 2);
+  return (n * nvv + 255) / 256;
+}
+
+hipError_t launch_moments(int64_t nblocks, const double* dots, int s0, int count, double* sums,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(moments_kernel, dim3((unsigned)count), dim3(256), 0, stream, nblocks, dots, s0, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgc(const double* c, int64_t ldc, int nt, int m1, int nv, const double* sums, double* out,
+                      double* zeta, hipStream_t stream) {
+  hipLaunchKernelGGL(dgc_kernel, dim3((unsigned)((std::max(nt, m1) + 255) / 256)), dim3(256), 0, stream, c, ldc, nt,
+                     m1, nv, sums, out, zeta);
+  return hipGetLastError();
 }
 
 }  // namespace ssm

@@ -87,8 +87,20 @@ struct Plan {
   int ckpt = 0;  // checkpoint interval s when the ring holds fewer than M+1 blocks, else 0
   int64_t ldc = 4, ldk = 8;
   size_t off_t = 0, off_c64 = 0, off_c32 = 0, off_chi = 0, off_clo = 0, off_w = 0, off_y = 0, off_z = 0, off_kw = 0, off_kz = 0,
-         off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, off_ckpt = 0, total = 0;
+         off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, off_ckpt = 0, off_dpart = 0,
+         off_dsums = 0, off_dgc = 0, total = 0;
+  int dgc_group = 0;  // recurrence steps whose inner-product partials are held at once (0: no DGC)
 };
+
+// Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
+// workgroup partials are reduced a group of steps at a time (at most 64 steps or 256 MiB).
+int dgc_steps(int degree) { return degree / 2 + 1; }
+int dgc_group(const ssm_csr* a, const ssm_params* p) {
+  if (!p->dgc) return 0;
+  const int64_t per_step = 2 * ssm::cheb_step_blocks(a->n, p->nv, p->precision != SSM_FP64) * 8;
+  const int64_t fit = std::max<int64_t>(1, (int64_t(256) << 20) / per_step);
+  return (int)std::min<int64_t>({(int64_t)64, fit, (int64_t)dgc_steps(p->degree)});
+}
 
 // Split BF16: one past the last degree whose coefficients reach 2^-8 of the table's
 // largest coefficient (host, from the FP64 table); degrees below it take the three
@@ -148,6 +160,12 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_y = take((size_t)pl.chunk * e * es);
   pl.ckpt = (p->ckpt_every > 0 && pl.chunk < p->degree + 1) ? p->ckpt_every : 0;
   pl.off_ckpt = take(pl.ckpt ? (size_t)2 * ckpt_pairs(p->degree, pl.ckpt) * e * es : 0);
+  pl.dgc_group = dgc_group(a, p);
+  pl.off_dpart = take(pl.dgc_group ? (size_t)pl.dgc_group * 2 *
+                                         ssm::cheb_step_blocks(a->n, p->nv, p->precision != SSM_FP64) * 8
+                                   : 0);
+  pl.off_dsums = take(pl.dgc_group ? (size_t)2 * dgc_steps(p->degree) * 8 : 0);
+  pl.off_dgc = take(pl.dgc_group ? (size_t)(p->nt + p->degree + 1) * 8 : 0);
   pl.total = o;
 }
 
@@ -229,8 +247,12 @@ struct ssm_ctx {
   double* dos = nullptr;
   int32_t* ranks = nullptr;
   double* norm = nullptr;
+  double* dpart = nullptr;  // DGC: workgroup partials of a group of steps
+  double* dsums = nullptr;  // DGC: <Y_s, Y_s>, <Y_{s+1}, Y_s> per step
+  double* dgc = nullptr;    // DGC: nt estimates, then M+1 moments
   std::vector<double> dos_host;
   bool have_dos = false;
+  bool have_dgc = false;
   ssm_stats stats{};
   std::vector<hipEvent_t> events;
   int last_batch_start = 0;
@@ -307,6 +329,11 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->dos = (double*)(c->ws + pl.off_dos);
   c->ranks = (int32_t*)(c->ws + pl.off_ranks);
   c->norm = (double*)(c->ws + pl.off_norm);
+  if (pl.dgc_group) {
+    c->dpart = (double*)(c->ws + pl.off_dpart);
+    c->dsums = (double*)(c->ws + pl.off_dsums);
+    c->dgc = (double*)(c->ws + pl.off_dgc);
+  }
   c->dos_host.assign(p->nt, 0.0);
 
   auto bail = [&](ssm_status st) {
@@ -392,6 +419,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   int64_t spmm_launches = 0, sweep_launches = 0;
 
   auto y_slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % pl.chunk) * e * es; };
+  const int64_t dgc_nblocks = ssm::cheb_step_blocks(n, nv, !f64);
   for (int pass = 0; pass < pl.passes; ++pass) {
     const int p0 = pass * pl.batch;
     const int nb = std::min(pl.batch, p.nt - p0);
@@ -411,14 +439,22 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
           const double a = (k == 1) ? alpha : 2.0 * alpha;
           const double b = (k == 1) ? beta : 2.0 * beta;
           const double cc = (k == 1) ? 0.0 : -1.0;
+          const int s_step = k - 1;  // this step forms Y_{s+1} from Y_s
+          const bool moments = pl.dgc_group && pass == 0 && s_step < dgc_steps(m);
+          double* dots = moments ? c->dpart + (size_t)(s_step % pl.dgc_group) * 2 * dgc_nblocks : nullptr;
           if (f64)
             err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
-                                            (const double*)x, (const double*)xp, nullptr, (double*)out, st);
+                                            (const double*)x, (const double*)xp, nullptr, (double*)out, st, dots);
           else
             err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
                                             (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out,
-                                            st);
+                                            st, dots);
           ++spmm_launches;
+          if (err == hipSuccess && moments &&
+              (s_step % pl.dgc_group == pl.dgc_group - 1 || s_step == dgc_steps(m) - 1)) {
+            const int s0 = s_step - s_step % pl.dgc_group;
+            err = ssm::launch_moments(dgc_nblocks, c->dpart, s0, s_step - s0 + 1, c->dsums, st);
+          }
         }
         if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
         if (pl.ckpt && pass == 0) {  // keep the checkpoint pairs for the adjoint
@@ -478,6 +514,10 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
   SSM_HIP(hipEventRecord(c->events[es_.en], st), "hipEventRecord");
   spans.push_back(es_);
+  if (pl.dgc_group) {
+    err = ssm::launch_dgc(c->c64, pl.ldc, p.nt, m + 1, nv, c->dsums, c->dgc, c->dgc + p.nt, st);
+    if (err != hipSuccess) return hip_fail(err, "Algorithm 2 kernel");
+  }
 
   std::vector<double> dos(p.nt);
   std::vector<int32_t> ranks(2 * (size_t)p.nt);
@@ -512,6 +552,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (ranks_host) std::copy(ranks.begin(), ranks.end(), ranks_host);
   c->dos_host = dos;
   c->have_dos = true;
+  c->have_dgc = pl.dgc_group > 0;
   c->z_valid = true;
   return SSM_OK;
 }
@@ -741,6 +782,21 @@ ssm_status ssm_trace(ssm_ctx* c, const double* w_host, double* tr) {
   double acc = 0.0;
   for (int i = 0; i < c->p.nt; ++i) acc += w_host[i] * c->dos_host[i];
   *tr = acc;
+  return SSM_OK;
+}
+
+ssm_status ssm_dgc(ssm_ctx* c, double* dgc_host, double* zeta_host) {
+  if (!c || !dgc_host) return fail(SSM_ERR_ARG, "ctx and dgc must be non-NULL");
+  if (!c->pl.dgc_group) return fail(SSM_ERR_STATE, "the context was made without dgc");
+  if (!c->have_dgc) return fail(SSM_ERR_STATE, "ssm_dgc before ssm_dos");
+  const int nt = c->p.nt, m1 = c->p.degree + 1;
+  SSM_HIP(hipMemcpyAsync(dgc_host, c->dgc, sizeof(double) * nt, hipMemcpyDeviceToHost, c->stream), "copy DGC");
+  if (zeta_host)
+    SSM_HIP(hipMemcpyAsync(zeta_host, c->dgc + nt, sizeof(double) * m1, hipMemcpyDeviceToHost, c->stream),
+            "copy moments");
+  SSM_HIP(hipStreamSynchronize(c->stream), "ssm_dgc sync");
+  for (int i = 0; i < nt; ++i)
+    if (!std::isfinite(dgc_host[i])) return fail(SSM_ERR_NONFINITE, "DGC estimate at point %d is not finite", i);
   return SSM_OK;
 }
 

@@ -18,10 +18,22 @@ hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, vo
 //   out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null)
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
-                                const double* xprev, const double* d, double* out, hipStream_t stream);
+                                const double* xprev, const double* d, double* out, hipStream_t stream,
+                                double* dots = nullptr);
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
-                                const float* xprev, const float* d, float* out, hipStream_t stream);
+                                const float* xprev, const float* d, float* out, hipStream_t stream,
+                                double* dots = nullptr);
+// Chebyshev moments for Algorithm 2.  With dots (2 cheb_step_blocks doubles) a step also
+// writes workgroup partials of <out, x> and <x, x>.  launch_moments reduces `count`
+// consecutive steps s0.. (partials 2 cheb_step_blocks apart; step s forms Y_{s+1} from
+// Y_s) into sums[2s] = <Y_s, Y_s>, sums[2s+1] = <Y_{s+1}, Y_s>.  launch_dgc forms
+// phi(t_i) = sum_l c[l][i] zeta_l (and zeta, if not NULL) from sums.
+int64_t cheb_step_blocks(int64_t n, int nv, int is_f32);
+hipError_t launch_moments(int64_t nblocks, const double* dots, int s0, int count, double* sums,
+                          hipStream_t stream);
+hipError_t launch_dgc(const double* c, int64_t ldc, int nt, int m1, int nv, const double* sums, double* out,
+                      double* zeta, hipStream_t stream);
 
 // Adjoint (adjoint.hip).
 hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, void* z, const double* kw_bar,

@@ -49,15 +49,16 @@ class DeviceCSR:
                          self.values.data_ptr())
 
 
-def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0) -> A.ssm_params:
+def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0, dgc=False) -> A.ssm_params:
     return A.ssm_params(float(lo), float(hi), float(sigma), float(tau), float(rho), int(nv), int(degree),
-                        int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF, int(ckpt_every))
+                        int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF, int(ckpt_every),
+                        int(bool(dgc)))
 
 
 def workspace_size(csr: DeviceCSR, *, lo, hi, sigma, nv, degree, nt, precision="fp32", tau=1e-7, rho=1e-3,
-                   seed=0, budget=0, ckpt_every=0) -> int:
+                   seed=0, budget=0, ckpt_every=0, dgc=False) -> int:
     out = C.c_size_t(0)
-    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every)
+    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc)
     A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(p), C.c_size_t(budget), C.byref(out)),
             "ssm_workspace_size")
     return int(out.value)
@@ -67,7 +68,7 @@ class SSM:
     """One context of the spectrum sweeping method (Algorithm 5) on the device."""
 
     def __init__(self, csr: DeviceCSR, *, lo, hi, sigma, nv, degree, t, precision="fp32", tau=1e-7, rho=1e-3,
-                 seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, device="cuda:0"):
+                 seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, dgc=False, device="cuda:0"):
         self.csr = csr
         self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         self.nt = int(self.t.size)
@@ -79,7 +80,8 @@ class SSM:
             if w.dtype != self.elem or tuple(w.shape) != (csr.n, nv) or not w.is_contiguous():
                 raise ValueError(f"w must be a contiguous {self.elem} tensor of shape ({csr.n}, {nv})")
         self.w_in = w
-        self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every)
+        self.degree = int(degree)
+        self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every, dgc)
         size = C.c_size_t(0)
         A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(self.params), C.c_size_t(budget),
                                          C.byref(size)), "ssm_workspace_size")
@@ -101,6 +103,15 @@ class SSM:
         A.check(A.lib.ssm_dos(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)),
                               ranks.ctypes.data_as(C.POINTER(C.c_int32))), "ssm_dos")
         return out, ranks[: self.nt].copy(), ranks[self.nt:].copy()
+
+    def dgc(self):
+        """(dgc, zeta): the DGC estimate of Algorithm 2 at the sweep points and the moments
+        zeta_0..zeta_M, from the last dos() (context made with dgc=True)."""
+        out = np.zeros(self.nt, dtype=np.float64)
+        zeta = np.zeros(self.degree + 1, dtype=np.float64)
+        A.check(A.lib.ssm_dgc(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)),
+                              zeta.ctypes.data_as(C.POINTER(C.c_double))), "ssm_dgc")
+        return out, zeta
 
     def trace(self, w) -> float:
         w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))

@@ -80,6 +80,23 @@ def test_workspace_plan_single_pass_size(A):
     assert out.value < (m + 1) * e + nt * e + 8 * 1024 * 1024
 
 
+@pytest.mark.parametrize("precision,vec", [(0, 2), (1, 4)])
+def test_dgc_moments_workspace(A, precision, vec):
+    """dgc != 0 adds the moments' workgroup partials (a group of at most 64 of the M/2 + 1
+    steps, two doubles per workgroup of 256 lanes, a lane per 16 bytes of a row), the
+    per-step sums and the nt + M + 1 outputs, and nothing else."""
+    n, nv, m, nt = 100000, 8, 300, 20
+    base, more = C.c_size_t(0), C.c_size_t(0)
+    p = _params(A, nv=nv, degree=m, nt=nt, precision=precision)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(base)) == 0
+    p.dgc = 1
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(more)) == 0
+    blocks = -(-n * (nv // vec) // 256)
+    up = lambda b: -(-b // 256) * 256
+    want = up(64 * 2 * blocks * 8) + up(2 * (m // 2 + 1) * 8) + up((nt + m + 1) * 8)
+    assert more.value - base.value == want
+
+
 def test_workspace_budget_forces_more_passes_or_chunks(A):
     n, nv, m, nt = 100000, 8, 200, 64
     p = _params(A, nv=nv, degree=m, nt=nt, precision=1)

@@ -199,3 +199,29 @@ def test_fullsize_mixed_adjoint_against_fp64(setup, precision, tol):
     err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
     print(f"{precision} adjoint at full size: {bs['ms_total']:.0f} ms, relative error vs FP64 {err:.3e}")
     assert err <= tol
+
+
+def test_fullsize_dgc_moments(setup):
+    """Algorithm 2 from the benchmark's recurrence (split-BF16 context): the first 17
+    moments against the oracle's zeta_l = Tr[W^T T_l(A~) W]/N_v on the device's W, and
+    |zeta_l| <= zeta_0 for every l (|T_l| <= 1 on the spectrum)."""
+    S, wl, g = setup
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
+                precision="bf16x3", seed=wl.seed, dgc=True, device=DEV)
+    dos, _, _ = ctx.dos()
+    st = ctx.stats()
+    dgc, zeta = ctx.dgc()
+    w = ctx.views()["w"].double().cpu().numpy()
+    ctx.close()
+    del ctx, csr
+    _free()
+    ref = np.zeros(17)
+    for l, v_c in O.chebyshev_blocks(wl.a, w, 16, wl.lo, wl.hi):
+        ref[l] = np.sum(w * v_c) / wl.nv
+    assert np.abs(zeta[:17] - ref).max() <= 1e-5 * ref[0]
+    assert np.all(np.abs(zeta) <= zeta[0] * (1 + 1e-5))
+    keep = dos > 1e-2 * dos.max()
+    l1 = np.abs(dgc[keep] - dos[keep]).sum() / np.abs(dos[keep]).sum()
+    print(f"DGC by-product: recurrence {st['ms_recurrence']:.1f} ms; DGC vs SS-DGC L1 at resolved points {l1:.2e}")
+    assert np.all(np.isfinite(dgc))

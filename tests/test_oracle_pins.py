@@ -244,6 +244,27 @@ def test_identity_probe_reproduces_exact_dos():
     assert np.all(out["dos"] <= ref + 1e-9 * gmax)
 
 
+def test_dgc_identity_probe_reproduces_exact_dos():
+    """Algorithm 2 with W = sqrt(N) I_N (N_v = N, W W^T = N_v I, the case in which the
+    Hutchinson average of Theorem 1 has no variance): zeta_l = Tr T_l(A~) exactly, so the
+    DGC estimate is the Chebyshev expansion of the regularised DOS itself, equal to it up
+    to the truncation of Theorem 2."""
+    rng = np.random.default_rng(12)
+    a = WL.laplacian_2d_dirichlet(14, rng.uniform(-1, 1, 196))
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    lam = np.linalg.eigvalsh(a.to_dense())
+    sigma = 0.05 * hw
+    t = 0.5 * (lo + hi) + hw * WL.midpoint_grid(40)
+    ref = O.exact_dos(lam, t, sigma)
+    probe = np.sqrt(a.n) * np.eye(a.n)
+    out = O.dgc_dos(a, probe, t, 200, sigma, lo, hi)
+    assert np.abs(out - ref).max() < 1e-8 * ref.max()
+    # a truncated expansion is visibly worse: the degree matters
+    coarse = O.dgc_dos(a, probe, t, 20, sigma, lo, hi)
+    assert np.abs(coarse - ref).max() > 1e-3 * ref.max()
+
+
 @pytest.mark.slow
 def test_ssm_beats_dgc_when_sampled_enough():
     """Section 3.2 / Fig. 6: once N_v exceeds the numerical rank of g(tI - A),
