@@ -25,6 +25,8 @@ Readings where the paper is silent (each also listed in the design notes):
   max_i s_i <= 0 nothing is kept and the estimate is 0.
 * Algorithm 4, step 4 keeps xi in [0, (1 + rho) / (N sqrt(2 pi sigma^2))]
   (closed interval, relative slack rho, default 1e-3).
+* Algorithm 7 takes mu_l (l <= M/2) from Algorithm 1 run at degree M (the
+  run's N_theta) and sets the rest to 0; M must be even (Proposition 1).
 * Algorithm 8 deconvolves with the unit-mass Gaussian (N times g_sigma),
   periodically on [-1, 1] in the rescaled variable, dropping wavenumbers k
   with exp(-(sigma^ pi k)^2 / 2) < eta (eta = 1e-10).
@@ -165,21 +167,24 @@ def geneig_trace(k_w: np.ndarray, k_z: np.ndarray, g_max: float, tau: float = 1e
     2. keep s_j >= tau max_i s_i  (S~, U~).
     3. eig of S~^{-1/2} U~^* Z^*Z U~ S~^{-1/2}  -> xi.
     4. keep xi in [0, (1 + rho) g_max].
-    Returns the sum of kept xi and the two kept counts (r1, r2).
+    Returns the sum of kept xi and the two kept counts (r1, r2); with
+    ``return_parts`` also a dict with s, xi and C~ = U~ S~^{-1/2} Q~ (Q~: the
+    eigenvectors of step 3 whose xi pass step 4), so that C~^* K_W C~ = I and
+    C~^* K_Z C~ = Xi~.
     """
     k_w = 0.5 * (k_w + k_w.T)
     s, u = np.linalg.eigh(k_w)
     smax = s.max() if s.size else 0.0
     if not smax > 0.0:
         out = (0.0, 0, 0)
-        return out + ({"s": s, "xi": np.zeros(0)},) if return_parts else out
+        return out + ({"s": s, "xi": np.zeros(0), "c": np.zeros((k_w.shape[0], 0))},) if return_parts else out
     keep = s >= tau * smax
     u_t = u[:, keep] / np.sqrt(s[keep])[None, :]
     b = u_t.T @ k_z @ u_t
-    xi = np.linalg.eigvalsh(0.5 * (b + b.T))
+    xi, q = np.linalg.eigh(0.5 * (b + b.T))
     in_range = (xi >= 0.0) & (xi <= (1.0 + rho) * g_max)
     out = (float(xi[in_range].sum()), int(keep.sum()), int(in_range.sum()))
-    return out + ({"s": s, "xi": xi},) if return_parts else out
+    return out + ({"s": s, "xi": xi, "c": u_t @ q[:, in_range]},) if return_parts else out
 
 
 def sweep(mu: np.ndarray, blocks) -> np.ndarray:
@@ -237,6 +242,78 @@ def ss_dgc(a, w, t, degree: int, sigma: float, lo: float, hi: float, tau: float 
     if keep:
         out.update(z=z, k_w=np.array(kws), k_z=np.array(kzs))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Section 4: RESS-DGC (Proposition 1, Theorem 4, Algorithms 6 and 7)
+# ----------------------------------------------------------------------------
+def square_coefficients(mu_half: np.ndarray, degree: int, n_theta: int | None = None) -> np.ndarray:
+    """nu_l(t_i), l = 0..M, with (sum_{k<=M/2} mu_k T_k)^2 = sum_{l<=M} nu_l T_l
+    (Proposition 1), by the quadrature of Algorithm 1 applied to the squared series:
+    p_j = sum_k mu_k T_k(cos theta_j), nu_l = (2 - delta_l0)/(2 N_theta) Re DFT(p^2)_l.
+    The quadrature is exact for N_theta > M (the integrand has degree <= 2M in
+    cos theta).  ``mu_half`` has shape (M/2 + 1, N_t); returns (M + 1, N_t).
+    """
+    n_theta = n_theta_for(degree) if n_theta is None else n_theta
+    assert n_theta > degree
+    theta = np.arange(2 * n_theta) * math.pi / n_theta
+    p = chebyshev_eval(np.asarray(mu_half, dtype=np.float64), np.cos(theta)[:, None])   # (2 N_theta, N_t)
+    phat = np.fft.fft(p * p, axis=0)
+    nu = phat[: degree + 1].real / (2 * n_theta)
+    nu[1:] *= 2.0
+    return nu
+
+
+def ress_dgc(a, w, w_tilde, t, degree: int, sigma: float, lo: float, hi: float, tau: float = 1e-7,
+             rho: float = 1e-3):
+    """RESS-DGC estimate of phi_sigma at the sweep points (Algorithm 7).
+
+    1. mu_l(t_i) by Algorithm 1 at degree M, set to 0 for l > M/2;
+    2. nu_l(t_i), l <= M, of the squared degree-M/2 series (Proposition 1);
+    3-15. one recurrence on W (N x N_v) and one on W~ (N x N~_v, may have no
+       columns); at every degree l: X_W = W^* V_c, X_C = W~^* V_c, X_W~ = W~^* V~_c, and
+       K_W += mu_l X_W, K_Z += nu_l X_W, K_C += mu_l X_C, K_W~ += mu_l X_W~ per point;
+    16-18. per point, Algorithm 4 on (K_Z, K_W) gives Xi~ and C~, and
+       phi~ = Tr Xi~ + (Tr K_W~ - Tr[K_C C~ C~^* K_C^*]) / N~_v  (the last term only
+       when N~_v > 0; Algorithm 6).
+    Returns a dict with ``dos``, ``r1``, ``r2`` and the accumulated matrices.
+    """
+    assert degree % 2 == 0, "Proposition 1 needs an even degree"
+    w = np.asarray(w, dtype=np.float64)
+    w_tilde = np.zeros((w.shape[0], 0)) if w_tilde is None else np.asarray(w_tilde, dtype=np.float64)
+    n, nv = w.shape
+    nvt = w_tilde.shape[1]
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    nt = t.size
+    half = degree // 2
+    mu = dgc_coefficients(t, degree, sigma, n, lo, hi)                    # step 1
+    mu[half + 1:] = 0.0
+    nu = square_coefficients(mu[: half + 1], degree)                       # step 2
+    k_w = np.zeros((nt, nv, nv))
+    k_z = np.zeros((nt, nv, nv))
+    k_c = np.zeros((nt, nvt, nv))
+    k_wt = np.zeros((nt, nvt, nvt))
+    blocks_t = chebyshev_blocks(a, w_tilde, degree, lo, hi) if nvt else None
+    for l, v_c in chebyshev_blocks(a, w, degree, lo, hi):                  # steps 6-15
+        x_w = w.T @ v_c
+        k_w += mu[l][:, None, None] * x_w[None]
+        k_z += nu[l][:, None, None] * x_w[None]
+        if nvt:
+            _, vt_c = next(blocks_t)
+            k_c += mu[l][:, None, None] * (w_tilde.T @ v_c)[None]
+            k_wt += mu[l][:, None, None] * (w_tilde.T @ vt_c)[None]
+    g_max = range_bound(sigma, n)
+    dos = np.zeros(nt)
+    r1 = np.zeros(nt, dtype=np.int64)
+    r2 = np.zeros(nt, dtype=np.int64)
+    for i in range(nt):                                                    # steps 16-18
+        tr, r1[i], r2[i], parts = geneig_trace(k_w[i], k_z[i], g_max, tau, rho, return_parts=True)
+        if nvt:
+            kcc = k_c[i] @ parts["c"]
+            tr += (np.trace(k_wt[i]) - np.sum(kcc * kcc)) / nvt
+        dos[i] = tr
+    return {"dos": dos, "r1": r1, "r2": r2, "mu": mu, "nu": nu, "k_w": k_w, "k_z": k_z, "k_c": k_c,
+            "k_wt": k_wt}
 
 
 # ----------------------------------------------------------------------------

@@ -287,6 +287,89 @@ def test_ssm_beats_dgc_when_sampled_enough():
 
 
 # ----------------------------------------------------------------------------
+# Section 4: RESS-DGC
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("half,nt", [(0, 1), (1, 2), (5, 3), (40, 4)])
+def test_square_coefficients_product_identity(half, nt):
+    """Proposition 1 against the closed form from T_p T_q = (T_{p+q} + T_{|p-q|})/2:
+    nu_l = 1/2 sum_{p+q=l} mu_p mu_q + 1/2 sum_{|p-q|=l} mu_p mu_q, and the squared series
+    at points of [-1, 1]."""
+    rng = np.random.default_rng(half + 7)
+    mu = rng.standard_normal((half + 1, nt)) / (1.0 + np.arange(half + 1))[:, None]
+    degree = 2 * half
+    nu = O.square_coefficients(mu, degree)
+    ref = np.zeros((degree + 1, nt))
+    for p in range(half + 1):
+        for q in range(half + 1):
+            ref[p + q] += 0.5 * mu[p] * mu[q]
+            ref[abs(p - q)] += 0.5 * mu[p] * mu[q]
+    scale = np.abs(mu).sum(axis=0) ** 2
+    assert np.all(np.abs(nu - ref) <= 1e-14 * scale)
+    x = np.cos(rng.uniform(0, np.pi, 9))[:, None]
+    assert np.all(np.abs(O.chebyshev_eval(nu, x) - O.chebyshev_eval(mu, x) ** 2) <= 1e-13 * scale)
+
+
+def _ress_case(nx=14, nv=16, degree=200, nt=30, sigma_hat=0.05, seed=3):
+    rng = np.random.default_rng(seed)
+    a = WL.laplacian_2d_dirichlet(nx, rng.uniform(-1, 1, nx * nx))
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    t = 0.5 * (lo + hi) + hw * WL.midpoint_grid(nt)
+    return a, lo, hi, sigma_hat * hw, t, WL.gaussian_block(a.n, nv, seed=seed), degree
+
+
+def test_ress_equals_ss_dgc_at_half_degree():
+    """Theorem 4 with N~_v = 0: K_W = W^* Z and K_Z = Z^* Z for Z = g^{M/2}(tI - A) W,
+    so RESS-DGC at degree M is SS-DGC at degree M/2 with the same (truncated) mu.
+    In the bulk (above 1e-2 of the maximum) the two agree to rounding.  Towards the
+    spectrum's edges both carry rounding noise of different origin (K_Z as a sum of
+    moments that cancel, against Z^* Z of a noisy Z), amplified by Algorithm 4's
+    S~^{-1/2}, and agree only to that level."""
+    a, lo, hi, sigma, t, w, m = _ress_case()
+    ress = O.ress_dgc(a, w, None, t, m, sigma, lo, hi)
+    ss = O.ss_dgc(a, w, t, m // 2, sigma, lo, hi, mu=ress["mu"][: m // 2 + 1], keep=True)
+    top = ss["dos"].max()
+    resolved = ss["dos"] > 1e-4 * top
+    assert resolved.sum() >= 20
+    diff = np.abs(ress["dos"] - ss["dos"])
+    assert diff[ss["dos"] > 0.5 * top].max() <= 1e-13 * top
+    assert diff[ss["dos"] > 1e-2 * top].max() <= 1e-8 * top
+    assert diff[resolved].max() <= 1e-7 * top
+    assert np.abs(ress["dos"] - ss["dos"]).max() <= 1e-4 * top
+    assert np.array_equal(ress["r1"][resolved], ss["r1"][resolved])
+    kz = ss["k_z"]
+    assert np.abs(ress["k_z"] - kz).max() <= 1e-11 * np.abs(kz).max()
+
+
+def test_ress_hybrid_identity_probe_gives_exact_trace():
+    """Algorithm 6 with W~ = sqrt(N) I_N (no Hutchinson variance): the correction is
+    Tr g^{M/2}(tI - A) - Tr Xi~ exactly, so the estimate is the exact regularised DOS up
+    to the degree-M/2 truncation, whatever W (here N_v = 8, far below the rank).  At the
+    spectrum's edges Tr Xi~ carries the rounding noise of the moment form of K_Z."""
+    a, lo, hi, sigma, t, w, m = _ress_case(nv=8, degree=400, nt=25, sigma_hat=0.05)
+    probe = np.sqrt(a.n) * np.eye(a.n)
+    out = O.ress_dgc(a, w, probe, t, m, sigma, lo, hi)
+    ref = O.exact_dos(np.linalg.eigvalsh(a.to_dense()), t, sigma)
+    resolved = ref > 1e-4 * ref.max()
+    assert resolved.sum() >= 20
+    assert np.abs(out["dos"] - ref)[resolved].max() < 1e-8 * ref.max()
+    assert np.abs(out["dos"] - ref).max() < 1e-4 * ref.max()
+    plain = O.ress_dgc(a, w, None, t, m, sigma, lo, hi)["dos"]
+    assert np.abs(plain - ref).max() > 1e-2 * ref.max()  # N_v = 8 alone misses mass
+
+
+def test_ress_correction_vanishes_when_sampled_enough():
+    """With N_v above the numerical rank the low-rank part is exact (Theorem 3), so the
+    hybrid correction is at rounding level and both estimates agree."""
+    a, lo, hi, sigma, t, w, m = _ress_case(nv=150, degree=400, nt=12, sigma_hat=0.05)
+    wt = WL.gaussian_block(a.n, 8, seed=99)
+    with_c = O.ress_dgc(a, w, wt, t, m, sigma, lo, hi)["dos"]
+    plain = O.ress_dgc(a, w, None, t, m, sigma, lo, hi)["dos"]
+    resolved = plain > 1e-4 * plain.max()
+    assert np.abs(with_c - plain)[resolved].max() <= 1e-6 * plain.max()
+
+
+# ----------------------------------------------------------------------------
 # Algorithm 8
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["x", "x2", "exp"])
