@@ -61,6 +61,16 @@ typedef enum ssm_precision {
                               lo.hi on BF16 MFMA, FP32 accumulation (CSR values float) */
 } ssm_precision;
 
+/* Estimator run by ssm_dos. */
+typedef enum ssm_method {
+  SSM_SS_DGC = 0,          /* Algorithm 5: every Z(t_i) = g^M(t_i I - A~) W formed, K_W = W^T Z,
+                              K_Z = Z^T Z */
+  SSM_RESS_DGC = 1         /* Algorithm 7 (Theorem 4): no Z; the moments X_l = V^T T_l(A~) V of
+                              V = [W W~] give K_W = sum_{l<=M/2} mu_l X_l and K_Z = sum_{l<=M}
+                              nu_l X_l (nu of Proposition 1), plus the hybrid correction of
+                              Algorithm 6 from the N~_v columns of W~ when nv_hybrid > 0 */
+} ssm_method;
+
 /* Sparse real symmetric matrix in CSR form, all arrays on the device and
  * borrowed for the lifetime of the context (or of the stage call). */
 typedef struct ssm_csr {
@@ -88,7 +98,13 @@ typedef struct ssm_params {
                               Y_{js}) (Y_k = T_k(A~)W, 1 <= j <= M/s) and the ring keeps >= s
                               blocks, so that the backward recomputes the rest segment by segment */
   int32_t dgc;             /* nonzero: ssm_dos also forms the DGC estimate of Algorithm 2 from the
-                              same recurrence (same W, M and sweep points); read it with ssm_dgc */
+                              same recurrence (same W, M and sweep points); read it with ssm_dgc
+                              (SSM_SS_DGC only) */
+  int32_t method;          /* an ssm_method (0 = SSM_SS_DGC).  SSM_RESS_DGC needs an even M,
+                              SSM_FP64 (else SSM_ERR_UNSUPPORTED), ckpt_every = 0 and dgc = 0 */
+  int32_t nv_hybrid;       /* N~_v of Algorithm 7: 0, or a multiple of 4 with nv + nv_hybrid <= 256
+                              (SSM_RESS_DGC only; 0 for SSM_SS_DGC).  The block W of ssm_create
+                              then has nv + nv_hybrid columns: W, then W~ */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)
@@ -137,6 +153,14 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
  * W^T Z kept by the tau test) then r2 (generalised eigenvalues kept by the
  * range test).  Synchronises the stream. */
 ssm_status ssm_dos(ssm_ctx* ctx, double* dos_host, int32_t* ranks_host);
+/* With method = SSM_RESS_DGC, ssm_dos returns the RESS-DGC estimate of Algorithm 7:
+ *   phi~(t_i) = Tr Xi~(t_i) + (Tr K_W~(t_i) - ||K_C(t_i) C~(t_i)||_F^2) / N~_v,
+ * the second term only when nv_hybrid = N~_v > 0, with K_C = W~^T g^{M/2} W and
+ * K_W~ = W~^T g^{M/2} W~ (Theorem 4).  The recurrence runs on V = [W W~] to degree
+ * M/2 + 1 only: for symmetric A~, T_s^2 = (T_{2s} + T_0)/2 and T_{s+1} T_s =
+ * (T_{2s+1} + T_1)/2 turn the Gram matrices of consecutive blocks into every moment
+ * X_l, l <= M (FP64 throughout).  ranks_host as for Algorithm 5 (r1, r2 of the
+ * N_v x N_v pencil).  The bound check uses ||T_{M/2+1}(A~)V||_F. */
 
 /* Sum_i w[i] * dos[i] over the DOS of the last ssm_dos (Algorithm 8, step 4).
  * SSM_ERR_STATE before the first ssm_dos. */
@@ -164,6 +188,10 @@ ssm_status ssm_get_stats(const ssm_ctx* ctx, ssm_stats* out);
 typedef struct ssm_views {
   void* w; void* y; void* z; double* k_w; double* k_z; double* coeff;
   int32_t chunk; int32_t batch; int32_t first_point_of_last_batch; int32_t elem_bytes;
+  double* moments;   /* SSM_RESS_DGC: X_l = V^T T_l(A~) V, l = 0..M, N_v'^2 doubles each
+                        (N_v' = nv + nv_hybrid); NULL otherwise.  z is NULL and chunk
+                        counts the ring's slots. */
+  double* coeff_sq;  /* SSM_RESS_DGC: nu_l(t_i) of Proposition 1, same layout as coeff */
 } ssm_views;
 ssm_status ssm_get_views(const ssm_ctx* ctx, ssm_views* out);
 

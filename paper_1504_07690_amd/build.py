@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libssm.so")
 
 SOURCES = ["coeffs.hip", "philox.hip", "cheb_spmm.hip", "reduce.hip", "sweep_gemm.hip", "gram.hip",
-           "geneig.hip", "adjoint.hip", "ssm_api.cpp"]
+           "geneig.hip", "adjoint.hip", "ress.hip", "ssm_api.cpp"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU forms are kept out of the generated code; hipcc's host pass

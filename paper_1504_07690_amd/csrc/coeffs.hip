@@ -47,7 +47,43 @@ __global__ void __launch_bounds__(256) dgc_coefficients_kernel(double c0, double
   }
 }
 
+// Proposition 1: nu_l(t_i), l = 0..2h, of the square of sum_{k<=h} mu_k(t_i) T_k.  With
+// T_p T_q = (T_{p+q} + T_{|p-q|}) / 2 over ordered pairs (p, q),
+//   nu_l = 1/2 sum_{p+q=l} mu_p mu_q + 1/2 sum_{|p-q|=l} mu_p mu_q,
+// the second sum being sum_p mu_p^2 for l = 0 and 2 sum_p mu_p mu_{p+l} otherwise: the
+// exact coefficients (the quadrature the proposition names gives the same numbers for
+// N_theta > 2h).  One lane per (l, column); columns nt..ldn-1 are written as 0.
+__global__ void __launch_bounds__(256) square_coefficients_kernel(const double* __restrict__ mu, int64_t ldc,
+                                                                  int nt, int h, int64_t ldn,
+                                                                  double* __restrict__ nu) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m1 = 2 * h + 1;
+  if (idx >= (int64_t)m1 * ldn) return;
+  const int l = (int)(idx / ldn);
+  const int i = (int)(idx - (int64_t)l * ldn);
+  if (i >= nt) {
+    nu[idx] = 0.0;
+    return;
+  }
+  double conv = 0.0;  // p + q = l
+  const int p_lo = l > h ? l - h : 0;
+  const int p_hi = l < h ? l : h;
+  for (int p = p_lo; p <= p_hi; ++p) conv += mu[(int64_t)p * ldc + i] * mu[(int64_t)(l - p) * ldc + i];
+  double diff = 0.0;  // |p - q| = l
+  for (int p = 0; p + l <= h; ++p) diff += mu[(int64_t)p * ldc + i] * mu[(int64_t)(p + l) * ldc + i];
+  if (l > 0) diff *= 2.0;
+  nu[idx] = 0.5 * (conv + diff);
+}
+
 }  // namespace
+
+hipError_t launch_square_coefficients(const double* mu, int64_t ldc, int nt, int h, double* nu, int64_t ldn,
+                                      hipStream_t stream) {
+  const int64_t total = (int64_t)(2 * h + 1) * ldn;
+  hipLaunchKernelGGL(square_coefficients_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, mu, ldc,
+                     nt, h, ldn, nu);
+  return hipGetLastError();
+}
 
 size_t coefficient_lds_bytes(int n_theta) { return 2 * (size_t)(n_theta + 1) * sizeof(double); }
 

@@ -150,11 +150,18 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
   }
 }
 
+// With nvh > 0 (Algorithm 6 / 7 with N~_v = nvh columns of W~) the point also gets the
+// hybrid correction (Tr K_W~ - ||K_C C~||_F^2) / N~_v, C~ = U~ S~^-1/2 Q~ with Q~ the
+// eigenvectors of step 3 that pass step 4: G = K_C U~ S~^-1/2 (N~_v x r1, in hscr) is
+// formed before V is reused for Q, then ||G Q~||_F^2 in a fixed order.
 __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const double* __restrict__ k_w,
                                                                   const double* __restrict__ k_z, double g_max,
                                                                   double tau, double rho, double* __restrict__ dos,
                                                                   int32_t* __restrict__ ranks, int ntb,
-                                                                  double* __restrict__ scratch) {
+                                                                  double* __restrict__ scratch, int nvh,
+                                                                  const double* __restrict__ k_c,
+                                                                  const double* __restrict__ trw,
+                                                                  double* __restrict__ hscr) {
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
@@ -199,13 +206,24 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   const int r1 = sh.misc[0];
   if (r1 == 0) {
     if (tid == 0) {
-      dos[i] = 0.0;
+      dos[i] = nvh ? trw[i] / nvh : 0.0;  // C~ is empty: only Tr K_W~ / N~_v remains
       if (ranks) {
         ranks[i] = 0;
         ranks[ntb + i] = 0;
       }
     }
     return;
+  }
+  double* g = nvh ? hscr + (int64_t)i * nvh * nv : nullptr;
+  if (nvh) {  // G = K_C U~ S~^-1/2  (N~_v x r1, row stride r1)
+    const double* kci = k_c + (int64_t)i * nvh * nv;
+    for (int idx = tid; idx < nvh * r1; idx += GE_THREADS) {
+      const int a = idx / r1, b = idx - a * r1;
+      const int kb = sh.kidx[b];
+      double acc = 0.0;
+      for (int c = 0; c < n; ++c) acc += kci[(int64_t)a * n + c] * sh.V[c * ld + kb];
+      g[idx] = acc * sh.scale[b];
+    }
   }
 
   // 3a. T = (Z^T Z) U~ S~^-1/2   (n x r1, global scratch, row stride r1)
@@ -236,26 +254,53 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
     }
   }
   __syncthreads();
-  jacobi(sh, nullptr, r1, ld);
+  if (nvh) {  // eigenvectors Q of B are needed: V (U no longer) starts as the identity
+    for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+      const int a = idx / r1, b = idx - a * r1;
+      sh.V[a * ld + b] = (a == b) ? 1.0 : 0.0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    jacobi(sh, sh.V, r1, ld);
+  } else {
+    jacobi(sh, nullptr, r1, ld);
+  }
 
-  // 4. range filter and trace (fixed order)
+  // 4. range filter and trace (fixed order); kidx now flags the eigenvectors kept
   if (tid == 0) {
     const double hi = (1.0 + rho) * g_max;
     double tr = 0.0;
     int r2 = 0;
     for (int j = 0; j < r1; ++j) {
       const double xi = sh.A[j * ld + j];
-      if (xi >= 0.0 && xi <= hi) {
+      const bool in = xi >= 0.0 && xi <= hi;
+      sh.kidx[j] = in ? 1 : 0;
+      if (in) {
         tr += xi;
         ++r2;
       }
     }
-    dos[i] = tr;
+    sh.s[0] = tr;
     if (ranks) {
       ranks[i] = r1;
       ranks[ntb + i] = r2;
     }
   }
+  __syncthreads();
+  double corr = 0.0;
+  if (nvh) {  // ||G Q~||_F^2
+    double part = 0.0;
+    for (int idx = tid; idx < nvh * r1; idx += GE_THREADS) {
+      const int a = idx / r1, j = idx - a * r1;
+      if (!sh.kidx[j]) continue;
+      double h = 0.0;
+      for (int b = 0; b < r1; ++b) h += g[(int64_t)a * r1 + b] * sh.V[b * ld + j];
+      part += h * h;
+    }
+    const double hs = block_sum(part, sh.red);
+    corr = (trw[i] - hs) / nvh;
+  }
+  if (tid == 0) dos[i] = sh.s[0] + corr;
 }
 
 // Backward of Algorithm 4 for one sweep point, truncation sets frozen (the
@@ -455,14 +500,16 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
 }
 
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
-                               double rho, double* dos, int32_t* ranks, double* scratch, hipStream_t stream) {
+                               double rho, double* dos, int32_t* ranks, double* scratch, hipStream_t stream,
+                               int nvh, const double* k_c, const double* trw, double* hscr) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
+  if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
   const size_t lds = geneig_lds_bytes(nv);
   hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_trace_kernel, dim3(ntb), dim3(GE_THREADS), lds, stream, nv, k_w, k_z, g_max, tau, rho,
-                     dos, ranks, ntb, scratch);
+                     dos, ranks, ntb, scratch, nvh, k_c, trw, hscr);
   return hipGetLastError();
 }
 

@@ -66,8 +66,8 @@ __device__ __forceinline__ void gram_load(GramStep<T, In>& st, __amdgpu_buffer_r
 
 template <int T, typename In>
 __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, const In* __restrict__ w,
-                                                   const In* __restrict__ z, int64_t rows_per_seg,
-                                                   double* __restrict__ part) {
+                                                   int64_t w_stride, const In* __restrict__ z, int64_t z_stride,
+                                                   int64_t rows_per_seg, double* __restrict__ part) {
   using G = GramTiles<T>;
   const int i = blockIdx.x;
   const int seg = blockIdx.y;
@@ -80,12 +80,13 @@ __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, c
   q = (q + 3) / 4 * 4;
   const int64_t r_begin = s_begin + wave * q;
   const int64_t r_end = (r_begin + q < s_end) ? r_begin + q : s_end;
-  const In* zi = z + (int64_t)i * n * nv;
+  const In* zi = z + (int64_t)i * z_stride;
+  const In* wi = w + (int64_t)i * w_stride;
   const int rows = (int)((r_end > r_begin) ? r_end - r_begin : 0);
   const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(zi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
   const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(w + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+      (void*)(wi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
   int lane_off[T];
 #pragma unroll
   for (int a = 0; a < T; ++a) lane_off[a] = ((lane >> 4) * nv + 16 * a + (lane & 15)) * (int)sizeof(In);
@@ -195,7 +196,8 @@ __device__ __forceinline__ void gram_tile_load(GramTileStep<In>& st, __amdgpu_bu
 
 template <typename In>
 __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int ntb, const In* __restrict__ w,
-                                                         const In* __restrict__ z, int64_t rows_per_seg, int ntile,
+                                                         int64_t w_stride, const In* __restrict__ z,
+                                                         int64_t z_stride, int64_t rows_per_seg, int ntile,
                                                          double* __restrict__ part) {
   const int i = blockIdx.x;
   const int seg = blockIdx.y;
@@ -214,12 +216,13 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
   q = (q + 3) / 4 * 4;
   const int64_t r_begin = s_begin + wave * q;
   const int64_t r_end = (r_begin + q < s_end) ? r_begin + q : s_end;
-  const In* zi = z + (int64_t)i * n * nv;
+  const In* zi = z + (int64_t)i * z_stride;
+  const In* wi = w + (int64_t)i * w_stride;
   const int rows = (int)((r_end > r_begin) ? r_end - r_begin : 0);
   const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(zi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
   const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(w + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
+      (void*)(wi + (r_end > r_begin ? r_begin : 0) * nv), (short)0, rows * nv * (int)sizeof(In), kBufferWord3);
   int off_a[GT_B], off_b[GT_B];
 #pragma unroll
   for (int a = 0; a < GT_B; ++a) {
@@ -322,15 +325,52 @@ int64_t rows_per_segment(int64_t n, int nseg) {
 }
 
 template <int T>
-hipError_t launch_t(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, int64_t rps, int segs,
-                    double* scratch, hipStream_t stream) {
+hipError_t launch_t(int is_f32, int64_t n, int nv, int ntb, const void* w, int64_t ws, const void* z, int64_t zs,
+                    int64_t rps, int segs, double* scratch, hipStream_t stream) {
   dim3 grid(ntb, segs);
   if (is_f32)
-    hipLaunchKernelGGL((gram_kernel<T, float>), grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb, (const float*)w,
-                       (const float*)z, rps, scratch);
+    hipLaunchKernelGGL((gram_kernel<T, float>), grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb, (const float*)w, ws,
+                       (const float*)z, zs, rps, scratch);
   else
     hipLaunchKernelGGL((gram_kernel<T, double>), grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
-                       (const double*)w, (const double*)z, rps, scratch);
+                       (const double*)w, ws, (const double*)z, zs, rps, scratch);
+  return hipGetLastError();
+}
+
+// Point i reads W at w + i * ws and Z at z + i * zs (elements).
+hipError_t launch_strided(int is_f32, int64_t n, int nv, int ntb, const void* w, int64_t ws, const void* z,
+                          int64_t zs, double* k_w, double* k_z, int nseg, double* scratch, hipStream_t stream) {
+  // the number of segments actually used can drop when rows are rounded up
+  const int64_t rps = rows_per_segment(n, nseg);
+  const int segs = (int)((n + rps - 1) / rps);
+  const int t = (nv + 15) / 16;
+  // a wave's rows (plus the 8-row prefetch overrun) must be addressable by 32-bit byte offsets
+  if ((rps / GR_WAVES + 16) * (int64_t)nv * (is_f32 ? 4 : 8) >= (int64_t)1 << 31) return hipErrorInvalidValue;
+  hipError_t err;
+  switch (t) {
+    case 1: err = launch_t<1>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    case 2: err = launch_t<2>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    case 3: err = launch_t<3>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    case 4: err = launch_t<4>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    case 5: err = launch_t<5>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    case 6: err = launch_t<6>(is_f32, n, nv, ntb, w, ws, z, zs, rps, segs, scratch, stream); break;
+    default: {
+      if (t > 16) return hipErrorInvalidValue;
+      const int ntile = (t + GT_B - 1) / GT_B;
+      dim3 grid(ntb, segs, ntile * (ntile + 1) / 2);
+      if (is_f32)
+        hipLaunchKernelGGL(gram_tiled_kernel<float>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
+                           (const float*)w, ws, (const float*)z, zs, rps, ntile, scratch);
+      else
+        hipLaunchKernelGGL(gram_tiled_kernel<double>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
+                           (const double*)w, ws, (const double*)z, zs, rps, ntile, scratch);
+      err = hipGetLastError();
+    }
+  }
+  if (err != hipSuccess) return err;
+  const int64_t total = (int64_t)ntb * nv * nv;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, nv, ntb,
+                     segs * GR_WAVES, scratch, k_w, k_z);
   return hipGetLastError();
 }
 
@@ -340,38 +380,13 @@ int gram_scratch_slots(int nseg) { return nseg * GR_WAVES; }
 
 hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, double* k_w,
                        double* k_z, int nseg, double* scratch, hipStream_t stream) {
-  // the number of segments actually used can drop when rows are rounded up
-  const int64_t rps = rows_per_segment(n, nseg);
-  const int segs = (int)((n + rps - 1) / rps);
-  const int t = (nv + 15) / 16;
-  // a wave's rows (plus the 8-row prefetch overrun) must be addressable by 32-bit byte offsets
-  if ((rps / GR_WAVES + 16) * (int64_t)nv * (is_f32 ? 4 : 8) >= (int64_t)1 << 31) return hipErrorInvalidValue;
-  hipError_t err;
-  switch (t) {
-    case 1: err = launch_t<1>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    case 2: err = launch_t<2>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    case 3: err = launch_t<3>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    case 4: err = launch_t<4>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    case 5: err = launch_t<5>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    case 6: err = launch_t<6>(is_f32, n, nv, ntb, w, z, rps, segs, scratch, stream); break;
-    default: {
-      if (t > 16) return hipErrorInvalidValue;
-      const int ntile = (t + GT_B - 1) / GT_B;
-      dim3 grid(ntb, segs, ntile * (ntile + 1) / 2);
-      if (is_f32)
-        hipLaunchKernelGGL(gram_tiled_kernel<float>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
-                           (const float*)w, (const float*)z, rps, ntile, scratch);
-      else
-        hipLaunchKernelGGL(gram_tiled_kernel<double>, grid, dim3(64 * GR_WAVES), 0, stream, n, nv, ntb,
-                           (const double*)w, (const double*)z, rps, ntile, scratch);
-      err = hipGetLastError();
-    }
-  }
-  if (err != hipSuccess) return err;
-  const int64_t total = (int64_t)ntb * nv * nv;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, nv, ntb,
-                     segs * GR_WAVES, scratch, k_w, k_z);
-  return hipGetLastError();
+  return launch_strided(is_f32, n, nv, ntb, w, 0, z, n * nv, k_w, k_z, nseg, scratch, stream);
+}
+
+hipError_t launch_gram_pairs(int is_f32, int64_t n, int nv, int npairs, const void* y_hi, const void* y_lo,
+                             int64_t stride, double* k_w, double* k_z, int nseg, double* scratch,
+                             hipStream_t stream) {
+  return launch_strided(is_f32, n, nv, npairs, y_hi, stride, y_lo, stride, k_w, k_z, nseg, scratch, stream);
 }
 
 }  // namespace ssm

@@ -76,6 +76,20 @@ ssm_status check_params(const ssm_params* p) {
   if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16X3)
     return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
   if (p->ckpt_every != 0 && p->ckpt_every < 4) return fail(SSM_ERR_ARG, "ckpt_every must be 0 or >= 4");
+  if (p->method != SSM_SS_DGC && p->method != SSM_RESS_DGC) return fail(SSM_ERR_ARG, "unknown method %d", p->method);
+  if (p->method == SSM_SS_DGC) {
+    if (p->nv_hybrid != 0) return fail(SSM_ERR_ARG, "nv_hybrid applies to SSM_RESS_DGC only");
+  } else {
+    if (p->degree % 2) return fail(SSM_ERR_ARG, "RESS-DGC needs an even degree (Proposition 1), got %d", p->degree);
+    if (p->nv_hybrid < 0 || p->nv_hybrid % 4)
+      return fail(SSM_ERR_ARG, "nv_hybrid must be 0 or a positive multiple of 4 (got %d)", p->nv_hybrid);
+    if (p->nv + p->nv_hybrid > kMaxNv)
+      return fail(SSM_ERR_UNSUPPORTED, "nv + nv_hybrid > %d is not implemented in this build", kMaxNv);
+    if (p->precision != SSM_FP64)
+      return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC runs in FP64 only in this build (precision SSM_FP64)");
+    if (p->ckpt_every) return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC has no adjoint in this build (ckpt_every must be 0)");
+    if (p->dgc) return fail(SSM_ERR_UNSUPPORTED, "the DGC by-product is built for SSM_SS_DGC only");
+  }
   return SSM_OK;
 }
 
@@ -90,6 +104,10 @@ struct Plan {
          off_gpart = 0, off_escr = 0, off_dos = 0, off_ranks = 0, off_norm = 0, off_ckpt = 0, off_dpart = 0,
          off_dsums = 0, off_dgc = 0, total = 0;
   int dgc_group = 0;  // recurrence steps whose inner-product partials are held at once (0: no DGC)
+  // RESS-DGC: chunk = new blocks per round, ring of chunk + 1 slots
+  bool ress = false;
+  size_t off_nu = 0, off_kc = 0, off_trw = 0, off_hscr = 0, off_pw = 0, off_pz = 0, off_x = 0, off_kmu = 0,
+         off_knu = 0;
 };
 
 // Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
@@ -169,9 +187,67 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.total = o;
 }
 
+// RESS-DGC: blocks Y_0..Y_S of V = [W W~] (S = M/2 + 1) in a ring of chunk + 1 slots,
+// the pair Gram matrices of s = 0..S-1, the moments X_0..X_M, K_mu and K_nu per point.
+void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
+  const int nvp = p->nv + p->nv_hybrid;
+  const size_t e = (size_t)a->n * nvp;
+  const size_t nn = (size_t)p->nv * p->nv;
+  const size_t nnp = (size_t)nvp * nvp;
+  const int m1 = p->degree + 1;
+  const int S = p->degree / 2 + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  pl.off_t = take(p->nt * 8);
+  pl.off_c64 = take((size_t)m1 * pl.ldc * 8);
+  pl.off_nu = take((size_t)m1 * pl.ldc * 8);
+  pl.off_w = take(own_w ? e * 8 : 0);
+  pl.off_kw = take((size_t)p->nt * nn * 8);
+  pl.off_kz = take((size_t)p->nt * nn * 8);
+  pl.off_kc = take((size_t)p->nt * p->nv_hybrid * p->nv * 8);
+  pl.off_trw = take((size_t)p->nt * 8);
+  pl.off_hscr = take((size_t)p->nt * p->nv_hybrid * p->nv * 8);
+  pl.off_escr = take((size_t)p->nt * ssm::geneig_scratch_doubles(p->nv) * 8);
+  pl.off_dos = take(p->nt * 8);
+  pl.off_ranks = take(2 * (size_t)p->nt * 4);
+  pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
+  pl.off_pw = take((size_t)S * nnp * 8);
+  pl.off_pz = take((size_t)S * nnp * 8);
+  pl.off_x = take((size_t)m1 * nnp * 8);
+  pl.off_kmu = take((size_t)p->nt * nnp * 8);
+  pl.off_knu = take((size_t)p->nt * nnp * 8);
+  pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * std::max(pl.chunk, 1) * 2 * nnp * 8);
+  pl.off_y = take((size_t)(pl.chunk + 1) * e * 8);
+  pl.total = o;
+}
+
+ssm_status make_plan_ress(const ssm_csr* a, const ssm_params* p, bool own_w, size_t budget, Plan& out) {
+  const int S = p->degree / 2 + 1;
+  Plan pl;
+  pl.ress = true;
+  pl.passes = 1;
+  pl.batch = p->nt;
+  pl.ldc = (p->nt + 3) / 4 * 4;
+  for (int chunk = S; chunk >= 2; --chunk) {  // the ring keeps Y_{k-1}, Y_{k-2} and a round's first pair
+    pl.chunk = chunk;
+    pl.nseg = gram_segments(a->n, chunk);
+    layout_ress(pl, a, p, own_w);
+    if (!budget || pl.total <= budget) {
+      out = pl;
+      return SSM_OK;
+    }
+  }
+  return fail(SSM_ERR_WORKSPACE, "no RESS-DGC plan fits in %zu bytes of workspace", budget);
+}
+
 // Minimise modelled bytes: recurrence replays (one per pass) against read-modify-write
 // of the Z batch for every extra chunk.
 ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t budget, Plan& out) {
+  if (p->method == SSM_RESS_DGC) return make_plan_ress(a, p, own_w, budget, out);
   const size_t es = elem_bytes(p->precision);
   const double e = (double)a->n * p->nv;
   const double spmm_bytes = 3.0 * e * es + (double)a->nnz * (4.0 + es);
@@ -250,6 +326,16 @@ struct ssm_ctx {
   double* dpart = nullptr;  // DGC: workgroup partials of a group of steps
   double* dsums = nullptr;  // DGC: <Y_s, Y_s>, <Y_{s+1}, Y_s> per step
   double* dgc = nullptr;    // DGC: nt estimates, then M+1 moments
+  // RESS-DGC
+  double* nu = nullptr;     // (M+1) x ldc coefficients of the squared series
+  double* kc = nullptr;     // nt x N~_v x N_v
+  double* trw = nullptr;    // nt traces of K_W~
+  double* hscr = nullptr;   // Algorithm 6 scratch
+  double* pw = nullptr;     // S pair matrices (Y_{s+1}^T Y_s + Y_s^T Y_{s+1})/2
+  double* pz = nullptr;     // S pair matrices Y_s^T Y_s
+  double* xm = nullptr;     // moments X_0..X_M
+  double* kmu = nullptr;    // nt x N_v'^2
+  double* knu = nullptr;    // nt x N_v'^2
   std::vector<double> dos_host;
   bool have_dos = false;
   bool have_dgc = false;
@@ -334,6 +420,18 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
     c->dsums = (double*)(c->ws + pl.off_dsums);
     c->dgc = (double*)(c->ws + pl.off_dgc);
   }
+  if (pl.ress) {
+    c->z = nullptr;
+    c->nu = (double*)(c->ws + pl.off_nu);
+    c->kc = (double*)(c->ws + pl.off_kc);
+    c->trw = (double*)(c->ws + pl.off_trw);
+    c->hscr = (double*)(c->ws + pl.off_hscr);
+    c->pw = (double*)(c->ws + pl.off_pw);
+    c->pz = (double*)(c->ws + pl.off_pz);
+    c->xm = (double*)(c->ws + pl.off_x);
+    c->kmu = (double*)(c->ws + pl.off_kmu);
+    c->knu = (double*)(c->ws + pl.off_knu);
+  }
   c->dos_host.assign(p->nt, 0.0);
 
   auto bail = [&](ssm_status st) {
@@ -366,8 +464,12 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
       return bail(hip_fail(e, "copy of the coefficient table"));
     c->k3 = three_product_degrees(table, m1, pl.ldc, p->nt);
   }
-  if (own_w) {
-    if ((e = ssm::launch_gaussian_block(p->seed, a->n, p->nv, p->precision == SSM_FP64 ? 0 : 1, c->w,
+  if (pl.ress &&
+      (e = ssm::launch_square_coefficients(c->c64, pl.ldc, p->nt, p->degree / 2, c->nu, pl.ldc, c->stream)) !=
+          hipSuccess)
+    return bail(hip_fail(e, "squared-series coefficient kernel"));
+  if (own_w) {  // RESS-DGC: one block [W W~] of nv + nv_hybrid columns
+    if ((e = ssm::launch_gaussian_block(p->seed, a->n, p->nv + p->nv_hybrid, p->precision == SSM_FP64 ? 0 : 1, c->w,
                                         c->stream)) != hipSuccess)
       return bail(hip_fail(e, "W generator"));
   }
@@ -377,6 +479,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->stats.batch = pl.batch;
   c->stats.gram_segments = pl.nseg;
   c->stats.split_k3 = c->k3;
+  if (pl.ress) c->stats.chunk = pl.chunk + 1;  // ring slots
   *out = c;
   return SSM_OK;
 }
@@ -388,8 +491,13 @@ ssm_status ssm_destroy(ssm_ctx* c) {
   return SSM_OK;
 }
 
+namespace {
+ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host);
+}
+
 ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (!c || !dos_host) return fail(SSM_ERR_ARG, "ctx and dos_host must be non-NULL");
+  if (c->pl.ress) return ress_dos(c, dos_host, ranks_host);
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
   const int64_t n = c->a.n;
@@ -558,6 +666,143 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 }
 
 // ---------------------------------------------------------------------------
+// RESS-DGC driver (Algorithm 7, Theorem 4)
+// ---------------------------------------------------------------------------
+namespace {
+
+ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
+  const ssm_params& p = c->p;
+  const Plan& pl = c->pl;
+  const int64_t n = c->a.n;
+  const int nv = p.nv, nvh = p.nv_hybrid, nvp = nv + nvh;
+  const int64_t e = n * nvp;
+  const int64_t nnp = (int64_t)nvp * nvp;
+  const int m = p.degree, m1 = m + 1;
+  const int S = m / 2 + 1;          // pairs (Y_s, Y_{s+1}), s = 0..M/2
+  const int R = pl.chunk + 1;       // ring slots
+  const double alpha = 2.0 / (p.hi - p.lo);
+  const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
+  hipStream_t st = c->stream;
+  const int rounds = (S + pl.chunk - 1) / pl.chunk;
+  const size_t need = 4 * (size_t)rounds + 8;
+  while (c->events.size() < need) {
+    hipEvent_t ev;
+    SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
+    c->events.push_back(ev);
+  }
+  size_t evi = 0;
+  struct Span { size_t b, en; int kind; };  // 0 rec, 1 moments + per-point sums, 2 pair Gram, 3 eig
+  std::vector<Span> spans;
+  auto mark = [&]() -> size_t { return evi++; };
+  auto rec = [&](size_t ev) { return hipEventRecord(c->events[ev], st); };
+  const size_t ev_start = mark();
+  SSM_HIP(rec(ev_start), "hipEventRecord");
+  auto slot = [&](int k) -> double* { return (double*)c->y + (size_t)(k % R) * e; };
+  int64_t spmm_launches = 0;
+  hipError_t err = hipMemcpyAsync(slot(0), c->w, e * 8, hipMemcpyDeviceToDevice, st);
+  if (err != hipSuccess) return hip_fail(err, "copy of W");
+  int k = 0;       // last block formed
+  int s_done = 0;  // next pair to form
+  while (s_done < S) {
+    // a round forms Y_{k+1}..Y_{k_last}; the ring (chunk + 1 slots) still holds Y_{s_done}
+    const int k_last = std::min(S, s_done + pl.chunk);
+    Span rs{mark(), 0, 0};
+    SSM_HIP(rec(rs.b), "hipEventRecord");
+    for (int kk = k + 1; kk <= k_last; ++kk) {
+      const double* x = slot(kk - 1);
+      const double* xp = kk == 1 ? nullptr : slot(kk - 2);
+      err = ssm::launch_cheb_step_f64(n, nvp, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values,
+                                      kk == 1 ? alpha : 2.0 * alpha, kk == 1 ? beta : 2.0 * beta,
+                                      kk == 1 ? 0.0 : -1.0, x, xp, nullptr, slot(kk), st);
+      if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
+      ++spmm_launches;
+    }
+    k = k_last;
+    rs.en = mark();
+    SSM_HIP(rec(rs.en), "hipEventRecord");
+    spans.push_back(rs);
+    // pairs s_done..k_last-1, in runs whose two slots do not wrap
+    Span gs{rs.en, 0, 2};
+    for (int a = s_done; a < k_last;) {
+      const int sa = a % R;
+      const int len = sa == R - 1 ? 1 : std::min(k_last - a, R - 1 - sa);
+      const double* lo_blk = (const double*)c->y + (size_t)sa * e;
+      const double* hi_blk = sa == R - 1 ? (const double*)c->y : lo_blk + e;
+      err = ssm::launch_gram_pairs(0, n, nvp, len, hi_blk, lo_blk, e, c->pw + (int64_t)a * nnp,
+                                   c->pz + (int64_t)a * nnp, pl.nseg, c->gpart, st);
+      if (err != hipSuccess) return hip_fail(err, "pair Gram kernel");
+      a += len;
+    }
+    gs.en = mark();
+    SSM_HIP(rec(gs.en), "hipEventRecord");
+    spans.push_back(gs);
+    s_done = k_last;
+  }
+  // bound check inputs: ||V||_F^2 and ||T_{M/2+1}(A~) V||_F^2
+  err = ssm::launch_sumsq(c->w, e, 0, c->norm + 8, c->norm + 0, st);
+  if (err == hipSuccess) err = ssm::launch_sumsq(slot(S), e, 0, c->norm + 8, c->norm + 1, st);
+  if (err != hipSuccess) return hip_fail(err, "norm kernel");
+  // moments and the per-point sums (FP64 sweep GEMM over X, blocks of N_v'^2 entries)
+  Span ms{mark(), 0, 1};
+  SSM_HIP(rec(ms.b), "hipEventRecord");
+  err = ssm::launch_ress_moments(nvp, m1, c->pw, c->pz, c->xm, st);
+  if (err == hipSuccess)
+    err = ssm::launch_sweep_f64(nnp, S, p.nt, c->c64, pl.ldc, pl.ldc, c->xm, c->kmu, 0, st);
+  if (err == hipSuccess)
+    err = ssm::launch_sweep_f64(nnp, m1, p.nt, c->nu, pl.ldc, pl.ldc, c->xm, c->knu, 0, st);
+  if (err == hipSuccess) err = ssm::launch_ress_extract(p.nt, nv, nvh, c->kmu, c->knu, c->kw, c->kz, c->kc, c->trw, st);
+  if (err != hipSuccess) return hip_fail(err, "moment kernels");
+  ms.en = mark();
+  SSM_HIP(rec(ms.en), "hipEventRecord");
+  spans.push_back(ms);
+  const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
+  Span es_{mark(), mark(), 3};
+  SSM_HIP(rec(es_.b), "hipEventRecord");
+  err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks, c->escr, st,
+                                 nvh, c->kc, c->trw, c->hscr);
+  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
+  SSM_HIP(rec(es_.en), "hipEventRecord");
+  spans.push_back(es_);
+
+  std::vector<double> dos(p.nt);
+  std::vector<int32_t> ranks(2 * (size_t)p.nt);
+  double norms[2];
+  SSM_HIP(hipMemcpyAsync(dos.data(), c->dos, sizeof(double) * p.nt, hipMemcpyDeviceToHost, st), "copy DOS");
+  SSM_HIP(hipMemcpyAsync(ranks.data(), c->ranks, sizeof(int32_t) * 2 * p.nt, hipMemcpyDeviceToHost, st), "copy ranks");
+  SSM_HIP(hipMemcpyAsync(norms, c->norm, sizeof(norms), hipMemcpyDeviceToHost, st), "copy norms");
+  SSM_HIP(hipStreamSynchronize(st), "ssm_dos sync");
+  ssm_stats& Sx = c->stats;
+  Sx.ms_recurrence = Sx.ms_sweep = Sx.ms_gram = Sx.ms_geneig = 0.0;
+  for (const Span& sp : spans) {
+    float ms_ = 0.f;
+    SSM_HIP(hipEventElapsedTime(&ms_, c->events[sp.b], c->events[sp.en]), "hipEventElapsedTime");
+    double* dst = sp.kind == 0 ? &Sx.ms_recurrence : sp.kind == 1 ? &Sx.ms_sweep : sp.kind == 2 ? &Sx.ms_gram
+                                                                                    : &Sx.ms_geneig;
+    *dst += ms_;
+  }
+  float tot = 0.f;
+  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[es_.en]), "hipEventElapsedTime");
+  Sx.ms_total = tot;
+  Sx.spmm_launches = spmm_launches;
+  Sx.sweep_launches = 2;
+  if (std::isnan(norms[0]) || std::isnan(norms[1]))
+    return fail(SSM_ERR_NONFINITE, "NaN in W or T_{M/2+1}(A~)W: non-finite values, or [lo, hi] far from spec(A)");
+  if (!std::isfinite(norms[0]) || !std::isfinite(norms[1]) || norms[1] > (1.0 + 1e-3) * (1.0 + 1e-3) * norms[0])
+    return fail(SSM_ERR_BOUNDS, "||T_{M/2+1}(A~)W||_F^2 = %g exceeds ||W||_F^2 = %g: spectrum not inside [lo, hi]",
+                norms[1], norms[0]);
+  for (int i = 0; i < p.nt; ++i)
+    if (!std::isfinite(dos[i])) return fail(SSM_ERR_NONFINITE, "DOS at point %d is not finite", i);
+  std::copy(dos.begin(), dos.end(), dos_host);
+  if (ranks_host) std::copy(ranks.begin(), ranks.end(), ranks_host);
+  c->dos_host = dos;
+  c->have_dos = true;
+  c->z_valid = false;
+  return SSM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Adjoint
 // ---------------------------------------------------------------------------
 namespace {
@@ -619,6 +864,7 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
   const int m = p.degree, m1 = m + 1;
+  if (pl.ress) return fail(SSM_ERR_UNSUPPORTED, "no adjoint for RESS-DGC in this build");
   if (pl.passes != 1 || (pl.chunk != m1 && !pl.ckpt))
     return fail(SSM_ERR_UNSUPPORTED,
                 "the adjoint needs a single-pass plan holding every T_k(A~)W, or one made with ckpt_every > 0");
@@ -818,6 +1064,9 @@ ssm_status ssm_get_views(const ssm_ctx* c, ssm_views* out) {
   out->batch = c->pl.batch;
   out->first_point_of_last_batch = c->last_batch_start;
   out->elem_bytes = (int32_t)elem_bytes(c->p.precision);
+  out->moments = c->xm;
+  out->coeff_sq = c->nu;
+  if (c->pl.ress) out->chunk = c->pl.chunk + 1;
   return SSM_OK;
 }
 

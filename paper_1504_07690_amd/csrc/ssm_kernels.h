@@ -10,6 +10,10 @@ namespace ssm {
 hipError_t launch_coefficients(double c0, double hw, double sigma, double inv_norm, const double* t, int nt,
                                int degree, int n_theta, double* c, float* c32, int64_t ldc, hipStream_t stream);
 size_t coefficient_lds_bytes(int n_theta);
+// Proposition 1: nu (2h+1 rows, row stride ldn, columns nt..ldn-1 zero) of the square of
+// sum_{k<=h} mu_k T_k, mu read as rows 0..h of c (row stride ldc).
+hipError_t launch_square_coefficients(const double* mu, int64_t ldc, int nt, int h, double* nu, int64_t ldn,
+                                      hipStream_t stream);
 
 // Philox4x32-10 + Box-Muller block (philox.hip).
 hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, void* w, hipStream_t stream);
@@ -87,6 +91,11 @@ hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m
 int gram_scratch_slots(int nseg);
 hipError_t launch_gram(int is_f32, int64_t n, int nv, int ntb, const void* w, const void* z, double* k_w,
                        double* k_z, int nseg, double* scratch, hipStream_t stream);
+// Pair mode: pair j takes W = y_hi + j*stride and Z = y_lo + j*stride (elements), so
+// k_w[j] = (y_hi_j^T y_lo_j + y_lo_j^T y_hi_j)/2 and k_z[j] = y_lo_j^T y_lo_j.
+hipError_t launch_gram_pairs(int is_f32, int64_t n, int nv, int npairs, const void* y_hi, const void* y_lo,
+                             int64_t stride, double* k_w, double* k_z, int nseg, double* scratch,
+                             hipStream_t stream);
 
 // Algorithm 4 + trace (geneig.hip).
 // Per-point FP64 scratch of launch_geneig_trace / launch_geneig_backward: the
@@ -99,9 +108,18 @@ __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
   const int64_t n = nv;
   return 3 * n * n + (nv > 96 ? 2 * n * (n + 1) : 0);
 }
+// nvh > 0 adds the hybrid correction of Algorithm 6 from k_c (ntb x nvh x nv), trw (ntb)
+// with hscr (ntb * nvh * nv doubles) as scratch.
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max,
                                double tau, double rho, double* dos, int32_t* ranks, double* scratch,
-                               hipStream_t stream);
+                               hipStream_t stream, int nvh = 0, const double* k_c = nullptr,
+                               const double* trw = nullptr, double* hscr = nullptr);
+// RESS-DGC (ress.hip): X_l, l < m1, of the N_v' = nvp block from the pair Gram matrices,
+// and the per-point split of K_mu, K_nu (nvp x nvp each) into K_W, K_Z (nv x nv), K_C
+// (nvh x nv) and Tr K_W~.
+hipError_t launch_ress_moments(int nvp, int m1, const double* pw, const double* pz, double* x, hipStream_t stream);
+hipError_t launch_ress_extract(int nt, int nv, int nvh, const double* kmu, const double* knu, double* kw, double* kz,
+                               double* kc, double* trw, hipStream_t stream);
 size_t geneig_lds_bytes(int nv);
 // Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z.
 // scratch: 3 * ntb * nv * nv doubles.

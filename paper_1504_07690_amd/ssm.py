@@ -49,26 +49,33 @@ class DeviceCSR:
                          self.values.data_ptr())
 
 
-def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0, dgc=False) -> A.ssm_params:
+METHOD = {"ss": 0, "ress": 1}
+
+
+def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0, dgc=False, method="ss",
+            nv_hybrid=0) -> A.ssm_params:
     return A.ssm_params(float(lo), float(hi), float(sigma), float(tau), float(rho), int(nv), int(degree),
                         int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF, int(ckpt_every),
-                        int(bool(dgc)))
+                        int(bool(dgc)), int(METHOD[method]), int(nv_hybrid))
 
 
 def workspace_size(csr: DeviceCSR, *, lo, hi, sigma, nv, degree, nt, precision="fp32", tau=1e-7, rho=1e-3,
-                   seed=0, budget=0, ckpt_every=0, dgc=False) -> int:
+                   seed=0, budget=0, ckpt_every=0, dgc=False, method="ss", nv_hybrid=0) -> int:
     out = C.c_size_t(0)
-    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc)
+    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc, method, nv_hybrid)
     A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(p), C.c_size_t(budget), C.byref(out)),
             "ssm_workspace_size")
     return int(out.value)
 
 
 class SSM:
-    """One context of the spectrum sweeping method (Algorithm 5) on the device."""
+    """One context of the spectrum sweeping method on the device: Algorithm 5 (method "ss")
+    or Algorithm 7 (method "ress", with nv_hybrid columns of W~ for the correction of
+    Algorithm 6; w then has nv + nv_hybrid columns)."""
 
     def __init__(self, csr: DeviceCSR, *, lo, hi, sigma, nv, degree, t, precision="fp32", tau=1e-7, rho=1e-3,
-                 seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, dgc=False, device="cuda:0"):
+                 seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, dgc=False, method="ss",
+                 nv_hybrid=0, device="cuda:0"):
         self.csr = csr
         self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         self.nt = int(self.t.size)
@@ -77,11 +84,15 @@ class SSM:
         self.elem = torch.float64 if precision == "fp64" else torch.float32
         if w is not None:
             _require_cuda(w)
-            if w.dtype != self.elem or tuple(w.shape) != (csr.n, nv) or not w.is_contiguous():
-                raise ValueError(f"w must be a contiguous {self.elem} tensor of shape ({csr.n}, {nv})")
+            cols = nv + nv_hybrid
+            if w.dtype != self.elem or tuple(w.shape) != (csr.n, cols) or not w.is_contiguous():
+                raise ValueError(f"w must be a contiguous {self.elem} tensor of shape ({csr.n}, {cols})")
         self.w_in = w
         self.degree = int(degree)
-        self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every, dgc)
+        self.method = method
+        self.nv_hybrid = int(nv_hybrid)
+        self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every, dgc,
+                              method, nv_hybrid)
         size = C.c_size_t(0)
         A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(self.params), C.c_size_t(budget),
                                          C.byref(size)), "ssm_workspace_size")
@@ -134,18 +145,23 @@ class SSM:
         v = A.ssm_views()
         A.check(A.lib.ssm_get_views(self._ctx, C.byref(v)), "ssm_get_views")
         n, nv, nt = self.csr.n, self.nv, self.nt
-        e = n * nv
+        nvp = nv + self.nv_hybrid  # columns of the block the recurrence runs on
+        e = n * nvp
         m1 = self.params.degree + 1
         ldc = (nt + 3) // 4 * 4
         out = {
-            "y": self._view(v.y, v.chunk * e, self.elem).view(v.chunk, n, nv),
-            "z": self._view(v.z, v.batch * e, self.elem).view(v.batch, n, nv),
+            "y": self._view(v.y, v.chunk * e, self.elem).view(v.chunk, n, nvp),
             "k_w": self._view(v.k_w, nt * nv * nv, torch.float64).view(nt, nv, nv),
             "k_z": self._view(v.k_z, nt * nv * nv, torch.float64).view(nt, nv, nv),
             "coeff": self._view(v.coeff, m1 * ldc, torch.float64).view(m1, ldc)[:, :nt],
             "chunk": v.chunk, "batch": v.batch, "first_point_of_last_batch": v.first_point_of_last_batch,
         }
-        out["w"] = self.w_in if self.w_in is not None else self._view(v.w, e, self.elem).view(n, nv)
+        if v.z:
+            out["z"] = self._view(v.z, v.batch * e, self.elem).view(v.batch, n, nvp)
+        if v.moments:
+            out["moments"] = self._view(v.moments, m1 * nvp * nvp, torch.float64).view(m1, nvp, nvp)
+            out["coeff_sq"] = self._view(v.coeff_sq, m1 * ldc, torch.float64).view(m1, ldc)[:, :nt]
+        out["w"] = self.w_in if self.w_in is not None else self._view(v.w, e, self.elem).view(n, nvp)
         return out
 
     def backward(self, dos_bar) -> torch.Tensor:

@@ -97,6 +97,37 @@ def test_dgc_moments_workspace(A, precision, vec):
     assert more.value - base.value == want
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(method=2), 1), (dict(nv_hybrid=4), 1), (dict(method=1, degree=51), 1),
+    (dict(method=1, degree=50, precision=1), 7), (dict(method=1, degree=50, precision=0, nv_hybrid=6), 1),
+    (dict(method=1, degree=50, precision=0, nv_hybrid=-4), 1),
+    (dict(method=1, degree=50, precision=0, nv=128, nv_hybrid=132), 7),
+    (dict(method=1, degree=50, precision=0, ckpt_every=8), 7), (dict(method=1, degree=50, precision=0, dgc=1), 7),
+])
+def test_ress_params_validated(A, kw, status):
+    out = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A)), C.byref(_params(A, **kw)), 0, C.byref(out)) == status
+
+
+def test_ress_workspace_plan(A):
+    """RESS-DGC keeps no Z: with no budget the ring holds Y_0..Y_{M/2+1} of the
+    N x (N_v + N~_v) block; a budget shrinks the ring down to three slots."""
+    n, nv, nvh, m, nt = 20000, 8, 4, 60, 30
+    p = _params(A, nv=nv, degree=m, nt=nt, precision=0, method=1, nv_hybrid=nvh)
+    full = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(full)) == 0
+    e = n * (nv + nvh) * 8
+    ring = (m // 2 + 2) * e
+    assert ring <= full.value < ring + 16 * 1024 * 1024  # + Gram partials, moments, per-point sums
+    small = C.c_size_t(0)
+    budget = 10 * e + 8 * 1024 * 1024
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), budget, C.byref(small)) == 0
+    assert small.value <= budget and small.value < full.value
+    tiny = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 2 * e, C.byref(tiny)) == \
+        A.SSM_ERR_WORKSPACE
+
+
 def test_workspace_budget_forces_more_passes_or_chunks(A):
     n, nv, m, nt = 100000, 8, 200, 64
     p = _params(A, nv=nv, degree=m, nt=nt, precision=1)
