@@ -8,10 +8,11 @@ Gram / Algorithm 4; the FP64, FP32 and plain-BF16 paths are timed beside it with
 their DOS L1 against the FP64 path.  One step = one full ssm_dos (coefficients and
 W are set up once, outside the timed region).  The adjoint (ssm_backward) of the
 measured path is timed once after the steps, and so is one ssm_dos that also forms the
-DGC estimate of Algorithm 2 from the same recurrence.
+DGC estimate of Algorithm 2 from the same recurrence, and RESS-DGC (Algorithm 7, FP64)
+with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6).
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
-                    [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint] [--no-dgc]
+                    [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint] [--no-dgc] [--no-ress]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -103,6 +104,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint (ssm_backward)")
     ap.add_argument("--no-dgc", action="store_true", help="skip the run with the DGC moments (Algorithm 2)")
+    ap.add_argument("--no-ress", action="store_true", help="skip the RESS-DGC runs (Algorithm 7)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -250,6 +252,32 @@ def main():
             "ms_recurrence_without": st["ms_recurrence"],
             "ssm_dos_max_rel_change": float(np.abs(dosd - dos).max() / dos.max()),
             "dgc_vs_ssm_l1_resolved": float(np.abs(dgc_out["dos"][keep] - dosd[keep]).sum() / np.abs(dosd[keep]).sum())}
+    if not args.no_ress:
+        # Algorithm 7 (FP64) on the same workload: N_v = 80 alone, and 40 + 40 with the
+        # hybrid correction of Algorithm 6 (the paper's split when N_v is short of the rank)
+        keep = dos > 1e-2 * dos.max()
+        for nvr, nvh in ((80, 0), (40, 40)):
+            csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=dev)
+            ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nvr, degree=m, t=wl.t, precision="fp64",
+                        seed=wl.seed, method="ress", nv_hybrid=nvh, budget=budget_left(), device=dev)
+            ctx.dos()
+            torch.cuda.synchronize()
+            t_r = time.perf_counter()
+            dres, _, _ = ctx.dos()
+            torch.cuda.synchronize()
+            msr = (time.perf_counter() - t_r) * 1e3
+            str_ = ctx.stats()
+            ctx.close()
+            del ctx, csr
+            torch.cuda.empty_cache()
+            entry = {"s_per_dos": msr / 1e3, "phases_ms": {k: str_[k] for k in
+                                                           ("ms_recurrence", "ms_gram", "ms_sweep", "ms_geneig")},
+                     "ring_slots": str_["chunk"]}
+            if "dos" in dgc_out:
+                entry["l1_vs_dgc_resolved"] = float(np.abs(dres[keep] - dgc_out["dos"][keep]).sum()
+                                                    / np.abs(dgc_out["dos"][keep]).sum())
+            comparisons[f"ress_dgc_fp64_nv{nvr}_hybrid{nvh}"] = entry
+            log(f"RESS-DGC N_v={nvr} N~_v={nvh}: {msr:.1f} ms/DOS  phases {entry['phases_ms']}")
     out["comparisons"] = comparisons
     if adjoint:
         out["adjoint"] = adjoint

@@ -225,3 +225,29 @@ def test_fullsize_dgc_moments(setup):
     l1 = np.abs(dgc[keep] - dos[keep]).sum() / np.abs(dos[keep]).sum()
     print(f"DGC by-product: recurrence {st['ms_recurrence']:.1f} ms; DGC vs SS-DGC L1 at resolved points {l1:.2e}")
     assert np.all(np.isfinite(dgc))
+
+
+def test_fullsize_ress_hybrid(setup):
+    """RESS-DGC with the hybrid correction (N_v = N~_v = 40) at the benchmark's size: the
+    moments X_0..X_8 of the device's block against the oracle's V^T T_l(A~) V, and a
+    finite estimate."""
+    S, wl, g = setup
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=DEV)
+    free, _ = torch.cuda.mem_get_info()
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=40, degree=wl.degree, t=wl.t, precision="fp64",
+                seed=wl.seed, method="ress", nv_hybrid=40, budget=int(free - 8 * (1 << 30)), device=DEV)
+    dos, r1, r2 = ctx.dos()
+    st = ctx.stats()
+    v = ctx.views()
+    x = v["moments"][:9].cpu().numpy()
+    w = v["w"].cpu().numpy()
+    ctx.close()
+    del ctx, csr
+    _free()
+    ref = np.zeros_like(x)
+    for l, v_c in O.chebyshev_blocks(wl.a, w, 8, wl.lo, wl.hi):
+        ref[l] = w.T @ v_c
+    assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref[0]).max()
+    assert np.all(np.isfinite(dos))
+    print(f"RESS-DGC 40+40: {st['ms_total']:.1f} ms (recurrence {st['ms_recurrence']:.1f}, pair Gram "
+          f"{st['ms_gram']:.1f}, moments {st['ms_sweep']:.1f}, Alg. 4 {st['ms_geneig']:.1f}), ring {st['chunk']}")
