@@ -314,8 +314,13 @@ ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, 
                            const void* y, void* z, int32_t accumulate, int32_t k3, void* stream);
 
 /* Gram matrices of ntb sweep points (Eq. tracelr, Algorithm 5 step 13):
- * k_w[i] = (W^T Z_i + Z_i^T W)/2,  k_z[i] = Z_i^T Z_i  (nv x nv doubles each),
- * Z_i = z + i*n*nv.  Products and sums in FP64 (FP32 inputs widened exactly).
+ * k_w[i] = the symmetric completion of W^T Z_i from its upper 16 x 16 blocks: entry
+ * (r, c) of block (a, b), a < b, is (W^T Z_i)[r][c] and is mirrored to (c, r); diagonal
+ * blocks are ((W^T Z_i) + (W^T Z_i)^T)/2.  W^T Z_i is symmetric in exact arithmetic on
+ * the method's path (Z_i = g(t_i I - A) W, A symmetric), where this equals
+ * (W^T Z_i + Z_i^T W)/2 up to rounding with one block product less.
+ * k_z[i] = Z_i^T Z_i  (nv x nv doubles each), Z_i = z + i*n*nv.
+ * Products and sums in FP64 (FP32 inputs widened exactly).
  * w, z: double for SSM_FP64, float otherwise.  The rows are split in nseg
  * segments, each walked by four waves whose partial sums go to `scratch`
  * (4*nseg*ntb*2*nv*nv doubles)

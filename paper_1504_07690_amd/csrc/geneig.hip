@@ -21,7 +21,7 @@ namespace ssm {
 
 namespace {
 
-constexpr int GE_THREADS = 256;
+constexpr int GE_MAX_THREADS = 1024;
 constexpr int GE_LDS_NV = 96;   // largest N_v whose two matrices sit in LDS
 constexpr int GE_MAX_NV = 256;
 constexpr int GE_MAX_SWEEPS = 40;
@@ -33,7 +33,7 @@ struct GeShared {
   double* scale;  // s^-1/2 of kept ones
   double* cs;     // pair cosines
   double* sn;     // pair sines
-  double* red;    // reduction scratch (GE_THREADS)
+  double* red;    // reduction scratch (one double per thread)
   int* pp;        // pair rows
   int* qq;        // pair cols
   int* kidx;      // kept indices
@@ -41,7 +41,7 @@ struct GeShared {
 };
 
 // Small arrays in LDS; A and V (n x (n+1) each) in LDS too, or at `big` (global).
-__device__ void ge_layout(GeShared& sh, double* lds, int n, double* big) {
+__device__ void ge_layout(GeShared& sh, double* lds, int n, double* big, int threads) {
   const int ld = n + 1;
   double* small = lds;
   if (big) {
@@ -57,17 +57,18 @@ __device__ void ge_layout(GeShared& sh, double* lds, int n, double* big) {
   sh.cs = sh.scale + GE_MAX_NV;
   sh.sn = sh.cs + GE_MAX_NV / 2;
   sh.red = sh.sn + GE_MAX_NV / 2;
-  sh.pp = (int*)(sh.red + GE_THREADS);
+  sh.pp = (int*)(sh.red + threads);
   sh.qq = sh.pp + GE_MAX_NV / 2;
   sh.kidx = sh.qq + GE_MAX_NV / 2;
   sh.misc = sh.kidx + GE_MAX_NV;
 }
 
+template <int TH>
 __device__ double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
   red[tid] = v;
   __syncthreads();
-  for (int st = GE_THREADS / 2; st > 0; st >>= 1) {
+  for (int st = TH / 2; st > 0; st >>= 1) {
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
@@ -78,6 +79,7 @@ __device__ double block_sum(double v, double* red) {
 
 // Diagonalise the symmetric n x n matrix in sh.A (row stride ld); accumulate the
 // rotations into V (if V != nullptr, V must hold the identity on entry).
+template <int TH>
 __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
   double* A = sh.A;
   const int tid = threadIdx.x;
@@ -85,14 +87,14 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
   const int npairs = ne / 2;
   for (int sweep = 0; sweep < GE_MAX_SWEEPS; ++sweep) {
     double off = 0.0, all = 0.0;
-    for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    for (int idx = tid; idx < n * n; idx += TH) {
       const int r = idx / n, c = idx - r * n;
       const double v = A[r * ld + c];
       all += v * v;
       if (r != c) off += v * v;
     }
-    off = block_sum(off, sh.red);
-    all = block_sum(all, sh.red);
+    off = block_sum<TH>(off, sh.red);
+    all = block_sum<TH>(all, sh.red);
     if (!(off > 1e-28 * all)) break;  // also stops on an all-zero matrix
     for (int round = 0; round < ne - 1; ++round) {
       if (tid < npairs) {
@@ -120,7 +122,7 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
       }
       __syncthreads();
       // rows: A <- J^T A  (row p <- c row_p - s row_q, row q <- s row_p + c row_q)
-      for (int idx = tid; idx < npairs * n; idx += GE_THREADS) {
+      for (int idx = tid; idx < npairs * n; idx += TH) {
         const int j = idx / n, col = idx - j * n;
         const int p = sh.pp[j], q = sh.qq[j];
         if (p < 0) continue;
@@ -131,7 +133,7 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
       }
       __syncthreads();
       // columns: A <- A J, V <- V J; the pivot pair (p,q),(q,p) becomes exactly 0
-      for (int idx = tid; idx < npairs * n; idx += GE_THREADS) {
+      for (int idx = tid; idx < npairs * n; idx += TH) {
         const int j = idx / n, row = idx - j * n;
         const int p = sh.pp[j], q = sh.qq[j];
         if (p < 0) continue;
@@ -154,7 +156,8 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
 // hybrid correction (Tr K_W~ - ||K_C C~||_F^2) / N~_v, C~ = U~ S~^-1/2 Q~ with Q~ the
 // eigenvectors of step 3 that pass step 4: G = K_C U~ S~^-1/2 (N~_v x r1, in hscr) is
 // formed before V is reused for Q, then ||G Q~||_F^2 in a fixed order.
-__global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const double* __restrict__ k_w,
+template <int TH>
+__global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* __restrict__ k_w,
                                                                   const double* __restrict__ k_z, double g_max,
                                                                   double tau, double rho, double* __restrict__ dos,
                                                                   int32_t* __restrict__ ranks, int ntb,
@@ -172,9 +175,9 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   const double* kz = k_z + i * nn;
   double* tmat = scratch + i * (int64_t)geneig_scratch_doubles(nv);
   GeShared sh;
-  ge_layout(sh, lds, n, nv > GE_LDS_NV ? tmat + nn : nullptr);
+  ge_layout(sh, lds, n, nv > GE_LDS_NV ? tmat + nn : nullptr, TH);
 
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     sh.A[r * ld + c] = kw[idx];
     sh.V[r * ld + c] = (r == c) ? 1.0 : 0.0;
@@ -182,8 +185,8 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   __syncthreads();
 
   // 1. W^T Z = U S U^T
-  jacobi(sh, sh.V, n, ld);
-  for (int j = tid; j < n; j += GE_THREADS) sh.s[j] = sh.A[j * ld + j];
+  jacobi<TH>(sh, sh.V, n, ld);
+  for (int j = tid; j < n; j += TH) sh.s[j] = sh.A[j * ld + j];
   __syncthreads();
 
   // 2. truncation
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   double* g = nvh ? hscr + (int64_t)i * nvh * nv : nullptr;
   if (nvh) {  // G = K_C U~ S~^-1/2  (N~_v x r1, row stride r1)
     const double* kci = k_c + (int64_t)i * nvh * nv;
-    for (int idx = tid; idx < nvh * r1; idx += GE_THREADS) {
+    for (int idx = tid; idx < nvh * r1; idx += TH) {
       const int a = idx / r1, b = idx - a * r1;
       const int kb = sh.kidx[b];
       double acc = 0.0;
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   }
 
   // 3a. T = (Z^T Z) U~ S~^-1/2   (n x r1, global scratch, row stride r1)
-  for (int idx = tid; idx < n * r1; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * r1; idx += TH) {
     const int row = idx / r1, a = idx - row * r1;
     const int ka = sh.kidx[a];
     double acc = 0.0;
@@ -237,7 +240,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   __threadfence_block();
   __syncthreads();
   // 3b. B = S~^-1/2 U~^T T  -> A (r1 x r1)
-  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+  for (int idx = tid; idx < r1 * r1; idx += TH) {
     const int a = idx / r1, b = idx - a * r1;
     const int ka = sh.kidx[a];
     double acc = 0.0;
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
     sh.A[a * ld + b] = acc * sh.scale[a];
   }
   __syncthreads();
-  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+  for (int idx = tid; idx < r1 * r1; idx += TH) {
     const int a = idx / r1, b = idx - a * r1;
     if (a < b) {
       const double m = 0.5 * (sh.A[a * ld + b] + sh.A[b * ld + a]);
@@ -255,15 +258,15 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   }
   __syncthreads();
   if (nvh) {  // eigenvectors Q of B are needed: V (U no longer) starts as the identity
-    for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+    for (int idx = tid; idx < r1 * r1; idx += TH) {
       const int a = idx / r1, b = idx - a * r1;
       sh.V[a * ld + b] = (a == b) ? 1.0 : 0.0;
     }
     __threadfence_block();
     __syncthreads();
-    jacobi(sh, sh.V, r1, ld);
+    jacobi<TH>(sh, sh.V, r1, ld);
   } else {
-    jacobi(sh, nullptr, r1, ld);
+    jacobi<TH>(sh, nullptr, r1, ld);
   }
 
   // 4. range filter and trace (fixed order); kidx now flags the eigenvectors kept
@@ -290,14 +293,14 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
   double corr = 0.0;
   if (nvh) {  // ||G Q~||_F^2
     double part = 0.0;
-    for (int idx = tid; idx < nvh * r1; idx += GE_THREADS) {
+    for (int idx = tid; idx < nvh * r1; idx += TH) {
       const int a = idx / r1, j = idx - a * r1;
       if (!sh.kidx[j]) continue;
       double h = 0.0;
       for (int b = 0; b < r1; ++b) h += g[(int64_t)a * r1 + b] * sh.V[b * ld + j];
       part += h * h;
     }
-    const double hs = block_sum(part, sh.red);
+    const double hs = block_sum<TH>(part, sh.red);
     corr = (trw[i] - hs) / nvh;
   }
   if (tid == 0) dos[i] = sh.s[0] + corr;
@@ -316,7 +319,8 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_trace_kernel(int nv, const 
 // the kept set; kept/kept entries are -1/(sqrt s_j sqrt s_k (sqrt s_j + sqrt s_k)).
 // Both are scaled by phibar[i].  Scratch per point: 3 N_v x N_v doubles
 // (U, Kt, and one product).
-__global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, const double* __restrict__ k_w,
+template <int TH>
+__global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const double* __restrict__ k_w,
                                                                      const double* __restrict__ k_z, double g_max,
                                                                      double tau, double rho,
                                                                      const double* __restrict__ phibar,
@@ -335,22 +339,22 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   double* ktg = ug + nn;                                                    // Kt = U^T K_Z U
   double* tg = ug + 2 * nn;                                                 // products
   GeShared sh;
-  ge_layout(sh, lds, n, nv > GE_LDS_NV ? ug + 3 * nn : nullptr);
+  ge_layout(sh, lds, n, nv > GE_LDS_NV ? ug + 3 * nn : nullptr, TH);
   double* f = sh.scale;  // F(s_j) for every j (0 when dropped)
   double* kwb = kw_bar + i * nn;
   double* kzb = kz_bar + i * nn;
   const double pb = phibar[i];
 
   // 1. eig(K_W)
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     sh.A[r * ld + c] = kw[idx];
     sh.V[r * ld + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi(sh, sh.V, n, ld);
-  for (int j = tid; j < n; j += GE_THREADS) sh.s[j] = sh.A[j * ld + j];
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) ug[idx] = sh.V[(idx / n) * ld + idx % n];
+  jacobi<TH>(sh, sh.V, n, ld);
+  for (int j = tid; j < n; j += TH) sh.s[j] = sh.A[j * ld + j];
+  for (int idx = tid; idx < n * n; idx += TH) ug[idx] = sh.V[(idx / n) * ld + idx % n];
   __syncthreads();
   // 2. truncation (as in the forward kernel)
   if (tid == 0) {
@@ -368,14 +372,14 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   __syncthreads();
   const int r1 = sh.misc[0];
   if (r1 == 0 || pb == 0.0) {
-    for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+    for (int idx = tid; idx < n * n; idx += TH) {
       kwb[idx] = 0.0;
       kzb[idx] = 0.0;
     }
     return;
   }
   // 3. Kt = U^T K_Z U: T = K_Z U (global), then Kt = U^T T -> A and global
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     double acc = 0.0;
     for (int q = 0; q < n; ++q) acc += kz[(int64_t)r * n + q] * sh.V[q * ld + c];
@@ -383,34 +387,34 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   }
   __threadfence_block();
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     double acc = 0.0;
     for (int q = 0; q < n; ++q) acc += sh.V[q * ld + r] * tg[(int64_t)q * n + c];
     sh.A[r * ld + c] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // symmetrise, keep a copy
+  for (int idx = tid; idx < n * n; idx += TH) {  // symmetrise, keep a copy
     const int r = idx / n, c = idx - r * n;
     ktg[idx] = 0.5 * (sh.A[r * ld + c] + sh.A[c * ld + r]);
   }
   __threadfence_block();
   __syncthreads();
   // 4. B = D Kt D on the kept set -> A (r1 x r1), eigenvectors -> V
-  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+  for (int idx = tid; idx < r1 * r1; idx += TH) {
     const int a = idx / r1, b = idx - a * r1;
     const int ka = sh.kidx[a], kb = sh.kidx[b];
     sh.A[a * ld + b] = f[ka] * ktg[(int64_t)ka * n + kb] * f[kb];
     sh.V[a * ld + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi(sh, sh.V, r1, ld);
+  jacobi<TH>(sh, sh.V, r1, ld);
   // 5. P (U coordinates, n x n) = sum over in-range xi of x x^T, embedded -> global tg
   const double hi = (1.0 + rho) * g_max;
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) tg[idx] = 0.0;
+  for (int idx = tid; idx < n * n; idx += TH) tg[idx] = 0.0;
   __threadfence_block();
   __syncthreads();
-  for (int idx = tid; idx < r1 * r1; idx += GE_THREADS) {
+  for (int idx = tid; idx < r1 * r1; idx += TH) {
     const int a = idx / r1, b = idx - a * r1;
     double acc = 0.0;
     for (int j = 0; j < r1; ++j) {
@@ -422,14 +426,14 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   __threadfence_block();
   __syncthreads();
   // 6. M1 = Gamma o (Kt D P + P D Kt) -> V;  M2 = D P D -> A
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int j = idx / n, k = idx - j * n;
     double acc = 0.0;  // (Kt D P)[j][k]
     for (int q = 0; q < n; ++q) acc += ktg[(int64_t)j * n + q] * f[q] * tg[(int64_t)q * n + k];
     sh.V[j * ld + k] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int j = idx / n, k = idx - j * n;
     if (j > k) continue;
     const double sj = sh.s[j], sk = sh.s[k];
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
     sh.V[j * ld + k] = g * h;
     sh.V[k * ld + j] = g * h;
   }
-  for (int idx = tid; idx < n * n; idx += GE_THREADS) {
+  for (int idx = tid; idx < n * n; idx += TH) {
     const int j = idx / n, k = idx - j * n;
     sh.A[j * ld + k] = f[j] * tg[idx] * f[k];
   }
@@ -458,7 +462,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
   for (int which = 0; which < 2; ++which) {
     const double* m = which == 0 ? sh.V : sh.A;
     double* out = which == 0 ? kwb : kzb;
-    for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // T = U M
+    for (int idx = tid; idx < n * n; idx += TH) {  // T = U M
       const int r = idx / n, c = idx - r * n;
       double acc = 0.0;
       for (int q = 0; q < n; ++q) acc += ug[(int64_t)r * n + q] * m[q * ld + c];
@@ -466,7 +470,7 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
     }
     __threadfence_block();
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += GE_THREADS) {  // out = T U^T
+    for (int idx = tid; idx < n * n; idx += TH) {  // out = T U^T
       const int r = idx / n, c = idx - r * n;
       double acc = 0.0;
       for (int q = 0; q < n; ++q) acc += tg[(int64_t)r * n + q] * ug[(int64_t)c * n + q];
@@ -479,11 +483,40 @@ __global__ void __launch_bounds__(GE_THREADS) geneig_backward_kernel(int nv, con
 
 }  // namespace
 
+// Threads per point: the Jacobi rounds are latency-bound at one workgroup per CU, so the
+// larger matrices take more waves (measured on the benchmark's pencils: N_v = 80 runs in
+// 0.63x the time with 512 threads; N_v = 40 is fastest with 256).
+int geneig_threads(int nv) { return nv <= 48 ? 256 : nv <= GE_LDS_NV ? 512 : GE_MAX_THREADS; }
+
 size_t geneig_lds_bytes(int nv) {
   const size_t n = (size_t)nv, ld = n + 1;
   const size_t mats = nv > GE_LDS_NV ? 0 : 2 * n * ld;
-  return (mats + 2 * GE_MAX_NV + GE_MAX_NV + GE_THREADS) * sizeof(double) +
+  return (mats + 2 * GE_MAX_NV + GE_MAX_NV + (size_t)geneig_threads(nv)) * sizeof(double) +
          (GE_MAX_NV + GE_MAX_NV + 4) * sizeof(int);
+}
+
+template <int TH>
+hipError_t launch_backward_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                             double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
+                             size_t lds, hipStream_t stream) {
+  hipError_t err = hipFuncSetAttribute((const void*)geneig_backward_kernel<TH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(geneig_backward_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho,
+                     phibar, kw_bar, kz_bar, scratch);
+  return hipGetLastError();
+}
+
+template <int TH>
+hipError_t launch_trace_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                          double rho, double* dos, int32_t* ranks, double* scratch, int nvh, const double* k_c,
+                          const double* trw, double* hscr, size_t lds, hipStream_t stream) {
+  hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel<TH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(geneig_trace_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho, dos,
+                     ranks, ntb, scratch, nvh, k_c, trw, hscr);
+  return hipGetLastError();
 }
 
 hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
@@ -491,12 +524,15 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
                                   hipStream_t stream) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   const size_t lds = geneig_lds_bytes(nv);
-  hipError_t err = hipFuncSetAttribute((const void*)geneig_backward_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(geneig_backward_kernel, dim3(ntb), dim3(GE_THREADS), lds, stream, nv, k_w, k_z, g_max, tau, rho,
-                     phibar, kw_bar, kz_bar, scratch);
-  return hipGetLastError();
+  switch (geneig_threads(nv)) {
+    case 256:
+      return launch_backward_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, lds, stream);
+    case 512:
+      return launch_backward_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, lds, stream);
+    default:
+      return launch_backward_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch,
+                                               lds, stream);
+  }
 }
 
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
@@ -505,12 +541,17 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
   const size_t lds = geneig_lds_bytes(nv);
-  hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(geneig_trace_kernel, dim3(ntb), dim3(GE_THREADS), lds, stream, nv, k_w, k_z, g_max, tau, rho,
-                     dos, ranks, ntb, scratch, nvh, k_c, trw, hscr);
-  return hipGetLastError();
+  switch (geneig_threads(nv)) {
+    case 256:
+      return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, lds,
+                                 stream);
+    case 512:
+      return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, lds,
+                                 stream);
+    default:
+      return launch_trace_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw,
+                                            hscr, lds, stream);
+  }
 }
 
 }  // namespace ssm

@@ -1,19 +1,22 @@
 // Gram matrices of the sweep (Eq. tracelr; Algorithm 5, step 13):
 //
-//   K_W(t_i) = (W^T Z_i + Z_i^T W) / 2,   K_Z(t_i) = Z_i^T Z_i,     Z_i, W: N x N_v
+//   K_W(t_i) = W^T Z_i (symmetric),   K_Z(t_i) = Z_i^T Z_i,     Z_i, W: N x N_v
 //
 // in FP64 on v_mfma_f64_16x16x4_f64.  FP32 inputs are widened to FP64 exactly, so
-// every product is exact and only the FP64 sums round.
+// every product is exact and only the FP64 sums round.  W^T Z_i = W^T g(t_i I - A~) W is
+// symmetric in exact arithmetic, so only its upper 16x16 blocks W_a^T Z_b (a <= b) are
+// formed: a diagonal block is averaged with its transpose and the lower blocks mirror
+// the upper ones.  This is one symmetric completion of the computed W^T Z; (W^T Z +
+// Z^T W)/2 is another, with the same value in exact arithmetic and one more product.
 //
 // Work split (N_v <= 96): one workgroup per (sweep point, row segment); each of its
 // four waves walks a contiguous quarter of the segment, four rows per MFMA step (the
-// MFMA's k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of
-// W^T Z + Z^T W (W^T Z alone on the diagonal) in registers, so its operands come
-// straight from memory: lane l reads column 16a + l%16 of row r + l/16 for each column
-// block a, for Z_i and W (a 4-row slab is contiguous), two steps ahead of the MFMAs
-// that consume them.  Each wave writes its partial blocks to scratch; a second kernel
-// adds the partials in a fixed order, mirrors the lower triangle and halves K_W
-// (deterministic).
+// MFMA's k).  A wave keeps every upper 16x16 block (a <= b) of Z^T Z and of W^T Z in
+// registers, so its operands come straight from memory: lane l reads column
+// 16a + l%16 of row r + l/16 for each column block a, for Z_i and W (a 4-row slab is
+// contiguous), two steps ahead of the MFMAs that consume them.  Each wave writes its
+// partial blocks to scratch; a second kernel adds the partials in a fixed order and
+// completes the symmetric matrices (deterministic).
 #include "ssm_kernels.h"
 
 namespace ssm {
@@ -130,15 +133,6 @@ __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, c
         const int p = a * T - a * (a - 1) / 2 + (bb - a);
         acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wf[a], zf[bb], acc_wz[p], 0, 0, 0);
       }
-    // Z_a^T W_b only off the diagonal: on a diagonal block it is the transpose of W_a^T Z_a,
-    // and the reduction symmetrises that block instead
-#pragma unroll
-    for (int a = 0; a < T; ++a)
-#pragma unroll
-      for (int bb = a + 1; bb < T; ++bb) {
-        const int p = a * T - a * (a - 1) / 2 + (bb - a);
-        acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(zf[a], wf[bb], acc_wz[p], 0, 0, 0);
-      }
     __builtin_amdgcn_sched_barrier(0);  // keep steps apart: their operands need not be live together
   };
 #pragma clang loop unroll(disable)
@@ -171,13 +165,13 @@ __global__ void __launch_bounds__(256) gram_kernel(int64_t n, int nv, int ntb, c
 }
 
 // N_v above 96: the block grid is cut into tiles of 4 x 4 column blocks, (ti, tj) with
-// ti <= tj, one tile per blockIdx.z; each wave keeps the 16 Z^T Z and 16 W^T Z + Z^T W
+// ti <= tj, one tile per blockIdx.z; each wave keeps the 16 Z^T Z and 16 W^T Z
 // blocks of its tile (on a diagonal tile the lower blocks are computed and not stored).
 constexpr int GT_B = 4;
 
 template <typename In>
 struct GramTileStep {
-  In za[GT_B], wa[GT_B], zb[GT_B], wb[GT_B];
+  In za[GT_B], wa[GT_B], zb[GT_B];
 };
 
 template <typename In>
@@ -190,7 +184,6 @@ __device__ __forceinline__ void gram_tile_load(GramTileStep<In>& st, __amdgpu_bu
     st.za[a] = buffer_load<In>(rz, base + off_a[a]);
     st.wa[a] = buffer_load<In>(rw, base + off_a[a]);
     st.zb[a] = buffer_load<In>(rz, base + off_b[a]);
-    st.wb[a] = buffer_load<In>(rw, base + off_b[a]);
   }
 }
 
@@ -241,13 +234,12 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
   gram_tile_load<In>(buf1, rz, rw, 4, nv, off_a, off_b);
   __builtin_amdgcn_sched_barrier(0);
   auto step = [&](GramTileStep<In>& b, int rr) {
-    double za[GT_B], wa[GT_B], zb[GT_B], wb[GT_B];
+    double za[GT_B], wa[GT_B], zb[GT_B];
 #pragma unroll
     for (int a = 0; a < GT_B; ++a) {
       za[a] = (double)b.za[a];
       wa[a] = (double)b.wa[a];
       zb[a] = (double)b.zb[a];
-      wb[a] = (double)b.wb[a];
     }
     gram_tile_load<In>(b, rz, rw, rr + 8, nv, off_a, off_b);
 #pragma unroll
@@ -257,8 +249,6 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
         const int p = a * GT_B + bb;
         acc_zz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], zb[bb], acc_zz[p], 0, 0, 0);
         acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[a], zb[bb], acc_wz[p], 0, 0, 0);
-        if (ti != tj || a != bb)  // diagonal blocks: W_a^T Z_a alone (symmetrised in the reduction)
-          acc_wz[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[a], wb[bb], acc_wz[p], 0, 0, 0);
       }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -291,9 +281,8 @@ __global__ void __launch_bounds__(256) gram_tiled_kernel(int64_t n, int nv, int 
 }
 
 // K(i)[r][c] = sum over segments of the stored upper block entry; the lower blocks
-// mirror the upper ones; the diagonal blocks are averaged with their transpose.  A
-// diagonal block of the W-part holds W_a^T Z_a alone (an off-diagonal one W_a^T Z_b +
-// Z_a^T W_b), hence its factor 1/2 against 1/4.
+// mirror the upper ones; the diagonal blocks are averaged with their transpose (off the
+// diagonal blocks o1 = o2, so the factor 1/2 leaves the entry as stored).
 __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int nseg, const double* __restrict__ part,
                                                           double* __restrict__ k_w, double* __restrict__ k_z) {
   const int64_t nn = (int64_t)nv * nv;
@@ -316,7 +305,7 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(int nv, int ntb, int n
     sw2 += pw[o2];
   }
   k_z[gid] = 0.5 * (sz1 + sz2);
-  k_w[gid] = ((r >> 4) == (c >> 4) ? 0.5 : 0.25) * (sw1 + sw2);
+  k_w[gid] = 0.5 * (sw1 + sw2);
 }
 
 int64_t rows_per_segment(int64_t n, int nseg) {
