@@ -159,8 +159,12 @@ ssm_status ssm_dos(ssm_ctx* ctx, double* dos_host, int32_t* ranks_host);
  * K_W~ = W~^T g^{M/2} W~ (Theorem 4).  The recurrence runs on V = [W W~] to degree
  * M/2 + 1 only: for symmetric A~, T_s^2 = (T_{2s} + T_0)/2 and T_{s+1} T_s =
  * (T_{2s+1} + T_1)/2 turn the Gram matrices of consecutive blocks into every moment
- * X_l, l <= M (FP64 throughout).  ranks_host as for Algorithm 5 (r1, r2 of the
- * N_v x N_v pencil).  The bound check uses ||T_{M/2+1}(A~)V||_F. */
+ * X_l, l <= M (FP64 throughout).  Algorithm 4's truncation also drops eigenvalues of
+ * K_W(t_i) below 1e-12 sum_{l<=M/2} |mu_l(t_i)| max|X_l[:nv, :nv]|, the rounding level of
+ * K_W as a sum of moments (at sweep points outside the spectrum K_W and K_Z are both
+ * rounding, and their pencil would otherwise report arbitrary values).  ranks_host as
+ * for Algorithm 5 (r1, r2 of the N_v x N_v pencil).  The bound check uses
+ * ||T_{M/2+1}(A~)V||_F. */
 
 /* Sum_i w[i] * dos[i] over the DOS of the last ssm_dos (Algorithm 8, step 4).
  * SSM_ERR_STATE before the first ssm_dos. */

@@ -27,6 +27,8 @@ Readings where the paper is silent (each also listed in the design notes):
   (closed interval, relative slack rho, default 1e-3).
 * Algorithm 7 takes mu_l (l <= M/2) from Algorithm 1 run at degree M (the
   run's N_theta) and sets the rest to 0; M must be even (Proposition 1).
+* Algorithm 7's truncation also drops eigenvalues of K_W below the rounding
+  level of its moment sum, 1e-12 sum_l |mu_l(t_i)| max|X_W,l| (see ress_dgc).
 * Algorithm 8 deconvolves with the unit-mass Gaussian (N times g_sigma),
   periodically on [-1, 1] in the rescaled variable, dropping wavenumbers k
   with exp(-(sigma^ pi k)^2 / 2) < eta (eta = 1e-10).
@@ -160,11 +162,11 @@ def dgc_dos(a, w, t, degree, sigma, lo, hi):
 # Algorithm 4: generalised eigenvalue problem, truncated
 # ----------------------------------------------------------------------------
 def geneig_trace(k_w: np.ndarray, k_z: np.ndarray, g_max: float, tau: float = 1e-7,
-                 rho: float = 1e-3, return_parts: bool = False):
+                 rho: float = 1e-3, return_parts: bool = False, s_floor: float = 0.0):
     """Tr Xi~ for the pencil (Z^*Z, W^*Z) of one sweep point (Algorithm 4).
 
     1. W^*Z = U S U^*.
-    2. keep s_j >= tau max_i s_i  (S~, U~).
+    2. keep s_j >= tau max_i s_i  (S~, U~), and s_j >= s_floor (0 unless given).
     3. eig of S~^{-1/2} U~^* Z^*Z U~ S~^{-1/2}  -> xi.
     4. keep xi in [0, (1 + rho) g_max].
     Returns the sum of kept xi and the two kept counts (r1, r2); with
@@ -178,7 +180,10 @@ def geneig_trace(k_w: np.ndarray, k_z: np.ndarray, g_max: float, tau: float = 1e
     if not smax > 0.0:
         out = (0.0, 0, 0)
         return out + ({"s": s, "xi": np.zeros(0), "c": np.zeros((k_w.shape[0], 0))},) if return_parts else out
-    keep = s >= tau * smax
+    keep = (s >= tau * smax) & (s >= s_floor)
+    if not keep.any():
+        out = (0.0, 0, 0)
+        return out + ({"s": s, "xi": np.zeros(0), "c": np.zeros((k_w.shape[0], 0))},) if return_parts else out
     u_t = u[:, keep] / np.sqrt(s[keep])[None, :]
     b = u_t.T @ k_z @ u_t
     xi, q = np.linalg.eigh(0.5 * (b + b.T))
@@ -264,8 +269,11 @@ def square_coefficients(mu_half: np.ndarray, degree: int, n_theta: int | None = 
     return nu
 
 
+RESS_FLOOR = 1e-12  # eta of the rounding floor of Algorithm 7's truncation (see ress_dgc)
+
+
 def ress_dgc(a, w, w_tilde, t, degree: int, sigma: float, lo: float, hi: float, tau: float = 1e-7,
-             rho: float = 1e-3):
+             rho: float = 1e-3, eta: float = RESS_FLOOR):
     """RESS-DGC estimate of phi_sigma at the sweep points (Algorithm 7).
 
     1. mu_l(t_i) by Algorithm 1 at degree M, set to 0 for l > M/2;
@@ -276,6 +284,11 @@ def ress_dgc(a, w, w_tilde, t, degree: int, sigma: float, lo: float, hi: float, 
     16-18. per point, Algorithm 4 on (K_Z, K_W) gives Xi~ and C~, and
        phi~ = Tr Xi~ + (Tr K_W~ - Tr[K_C C~ C~^* K_C^*]) / N~_v  (the last term only
        when N~_v > 0; Algorithm 6).
+    Truncation floor: K_W is a sum of moments that cancel to almost nothing where
+    g^{M/2}(t_i I - A) W is small, so its rounding is about u sum_l |mu_l(t_i)| max|X_W,l|,
+    and so is K_Z's, independently.  Step 2 of Algorithm 4 therefore also drops s_j below
+    eta sum_l |mu_l(t_i)| max|X_W,l| (eta = 1e-12): below that the pencil's eigenvalues
+    are rounding and land anywhere, in range included.
     Returns a dict with ``dos``, ``r1``, ``r2`` and the accumulated matrices.
     """
     assert degree % 2 == 0, "Proposition 1 needs an even degree"
@@ -293,9 +306,11 @@ def ress_dgc(a, w, w_tilde, t, degree: int, sigma: float, lo: float, hi: float, 
     k_z = np.zeros((nt, nv, nv))
     k_c = np.zeros((nt, nvt, nv))
     k_wt = np.zeros((nt, nvt, nvt))
+    xmax = np.zeros(degree + 1)
     blocks_t = chebyshev_blocks(a, w_tilde, degree, lo, hi) if nvt else None
     for l, v_c in chebyshev_blocks(a, w, degree, lo, hi):                  # steps 6-15
         x_w = w.T @ v_c
+        xmax[l] = np.abs(x_w).max()
         k_w += mu[l][:, None, None] * x_w[None]
         k_z += nu[l][:, None, None] * x_w[None]
         if nvt:
@@ -303,17 +318,19 @@ def ress_dgc(a, w, w_tilde, t, degree: int, sigma: float, lo: float, hi: float, 
             k_c += mu[l][:, None, None] * (w_tilde.T @ v_c)[None]
             k_wt += mu[l][:, None, None] * (w_tilde.T @ vt_c)[None]
     g_max = range_bound(sigma, n)
+    floor = eta * (np.abs(mu) * xmax[:, None]).sum(axis=0)
     dos = np.zeros(nt)
     r1 = np.zeros(nt, dtype=np.int64)
     r2 = np.zeros(nt, dtype=np.int64)
     for i in range(nt):                                                    # steps 16-18
-        tr, r1[i], r2[i], parts = geneig_trace(k_w[i], k_z[i], g_max, tau, rho, return_parts=True)
+        tr, r1[i], r2[i], parts = geneig_trace(k_w[i], k_z[i], g_max, tau, rho, return_parts=True,
+                                               s_floor=floor[i])
         if nvt:
             kcc = k_c[i] @ parts["c"]
             tr += (np.trace(k_wt[i]) - np.sum(kcc * kcc)) / nvt
         dos[i] = tr
     return {"dos": dos, "r1": r1, "r2": r2, "mu": mu, "nu": nu, "k_w": k_w, "k_z": k_z, "k_c": k_c,
-            "k_wt": k_wt}
+            "k_wt": k_wt, "floor": floor}
 
 
 # ----------------------------------------------------------------------------

@@ -164,7 +164,8 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
                                                                   double* __restrict__ scratch, int nvh,
                                                                   const double* __restrict__ k_c,
                                                                   const double* __restrict__ trw,
-                                                                  double* __restrict__ hscr) {
+                                                                  double* __restrict__ hscr,
+                                                                  const double* __restrict__ s_floor) {
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
     for (int j = 0; j < n; ++j) smax = fmax(smax, sh.s[j]);
     int r1 = 0;
     if (smax > 0.0) {
-      const double thr = tau * smax;
+      const double thr = s_floor ? fmax(tau * smax, s_floor[i]) : tau * smax;
       for (int j = 0; j < n; ++j)
         if (sh.s[j] >= thr) {
           sh.kidx[r1] = j;
@@ -510,12 +511,13 @@ hipError_t launch_backward_t(int nv, int ntb, const double* k_w, const double* k
 template <int TH>
 hipError_t launch_trace_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                           double rho, double* dos, int32_t* ranks, double* scratch, int nvh, const double* k_c,
-                          const double* trw, double* hscr, size_t lds, hipStream_t stream) {
+                          const double* trw, double* hscr, const double* s_floor, size_t lds,
+                          hipStream_t stream) {
   hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel<TH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_trace_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho, dos,
-                     ranks, ntb, scratch, nvh, k_c, trw, hscr);
+                     ranks, ntb, scratch, nvh, k_c, trw, hscr, s_floor);
   return hipGetLastError();
 }
 
@@ -537,20 +539,21 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
 
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                                double rho, double* dos, int32_t* ranks, double* scratch, hipStream_t stream,
-                               int nvh, const double* k_c, const double* trw, double* hscr) {
+                               int nvh, const double* k_c, const double* trw, double* hscr,
+                               const double* s_floor) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
   const size_t lds = geneig_lds_bytes(nv);
   switch (geneig_threads(nv)) {
     case 256:
-      return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, lds,
-                                 stream);
+      return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
+                                 s_floor, lds, stream);
     case 512:
-      return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, lds,
-                                 stream);
+      return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
+                                 s_floor, lds, stream);
     default:
       return launch_trace_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw,
-                                            hscr, lds, stream);
+                                            hscr, s_floor, lds, stream);
   }
 }
 

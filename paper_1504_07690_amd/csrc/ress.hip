@@ -55,7 +55,49 @@ __global__ void __launch_bounds__(256) ress_extract_kernel(int nv, int nvh, cons
   }
 }
 
+// Rounding floor of the truncation: K_W(t_i) = sum_{l<=h} mu_l(t_i) X_l[:nv, :nv] rounds at
+// about u sum_l |mu_l(t_i)| max|X_l[:nv, :nv]|, so Algorithm 4 also drops eigenvalues below
+// eta times that sum.  One workgroup per l for the maxima (fixed order), then one lane
+// per point.
+__global__ void __launch_bounds__(256) ress_xmax_kernel(int nv, int nvp, const double* __restrict__ x,
+                                                        double* __restrict__ xmax) {
+  __shared__ double red[256];
+  const double* xl = x + (int64_t)blockIdx.x * nvp * nvp;
+  double m = 0.0;
+  for (int idx = threadIdx.x; idx < nv * nv; idx += 256) {
+    const int r = idx / nv, c = idx - r * nv;
+    m = fmax(m, fabs(xl[(int64_t)r * nvp + c]));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) xmax[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) ress_floor_kernel(const double* __restrict__ mu, int64_t ldc, int nt, int h,
+                                                         const double* __restrict__ xmax, double eta,
+                                                         double* __restrict__ floor_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  double acc = 0.0;
+  for (int l = 0; l <= h; ++l) acc += fabs(mu[(int64_t)l * ldc + i]) * xmax[l];
+  floor_out[i] = eta * acc;
+}
+
 }  // namespace
+
+hipError_t launch_ress_floor(int nv, int nvp, int h, const double* x, const double* mu, int64_t ldc, int nt,
+                             double eta, double* xmax, double* floor_out, hipStream_t stream) {
+  hipLaunchKernelGGL(ress_xmax_kernel, dim3(h + 1), dim3(256), 0, stream, nv, nvp, x, xmax);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(ress_floor_kernel, dim3((nt + 255) / 256), dim3(256), 0, stream, mu, ldc, nt, h, xmax, eta,
+                     floor_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_ress_moments(int nvp, int m1, const double* pw, const double* pz, double* x, hipStream_t stream) {
   const int64_t nn = (int64_t)nvp * nvp;

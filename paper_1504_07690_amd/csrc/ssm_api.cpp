@@ -107,7 +107,7 @@ struct Plan {
   // RESS-DGC: chunk = new blocks per round, ring of chunk + 1 slots
   bool ress = false;
   size_t off_nu = 0, off_kc = 0, off_trw = 0, off_hscr = 0, off_pw = 0, off_pz = 0, off_x = 0, off_kmu = 0,
-         off_knu = 0;
+         off_knu = 0, off_xmax = 0, off_floor = 0;
 };
 
 // Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
@@ -220,6 +220,8 @@ void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_x = take((size_t)m1 * nnp * 8);
   pl.off_kmu = take((size_t)p->nt * nnp * 8);
   pl.off_knu = take((size_t)p->nt * nnp * 8);
+  pl.off_xmax = take((size_t)S * 8);
+  pl.off_floor = take((size_t)p->nt * 8);
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * std::max(pl.chunk, 1) * 2 * nnp * 8);
   pl.off_y = take((size_t)(pl.chunk + 1) * e * 8);
   pl.total = o;
@@ -336,6 +338,8 @@ struct ssm_ctx {
   double* xm = nullptr;     // moments X_0..X_M
   double* kmu = nullptr;    // nt x N_v'^2
   double* knu = nullptr;    // nt x N_v'^2
+  double* xmax = nullptr;   // max |X_l[:N_v, :N_v]|, l <= M/2
+  double* sfloor = nullptr; // rounding floor of Algorithm 4's truncation per point
   std::vector<double> dos_host;
   bool have_dos = false;
   bool have_dgc = false;
@@ -431,6 +435,8 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
     c->xm = (double*)(c->ws + pl.off_x);
     c->kmu = (double*)(c->ws + pl.off_kmu);
     c->knu = (double*)(c->ws + pl.off_knu);
+    c->xmax = (double*)(c->ws + pl.off_xmax);
+    c->sfloor = (double*)(c->ws + pl.off_floor);
   }
   c->dos_host.assign(p->nt, 0.0);
 
@@ -670,6 +676,13 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Algorithm 4's truncation under RESS-DGC also drops eigenvalues of K_W below
+// kRessFloor * sum_{l<=M/2} |mu_l(t_i)| max|X_l|: the rounding level of K_W formed as a
+// sum of moments (about 4500 units of FP64 rounding).  Without it, at sweep points where
+// g^{M/2}(t_i I - A) W is rounding noise, K_Z's independent rounding gives the pencil
+// arbitrary eigenvalues, in range included.
+constexpr double kRessFloor = 1e-12;
+
 ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
@@ -751,6 +764,8 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (err == hipSuccess)
     err = ssm::launch_sweep_f64(nnp, m1, p.nt, c->nu, pl.ldc, pl.ldc, c->xm, c->knu, 0, st);
   if (err == hipSuccess) err = ssm::launch_ress_extract(p.nt, nv, nvh, c->kmu, c->knu, c->kw, c->kz, c->kc, c->trw, st);
+  if (err == hipSuccess)
+    err = ssm::launch_ress_floor(nv, nvp, m / 2, c->xm, c->c64, pl.ldc, p.nt, kRessFloor, c->xmax, c->sfloor, st);
   if (err != hipSuccess) return hip_fail(err, "moment kernels");
   ms.en = mark();
   SSM_HIP(rec(ms.en), "hipEventRecord");
@@ -759,7 +774,7 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   Span es_{mark(), mark(), 3};
   SSM_HIP(rec(es_.b), "hipEventRecord");
   err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks, c->escr, st,
-                                 nvh, c->kc, c->trw, c->hscr);
+                                 nvh, c->kc, c->trw, c->hscr, c->sfloor);
   if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
   SSM_HIP(rec(es_.en), "hipEventRecord");
   spans.push_back(es_);

@@ -110,16 +110,21 @@ __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
 }
 // nvh > 0 adds the hybrid correction of Algorithm 6 from k_c (ntb x nvh x nv), trw (ntb)
 // with hscr (ntb * nvh * nv doubles) as scratch.
+// s_floor (ntb doubles, may be null): Algorithm 4 step 2 also drops s_j < s_floor[i].
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max,
                                double tau, double rho, double* dos, int32_t* ranks, double* scratch,
                                hipStream_t stream, int nvh = 0, const double* k_c = nullptr,
-                               const double* trw = nullptr, double* hscr = nullptr);
+                               const double* trw = nullptr, double* hscr = nullptr,
+                               const double* s_floor = nullptr);
 // RESS-DGC (ress.hip): X_l, l < m1, of the N_v' = nvp block from the pair Gram matrices,
 // and the per-point split of K_mu, K_nu (nvp x nvp each) into K_W, K_Z (nv x nv), K_C
 // (nvh x nv) and Tr K_W~.
 hipError_t launch_ress_moments(int nvp, int m1, const double* pw, const double* pz, double* x, hipStream_t stream);
 hipError_t launch_ress_extract(int nt, int nv, int nvh, const double* kmu, const double* knu, double* kw, double* kz,
                                double* kc, double* trw, hipStream_t stream);
+// floor_out[i] = eta * sum_{l<=h} |mu_l(t_i)| max|X_l[:nv, :nv]| (xmax: h+1 doubles of scratch)
+hipError_t launch_ress_floor(int nv, int nvp, int h, const double* x, const double* mu, int64_t ldc, int nt,
+                             double eta, double* xmax, double* floor_out, hipStream_t stream);
 size_t geneig_lds_bytes(int nv);
 // Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z.
 // scratch: 3 * ntb * nv * nv doubles.

@@ -358,6 +358,26 @@ def test_ress_hybrid_identity_probe_gives_exact_trace():
     assert np.abs(plain - ref).max() > 1e-2 * ref.max()  # N_v = 8 alone misses mass
 
 
+def test_ress_floor_silences_points_outside_the_spectrum():
+    """Sweep points outside the spectrum of a clean 8^3 lattice, where g(tI - A) is below
+    1e-12 of its maximum: K_W and K_Z are rounding noise there, and without the rounding
+    floor of the truncation the pencil reports a fifth of the maximum; with it, nothing."""
+    a = WL.anderson_3d(8, np.zeros(512))
+    lam = np.linalg.eigvalsh(a.to_dense())
+    lo, hi = WL.interval(a)
+    hw = 0.5 * (hi - lo)
+    sigma = 0.01 * hw
+    t = 0.5 * (lo + hi) + hw * WL.midpoint_grid(60)
+    ref = O.exact_dos(lam, t, sigma)
+    out = ref < 1e-12 * ref.max()
+    assert out.sum() >= 2
+    w = WL.gaussian_block(a.n, 40, seed=4)
+    with_floor = O.ress_dgc(a, w, None, t, 600, sigma, lo, hi)["dos"]
+    without = O.ress_dgc(a, w, None, t, 600, sigma, lo, hi, eta=0.0)["dos"]
+    assert np.abs(with_floor[out]).max() <= 1e-9 * ref.max()
+    assert np.abs(without[out]).max() > 1e-2 * ref.max()
+
+
 def test_ress_correction_vanishes_when_sampled_enough():
     """With N_v above the numerical rank the low-rank part is exact (Theorem 3), so the
     hybrid correction is at rounding level and both estimates agree."""
