@@ -79,12 +79,19 @@ __device__ double block_sum(double v, double* red) {
 
 // Diagonalise the symmetric n x n matrix in sh.A (row stride ld); accumulate the
 // rotations into V (if V != nullptr, V must hold the identity on entry).
+// Each round rotates the disjoint index pairs (p_j, q_j) at once: A <- R^T A R, R the
+// product of the pair rotations.  Entries of the 2 x 2 block of pairs (j, k) depend only
+// on that block, so one lane updates a block (rows by pair j, then columns by pair k, the
+// order of a row pass followed by a column pass) and writes it and its mirror (k, j),
+// keeping A exactly symmetric; the pivot pair of a diagonal block becomes exactly 0.  When
+// n is odd the index left without a partner forms a one-element pair (q = -1, no rotation).
 template <int TH>
 __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
   double* A = sh.A;
   const int tid = threadIdx.x;
   const int ne = n + (n & 1);
   const int npairs = ne / 2;
+  const int nblocks = npairs * (npairs + 1) / 2;
   for (int sweep = 0; sweep < GE_MAX_SWEEPS; ++sweep) {
     double off = 0.0, all = 0.0;
     for (int idx = tid; idx < n * n; idx += TH) {
@@ -111,8 +118,8 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
           }
-        } else {
-          p = -1;
+        } else {  // the phantom index n of an odd n: its partner stays as it is
+          p = (p < n) ? p : q;
           q = -1;
         }
         sh.pp[tid] = p;
@@ -121,27 +128,59 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
         sh.sn[tid] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A  (row p <- c row_p - s row_q, row q <- s row_p + c row_q)
-      for (int idx = tid; idx < npairs * n; idx += TH) {
-        const int j = idx / n, col = idx - j * n;
-        const int p = sh.pp[j], q = sh.qq[j];
-        if (p < 0) continue;
-        const double c = sh.cs[j], s = sh.sn[j];
-        const double ap = A[p * ld + col], aq = A[q * ld + col];
-        A[p * ld + col] = c * ap - s * aq;
-        A[q * ld + col] = s * ap + c * aq;
+      // blocks (j, k), j <= k, numbered row by row
+      for (int idx = tid; idx < nblocks; idx += TH) {
+        int j = 0, rem = idx;
+        while (rem >= npairs - j) {
+          rem -= npairs - j;
+          ++j;
+        }
+        const int k = j + rem;
+        const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
+        const double cj = sh.cs[j], sj = sh.sn[j], ck = sh.cs[k], sk = sh.sn[k];
+        if (qj < 0 || qk < 0) {  // a one-element pair: a row, a column or one entry
+          if (qj < 0 && qk < 0) continue;  // its diagonal entry does not change
+          // the single index x against the pair (y0, y1) rotated by (c, s)
+          const int x = qj < 0 ? pj : pk;
+          const int y0 = qj < 0 ? pk : pj, y1 = qj < 0 ? qk : qj;
+          const double c = qj < 0 ? ck : cj, s = qj < 0 ? sk : sj;
+          const double a0 = A[x * ld + y0], a1 = A[x * ld + y1];
+          const double n0 = c * a0 - s * a1, n1 = s * a0 + c * a1;
+          A[x * ld + y0] = n0;
+          A[x * ld + y1] = n1;
+          A[y0 * ld + x] = n0;
+          A[y1 * ld + x] = n1;
+          continue;
+        }
+        const double a = A[pj * ld + pk], b = A[pj * ld + qk], c0 = A[qj * ld + pk], d = A[qj * ld + qk];
+        // rows by pair j
+        const double ra = cj * a - sj * c0, rc = sj * a + cj * c0;
+        const double rb = cj * b - sj * d, rd = sj * b + cj * d;
+        // columns by pair k
+        const double na = ck * ra - sk * rb, nb = sk * ra + ck * rb;
+        const double nc = ck * rc - sk * rd, nd = sk * rc + ck * rd;
+        if (j == k) {  // the pivot pair becomes exactly 0
+          A[pj * ld + pj] = na;
+          A[qj * ld + qj] = nd;
+          A[pj * ld + qj] = 0.0;
+          A[qj * ld + pj] = 0.0;
+        } else {
+          A[pj * ld + pk] = na;
+          A[pj * ld + qk] = nb;
+          A[qj * ld + pk] = nc;
+          A[qj * ld + qk] = nd;
+          A[pk * ld + pj] = na;
+          A[qk * ld + pj] = nb;
+          A[pk * ld + qj] = nc;
+          A[qk * ld + qj] = nd;
+        }
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J; the pivot pair (p,q),(q,p) becomes exactly 0
-      for (int idx = tid; idx < npairs * n; idx += TH) {
-        const int j = idx / n, row = idx - j * n;
-        const int p = sh.pp[j], q = sh.qq[j];
-        if (p < 0) continue;
-        const double c = sh.cs[j], s = sh.sn[j];
-        const double ap = A[row * ld + p], aq = A[row * ld + q];
-        A[row * ld + p] = (row == q) ? 0.0 : c * ap - s * aq;
-        A[row * ld + q] = (row == p) ? 0.0 : s * ap + c * aq;
-        if (V) {
+      if (V) {  // V <- V R: columns of each pair
+        for (int idx = tid; idx < npairs * n; idx += TH) {
+          const int k = idx / n, row = idx - k * n;
+          const int p = sh.pp[k], q = sh.qq[k];
+          if (q < 0) continue;
+          const double c = sh.cs[k], s = sh.sn[k];
           const double vp = V[row * ld + p], vq = V[row * ld + q];
           V[row * ld + p] = c * vp - s * vq;
           V[row * ld + q] = s * vp + c * vq;
