@@ -336,8 +336,9 @@ ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const
  * keep s_j >= tau max_j s_j (nothing if max s <= 0), B = S~^-1/2 U~^T k_z[i]
  * U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi in [0, (1 + rho) g_max];
  * ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).  Cyclic Jacobi in
- * FP64.  scratch: ntb*nv*nv doubles for nv <= 96, ntb*(nv*nv + 2*nv*(nv+1)) above
- * (the two Jacobi matrices then live in it instead of LDS). */
+ * FP64.  scratch: ntb*nv*nv doubles for nv <= 96, ntb*(nv*nv + nv*(nv+1)) for
+ * 96 < nv <= 128 (the eigenvector matrix then lives in it instead of LDS) and
+ * ntb*(nv*nv + 2*nv*(nv+1)) above (both Jacobi matrices). */
 ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max,
                             double tau, double rho, double* dos_dev, int32_t* ranks_dev, double* scratch,
                             void* stream);

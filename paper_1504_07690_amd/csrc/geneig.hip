@@ -12,8 +12,9 @@
 // (Golub & Van Loan, symmetric 2x2 Schur), then the rows of every pair are rotated,
 // then the columns (and the eigenvector columns).  The pivot entries are set to
 // exactly zero.  A sweep starts only while off(A)_F > 1e-14 ||A||_F.
-// The matrix and its eigenvectors live in LDS for N_v <= 96 (2 * 96 * 97 doubles)
-// and in the point's global scratch above that (N_v <= 256); the N_v x r1 product
+// The matrix and its eigenvectors live in LDS for N_v <= 96 (2 * 96 * 97 doubles), the
+// matrix alone up to N_v = 128 (eigenvectors in the point's global scratch), both in
+// global scratch above that (N_v <= 256); the N_v x r1 product
 // Z^T Z U~ S~^-1/2 goes through the same per-point scratch.
 #include "ssm_kernels.h"
 
@@ -22,7 +23,7 @@ namespace ssm {
 namespace {
 
 constexpr int GE_MAX_THREADS = 1024;
-constexpr int GE_LDS_NV = 96;   // largest N_v whose two matrices sit in LDS
+constexpr int GE_LDS_NV = 96;   // largest N_v whose two matrices sit in LDS (geneig_lds_matrices)
 constexpr int GE_MAX_NV = 256;
 constexpr int GE_MAX_SWEEPS = 40;
 
@@ -40,13 +41,19 @@ struct GeShared {
   int* misc;      // [0] = r1
 };
 
-// Small arrays in LDS; A and V (n x (n+1) each) in LDS too, or at `big` (global).
-__device__ void ge_layout(GeShared& sh, double* lds, int n, double* big, int threads) {
+// Small arrays in LDS; A and V (n x (n+1) each) in LDS as geneig_lds_matrices says, the
+// rest at `glob` (the point's global scratch).
+__device__ void ge_layout(GeShared& sh, double* lds, int n, double* glob, int threads) {
   const int ld = n + 1;
   double* small = lds;
-  if (big) {
-    sh.A = big;
-    sh.V = big + n * ld;
+  const int mats = geneig_lds_matrices(n);
+  if (mats == 0) {
+    sh.A = glob;
+    sh.V = glob + n * ld;
+  } else if (mats == 1) {
+    sh.A = lds;
+    sh.V = glob;
+    small = lds + n * ld;
   } else {
     sh.A = lds;
     sh.V = lds + n * ld;
@@ -215,7 +222,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
   const double* kz = k_z + i * nn;
   double* tmat = scratch + i * (int64_t)geneig_scratch_doubles(nv);
   GeShared sh;
-  ge_layout(sh, lds, n, nv > GE_LDS_NV ? tmat + nn : nullptr, TH);
+  ge_layout(sh, lds, n, tmat + nn, TH);
 
   for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
@@ -379,7 +386,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
   double* ktg = ug + nn;                                                    // Kt = U^T K_Z U
   double* tg = ug + 2 * nn;                                                 // products
   GeShared sh;
-  ge_layout(sh, lds, n, nv > GE_LDS_NV ? ug + 3 * nn : nullptr, TH);
+  ge_layout(sh, lds, n, ug + 3 * nn, TH);
   double* f = sh.scale;  // F(s_j) for every j (0 when dropped)
   double* kwb = kw_bar + i * nn;
   double* kzb = kz_bar + i * nn;
@@ -530,7 +537,7 @@ int geneig_threads(int nv) { return nv <= 48 ? 256 : nv <= GE_LDS_NV ? 512 : GE_
 
 size_t geneig_lds_bytes(int nv) {
   const size_t n = (size_t)nv, ld = n + 1;
-  const size_t mats = nv > GE_LDS_NV ? 0 : 2 * n * ld;
+  const size_t mats = (size_t)geneig_lds_matrices(nv) * n * ld;
   return (mats + 2 * GE_MAX_NV + GE_MAX_NV + (size_t)geneig_threads(nv)) * sizeof(double) +
          (GE_MAX_NV + GE_MAX_NV + 4) * sizeof(int);
 }

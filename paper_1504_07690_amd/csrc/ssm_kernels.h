@@ -100,13 +100,16 @@ hipError_t launch_gram_pairs(int is_f32, int64_t n, int nv, int npairs, const vo
 // Algorithm 4 + trace (geneig.hip).
 // Per-point FP64 scratch of launch_geneig_trace / launch_geneig_backward: the
 // products, plus the two Jacobi matrices when N_v > 96 (they no longer fit in LDS).
+// Jacobi matrices (n x (n+1) doubles each) held in LDS: both up to N_v = 96, the matrix
+// being diagonalised alone up to N_v = 128 (its eigenvectors in global scratch), none above.
+__host__ __device__ inline int geneig_lds_matrices(int nv) { return nv <= 96 ? 2 : nv <= 128 ? 1 : 0; }
 __host__ __device__ inline int64_t geneig_scratch_doubles(int nv) {
   const int64_t n = nv;
-  return n * n + (nv > 96 ? 2 * n * (n + 1) : 0);
+  return n * n + (2 - geneig_lds_matrices(nv)) * n * (n + 1);
 }
 __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
   const int64_t n = nv;
-  return 3 * n * n + (nv > 96 ? 2 * n * (n + 1) : 0);
+  return 3 * n * n + (2 - geneig_lds_matrices(nv)) * n * (n + 1);
 }
 // nvh > 0 adds the hybrid correction of Algorithm 6 from k_c (ntb x nvh x nv), trw (ntb)
 // with hscr (ntb * nvh * nv doubles) as scratch.
