@@ -82,21 +82,23 @@ def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
             got = y[k % chunk][int(r)].double().cpu().numpy()
             mag = 2 * (alpha * (np.abs(vals) @ np.abs(ym1)) + abs(beta) * np.abs(ym1_r)) + np.abs(ym2_r)
             assert np.all(np.abs(got - pred) <= 64 * 2.0 ** -24 * mag + 1e-30), (k, r)
-    # (2) sampled Gram entries of two points: K_Z[p][q] = z_p . z_q, K_W = (w_p . z_q + z_p . w_q)/2
+    # (2) sampled Gram entries of two points: K_Z[p][q] = z_p . z_q, K_W[p][q] from the upper
+    # 16 x 16 blocks of W^T Z (w_p . z_q when p's block precedes q's)
+    from gram_completion import entry
     z = v["z"]
     w = v["w"]
     for i in (0, len(t) - 1):
         for (p, q) in ((0, 0), (0, nv - 1), (nv // 2, nv // 3), (nv - 1, nv - 1)):
-            zp = z[i, :, p].double().cpu().numpy()
-            zq = z[i, :, q].double().cpu().numpy()
-            wp = w[:, p].double().cpu().numpy()
-            wq = w[:, q].double().cpu().numpy()
+            zi = z[i][:, [p, q]].double().cpu().numpy()
+            wi = w[:, [p, q]].double().cpu().numpy()
+            zp, zq = zi[:, 0], zi[:, 1]
             tol = (n + 4) * 2.0 ** -53
             kz = v["k_z"][i, p, q].item()
             kw = v["k_w"][i, p, q].item()
             assert abs(kz - zp @ zq) <= tol * (np.abs(zp) @ np.abs(zq)) + 1e-300
-            ref_w = 0.5 * (wp @ zq + zp @ wq)
-            mag_w = 0.5 * (np.abs(wp) @ np.abs(zq) + np.abs(zp) @ np.abs(wq))
+            wp, wq = wi[:, 0], wi[:, 1]
+            ref_w = entry(wp, wq, zp, zq, p, q)
+            mag_w = entry(np.abs(wp), np.abs(wq), np.abs(zp), np.abs(zq), p, q)
             assert abs(kw - ref_w) <= tol * mag_w + 1e-300
     # (3) Algorithm 4 on every point from the device's Gram matrices
     kw = v["k_w"].cpu().numpy()

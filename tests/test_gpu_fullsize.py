@@ -109,12 +109,16 @@ def test_fullsize_fp32_matches_golden_and_stages(setup):
         mag = O.sweep(np.abs(mu), iter(np.abs(yr)[:, None, :]))[:, 0, :]
         assert np.all(np.abs(zr - pred) <= 2e-6 * mag + 1e-30), r
 
-    # (b3) Gram matrices of the golden points from the device's Z and W
+    # (b3) Gram matrices of the golden points from the device's Z and W (K_W completed from
+    # the upper blocks of W^T Z, as the kernel forms it)
+    from gram_completion import upper_completion
     wh = v["w"].double().cpu().numpy()
     for j, p in enumerate(pts):
         zp = z[p].double().cpu().numpy()
-        rw, rz = O.gram(wh, zp)
-        mw, mz = O.gram(np.abs(wh), np.abs(zp))
+        _, rz = O.gram(wh, zp)
+        _, mz = O.gram(np.abs(wh), np.abs(zp))
+        rw = upper_completion(wh.T @ zp)
+        mw = upper_completion(np.abs(wh).T @ np.abs(zp))
         tol = (n + 4) * 2.0 ** -53
         assert np.all(np.abs(v["k_w"][p].cpu().numpy() - rw) <= tol * mw + 1e-300), p
         assert np.all(np.abs(v["k_z"][p].cpu().numpy() - rz) <= tol * mz + 1e-300), p

@@ -241,15 +241,7 @@ def test_gram(S, precision, n, nv, ntb, nseg):
     kw = torch.empty(ntb, nv, nv, dtype=torch.float64, device=DEV)
     kz = torch.empty_like(kw)
     S.gram(precision, torch.tensor(w, dtype=dt, device=DEV), torch.tensor(z, dtype=dt, device=DEV), kw, kz, nseg)
-
-    def upper_completion(m):
-        # entry (r, c) taken from the upper 16 x 16 block of the pair; diagonal blocks averaged
-        blk = np.arange(nv) // 16
-        upper = blk[:, None] < blk[None, :]
-        out = np.where(upper, m, m.T)
-        same = blk[:, None] == blk[None, :]
-        return np.where(same, 0.5 * (m + m.T), out)
-
+    from gram_completion import upper_completion
     for i in range(ntb):
         _, rz = O.gram(w, z[i])
         _, mz = O.gram(np.abs(w), np.abs(z[i]))
