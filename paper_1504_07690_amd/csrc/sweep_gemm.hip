@@ -423,52 +423,68 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k); rb2
   // holds the second k-step of a single-product unit
   f32x2 rb[8], rb2[8];
+  // Loop-invariant addressing, so that a unit adds only degree offsets that are the same
+  // for the whole wave.  Rows past arows and columns past e are read from the last valid
+  // row or column: they only feed outputs that are never stored.  Degrees past kc are
+  // read from degree kc - 1 against coefficients that are zero there.
+  const int c2 = (tid & 127) * 2;
+  const int wkb = __builtin_amdgcn_readfirstlane(tid >> 7) * 8;  // this wave's 8 degrees of B
+  const uint32_t qcol = (uint32_t)((q0 + c2 < e) ? q0 + c2 : e - 2);
+  const __bf16* a_hi[2];
+  const __bf16* a_lo[2];
+  int a_k[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int piece = tid + 512 * h;
+    const int64_t i = (i0 + (piece >> 2) < arows) ? i0 + (piece >> 2) : arows - 1;
+    a_k[h] = (piece & 3) * 8;
+    a_hi[h] = chi + i * ldk + a_k[h];
+    a_lo[h] = clo + i * ldk + a_k[h];
+  }
   auto load_unit = [&](int u) {
     const bool three = u < nk3;
     const int k0 = unit_k0(u);
+    if (k0 + (three ? X3_BK : 2 * X3_BK) <= kc) {  // the whole unit lies inside the chunk
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int piece = tid + 512 * h;
-      const int64_t i = i0 + (piece >> 2);
-      const int k = k0 + (piece & 3) * 8;
-      const int k2 = three ? k : k + X3_BK;
-      const __bf16* tab2 = three ? clo : chi;
-      u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (i < arows && k < kc) {
-        vh = *(const u16x8*)(chi + i * ldk + k);
-        if (k + 8 > kc) {  // entries past the chunk belong to the next chunk
+      for (int h = 0; h < 2; ++h) {
+        ra_hi[h] = *(const u16x8*)(a_hi[h] + k0);
+        ra_lo[h] = three ? *(const u16x8*)(a_lo[h] + k0) : *(const u16x8*)(a_hi[h] + k0 + X3_BK);
+      }
+    } else {  // the chunk's last unit: coefficients past kc belong to the next chunk
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = k0 + a_k[h];
+        const int k2 = three ? k : k + X3_BK;
+        const __bf16* p2 = three ? a_lo[h] + k0 : a_hi[h] + k0 + X3_BK;
+        u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (k < kc) {
+          vh = *(const u16x8*)(a_hi[h] + k0);
 #pragma unroll
           for (int j = 0; j < 8; ++j)
             if (k + j >= kc) vh[j] = 0;
         }
-      }
-      if (i < arows && k2 < kc) {
-        vl = *(const u16x8*)(tab2 + i * ldk + k2);
-        if (k2 + 8 > kc) {
+        if (k2 < kc) {
+          vl = *(const u16x8*)p2;
 #pragma unroll
           for (int j = 0; j < 8; ++j)
             if (k2 + j >= kc) vl[j] = 0;
         }
+        ra_hi[h] = vh;
+        ra_lo[h] = vl;
       }
-      ra_hi[h] = vh;
-      ra_lo[h] = vl;
     }
-    const int c2 = (tid & 127) * 2;
-    const int kq = k0 + (tid >> 7) * 8;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = kq + j;
-      f32x2 v = {0.f, 0.f};
-      if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
-      rb[j] = v;
+      const int k = k0 + wkb + j;
+      const float* row = y + (int64_t)(k < kc ? k : kc - 1) * e;
+      rb[j] = *(const f32x2*)(row + qcol);
     }
     if (!three) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int k = kq + X3_BK + j;
-        f32x2 v = {0.f, 0.f};
-        if (k < kc && q0 + c2 < e) v = *(const f32x2*)(y + (int64_t)k * e + q0 + c2);
-        rb2[j] = v;
+        const int k = k0 + X3_BK + wkb + j;
+        const float* row = y + (int64_t)(k < kc ? k : kc - 1) * e;
+        rb2[j] = *(const f32x2*)(row + qcol);
       }
     }
   };
@@ -485,7 +501,6 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       *(u16x8*)(ahi + o) = ra_hi[h];
       *(u16x8*)(alo + o) = ra_lo[h];
     }
-    const int c2 = (tid & 127) * 2;
     const int ch = tid >> 7;
     const int sw = tid & 1;  // odd lanes store their second element first
 #pragma unroll
@@ -651,6 +666,7 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t nt_pad = (ntiles + 7) / 8 * 8;
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (e < 2 || e % 2 || e >= ((int64_t)1 << 32) || arows < ntb) return hipErrorInvalidValue;  // 32-bit column offsets
   hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo, ldk,
                      arows, y, z, accumulate, mt, (int)ntiles, k3, m3);
   return hipGetLastError();
