@@ -257,6 +257,20 @@ typedef double (*ssm_scalar_fn)(double x, void* user);
 ssm_status ssm_trace_weights(double lo, double hi, int32_t nt, int64_t n, double sigma, double a,
                              double sigma_tilde, ssm_scalar_fn f, void* user, double* w_host);
 
+/* Algorithm 8 for f(x) = exp(-beta x) by the exact real-line deconvolution of Eq.
+ * (deconvolv): G * e^{-beta s} = e^{beta^2 sigma^2/2} e^{-beta s} for the unit-mass Gaussian G
+ * of width sigma, so f~(s) = e^{-beta^2 sigma^2/2} e^{-beta s} with no window and no periodic
+ * extension (the exponential's periodic extension would not decay in Fourier space).
+ * w_host[i] = N (hi - lo)/nt f~(t_i) on the nt midpoints of [lo, hi] (host, nt doubles),
+ * and 0 where t_i < spec_lo - beta sigma^2 - 10 sigma for a lower bound spec_lo of the
+ * spectrum (-INFINITY for none): the regularised DOS there is below e^{-50} of its values
+ * in exact arithmetic, and for beta > 0 the weights grow like e^{-beta t}, amplifying the
+ * estimate's rounding (in the FP32 modes by orders of magnitude).  Accurate when
+ * (hi - lo)/nt is below sigma and [lo, hi] covers every eigenvalue minus beta sigma^2 by
+ * several sigma.  SSM_ERR_ARG for non-finite or out-of-range arguments. */
+ssm_status ssm_trace_weights_exp(double lo, double hi, int32_t nt, int64_t n, double sigma, double beta,
+                                 double spec_lo, double* w_host);
+
 /* ------------------------------------------------------------------------
  * Stage calls: one step of the hot path each, on caller device buffers.
  * They enqueue on `stream` and return without synchronising.

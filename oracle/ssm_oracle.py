@@ -380,3 +380,23 @@ def trace_weights(f, n: int, lo: float, hi: float, nt: int, sigma: float, a: flo
     fk = np.where(np.abs(k) <= k_c, hk / gk, 0.0)
     f_tilde = np.fft.ifft(fk).real
     return n * (2.0 / nt) * hw * f_tilde
+
+
+def trace_weights_exp(beta: float, n: int, lo: float, hi: float, nt: int, sigma: float,
+                      spec_lo: float = -math.inf):
+    """Weights w_i with Tr exp(-beta A) ~= sum_i w_i phi~(t_i), by the exact real-line
+    deconvolution of Eq. (deconvolv): G * e^{-beta s} = e^{beta^2 sigma^2 / 2} e^{-beta s} for
+    the unit-mass Gaussian G of width sigma, so f~(s) = e^{-beta^2 sigma^2 / 2} e^{-beta s},
+    and w_i = N dt f~(t_i) on the nt midpoints of [lo, hi] (dt = (hi - lo)/nt, A's units).
+    No periodic extension or window: the exponential grows without bound off the spectrum,
+    and its periodic extension would not decay in Fourier space.  The sum is the midpoint
+    rule for sum_j (f~ * G)(lambda_j) = sum_j e^{-beta lambda_j}; it needs the grid to cover
+    each lambda_j - beta sigma^2 (the tilted Gaussian's centre) by several sigma.
+    Given a lower bound spec_lo of the spectrum, the weights below spec_lo - beta sigma^2 -
+    10 sigma are 0: the regularised DOS there is below e^{-50} of its values in exact
+    arithmetic, and for beta > 0 the weights grow like e^{-beta t}, so they would only
+    amplify the estimate's rounding."""
+    dt = (hi - lo) / nt
+    t = lo + dt * (np.arange(nt) + 0.5)
+    w = n * dt * np.exp(-0.5 * (beta * sigma) ** 2 - beta * t)
+    return np.where(t >= spec_lo - beta * sigma * sigma - 10.0 * sigma, w, 0.0)

@@ -76,6 +76,8 @@ _SIGS = {
     "ssm_get_backward_stats": (C.c_int, [_P, C.POINTER(ssm_backward_stats)]),
     "ssm_trace_weights": (C.c_int, [C.c_double, C.c_double, C.c_int32, C.c_int64, C.c_double, C.c_double,
                                     C.c_double, SCALAR_FN, _P, C.POINTER(C.c_double)]),
+    "ssm_trace_weights_exp": (C.c_int, [C.c_double, C.c_double, C.c_int32, C.c_int64, C.c_double, C.c_double,
+                                        C.c_double, C.POINTER(C.c_double)]),
     "ssm_coefficients": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int64, _P, C.c_int32, C.c_int32,
                                    _P, _P, _P]),
     "ssm_gaussian_block": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, _P, _P]),

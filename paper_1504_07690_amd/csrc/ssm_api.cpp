@@ -1094,6 +1094,26 @@ ssm_status ssm_get_views(const ssm_ctx* c, ssm_views* out) {
 // division happens in the wavenumber domain so that rounding of h is amplified
 // only at the wavenumbers where the Gaussian-damped DOS is itself negligible.
 // ---------------------------------------------------------------------------
+ssm_status ssm_trace_weights_exp(double lo, double hi, int32_t nt, int64_t n, double sigma, double beta,
+                                 double spec_lo, double* w_host) {
+  if (!w_host) return fail(SSM_ERR_ARG, "w must be non-NULL");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) return fail(SSM_ERR_ARG, "need finite lo < hi");
+  if (nt < 1) return fail(SSM_ERR_ARG, "nt must be >= 1");
+  if (n < 1) return fail(SSM_ERR_ARG, "n must be >= 1");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(SSM_ERR_ARG, "sigma must be > 0");
+  if (!std::isfinite(beta)) return fail(SSM_ERR_ARG, "beta must be finite");
+  if (std::isnan(spec_lo)) return fail(SSM_ERR_ARG, "spec_lo must not be NaN");
+  const double dt = (hi - lo) / nt;
+  const double scale = (double)n * dt * std::exp(-0.5 * (beta * sigma) * (beta * sigma));
+  const double t_cut = spec_lo - beta * sigma * sigma - 10.0 * sigma;
+  for (int i = 0; i < nt; ++i) {
+    const double t = lo + dt * (i + 0.5);
+    w_host[i] = t >= t_cut ? scale * std::exp(-beta * t) : 0.0;
+    if (!std::isfinite(w_host[i])) return fail(SSM_ERR_NONFINITE, "weight %d overflows", i);
+  }
+  return SSM_OK;
+}
+
 ssm_status ssm_trace_weights(double lo, double hi, int32_t nt, int64_t n, double sigma, double a, double sigma_tilde,
                              ssm_scalar_fn f, void* user, double* w_host) {
   if (!f || !w_host) return fail(SSM_ERR_ARG, "f and w must be non-NULL");

@@ -225,6 +225,16 @@ def dos_autograd(values: torch.Tensor, row_ptr: torch.Tensor, col_idx: torch.Ten
     return SpectrumSweep.apply(values, row_ptr, col_idx, n, opts)
 
 
+def trace_weights_exp(beta, *, lo, hi, nt, n, sigma, spec_lo=-np.inf) -> np.ndarray:
+    """Weights of Tr exp(-beta A) by the exact real-line deconvolution, zero below
+    spec_lo - beta sigma^2 - 10 sigma (ssm_trace_weights_exp)."""
+    w = np.zeros(int(nt), dtype=np.float64)
+    A.check(A.lib.ssm_trace_weights_exp(float(lo), float(hi), int(nt), int(n), float(sigma), float(beta),
+                                        float(spec_lo), w.ctypes.data_as(C.POINTER(C.c_double))),
+            "ssm_trace_weights_exp")
+    return w
+
+
 def trace_weights(f, *, lo, hi, nt, n, sigma, a=0.9, sigma_tilde=0.016) -> np.ndarray:
     """Algorithm 8 weights (host, in the library): Tr f(A) ~= sum_i w_i dos_i."""
     cb = A.SCALAR_FN(lambda x, _u: float(f(x)))

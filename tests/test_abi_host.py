@@ -262,6 +262,29 @@ def test_trace_weights_reproduce_exact_trace():
     assert abs(w @ O.exact_dos(lam, t, sigma) - np.sum(dense * dense)) < 1e-11 * np.sum(dense * dense)
 
 
+@pytest.mark.parametrize("beta,nt", [(0.0, 10), (1.0, 400), (-0.7, 1000)])
+def test_trace_weights_exp_match_oracle(beta, nt):
+    from paper_1504_07690_amd import ssm as S
+    lo, hi, n, sigma = -3.0, 9.0, 5000, 0.04
+    w = S.trace_weights_exp(beta, lo=lo, hi=hi, nt=nt, n=n, sigma=sigma)
+    ref = O.trace_weights_exp(beta, n, lo, hi, nt, sigma)
+    assert np.all(np.abs(w - ref) <= 1e-14 * np.abs(ref))
+    w = S.trace_weights_exp(beta, lo=lo, hi=hi, nt=nt, n=n, sigma=sigma, spec_lo=-1.0)
+    ref = O.trace_weights_exp(beta, n, lo, hi, nt, sigma, spec_lo=-1.0)
+    assert np.array_equal(w == 0, ref == 0) and np.all(np.abs(w - ref) <= 1e-14 * np.abs(ref))
+
+
+def test_trace_weights_exp_validate(A):
+    w = (C.c_double * 4)()
+    inf = float("inf")
+    assert A.lib.ssm_trace_weights_exp(1.0, 0.0, 4, 10, 0.1, 1.0, -inf, w) == A.SSM_ERR_ARG
+    assert A.lib.ssm_trace_weights_exp(0.0, 1.0, 0, 10, 0.1, 1.0, -inf, w) == A.SSM_ERR_ARG
+    assert A.lib.ssm_trace_weights_exp(0.0, 1.0, 4, 10, 0.0, 1.0, -inf, w) == A.SSM_ERR_ARG
+    assert A.lib.ssm_trace_weights_exp(0.0, 1.0, 4, 10, 0.1, float("nan"), -inf, w) == A.SSM_ERR_ARG
+    assert A.lib.ssm_trace_weights_exp(0.0, 1.0, 4, 10, 0.1, 1.0, float("nan"), w) == A.SSM_ERR_ARG
+    assert A.lib.ssm_trace_weights_exp(-1e6, 1.0, 4, 10, 0.1, 1.0, -inf, w) == A.SSM_ERR_NONFINITE
+
+
 def test_trace_weights_validate():
     from paper_1504_07690_amd import ssm as S
     from paper_1504_07690_amd._abi import SSMError

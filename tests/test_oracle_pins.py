@@ -416,6 +416,33 @@ def test_trace_weights_exact_dos(name):
     assert abs(w @ phi - ref) < 1e-12 * abs(ref)
 
 
+@pytest.mark.parametrize("beta", [0.0, 0.3, 1.0])
+def test_trace_weights_exp_exact_dos(beta):
+    """The real-line deconvolution for exp(-beta x): applied to the exact regularised DOS of
+    a 27-point lognormal stencil it returns sum_j exp(-beta lambda_j) (beta = 0: N, the
+    DOS's unit mass), the midpoint rule on Gaussian integrands being exact to rounding once
+    the step is below sigma."""
+    a = WL.stencil27_lognormal(8, np.random.default_rng(5))
+    lam = np.linalg.eigvalsh(a.to_dense())
+    lo, hi = WL.interval(a)
+    sigma = 0.005 * 0.5 * (hi - lo)
+    nt = 2000
+    t = lo + (hi - lo) / nt * (np.arange(nt) + 0.5)
+    w = O.trace_weights_exp(beta, a.n, lo, hi, nt, sigma)
+    exact = np.exp(-beta * lam).sum()
+    assert abs(w @ O.exact_dos(lam, t, sigma) - exact) <= 1e-12 * exact
+    # cut below a lower bound of the spectrum (here the Gershgorin one): still exact
+    g_lo, _ = WL.gershgorin(a)
+    wc = O.trace_weights_exp(beta, a.n, lo, hi, nt, sigma, spec_lo=g_lo)
+    assert np.count_nonzero(wc) < nt
+    assert abs(wc @ O.exact_dos(lam, t, sigma) - exact) <= 1e-12 * exact
+    # a grid too coarse for sigma loses it: the step matters
+    coarse = O.trace_weights_exp(beta, a.n, lo, hi, 150, 0.02 * 0.5 * (hi - lo))
+    tc = lo + (hi - lo) / 150 * (np.arange(150) + 0.5)
+    if beta > 0:
+        assert abs(coarse @ O.exact_dos(lam, tc, 0.02 * 0.5 * (hi - lo)) - exact) > 1e-6 * exact
+
+
 def test_trace_weights_gaussian_semigroup():
     """h a Gaussian of width s > sigma: the deconvolved f~ is the Gaussian of width
     sqrt(s^2 - sigma^2) (Eq. deconvolv), checked on the grid."""
