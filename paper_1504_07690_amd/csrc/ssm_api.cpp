@@ -593,8 +593,9 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
                                     (double*)c->z, ch > 0, st);
       else if (p.precision == SSM_FP32_BF16X3)
         err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
-                                       c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0, (const float*)c->y,
-                                       (float*)c->z, ch > 0, c->k3 - k_first, nb, st);
+                                       c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0,
+                                       (int64_t)(p.nt - p0) * pl.ldk - k_first, (const float*)c->y, (float*)c->z,
+                                       ch > 0, c->k3 - k_first, nb, st);
       else if (p.precision == SSM_FP32)
         err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
                                     (const float*)c->y, (float*)c->z, ch > 0, st);
@@ -968,7 +969,8 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
     else
       err = ssm::launch_sweep_bf16x3(e, p.nt, len, (const __bf16*)(ws + L.chit) + (int64_t)a_lo * L.ldkt,
                                      (const __bf16*)(ws + L.clot) + (int64_t)a_lo * L.ldkt, L.ldkt, m1 - a_lo,
-                                     (const float*)c->z, (float*)ybar, 0, p.nt, c->k3 - a_lo, st);
+                                     (int64_t)(m1 - a_lo) * L.ldkt, (const float*)c->z, (float*)ybar, 0, p.nt,
+                                     c->k3 - a_lo, st);
     if (err != hipSuccess) return hip_fail(err, "transposed sweep");
     SSM_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
     if (pl.ckpt) {
@@ -1263,8 +1265,10 @@ ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, 
                            const void* y, void* z, int32_t accumulate, int32_t k3, void* stream) {
   if (!chi || !clo || !y || !z) return fail(SSM_ERR_ARG, "chi, clo, y, z must be non-NULL");
   if (e < 1 || kc < 1 || ntb < 1 || ldk < kc || ldk % 8 || e % 4) return fail(SSM_ERR_ARG, "need e % 4 == 0, ldk >= kc, ldk % 8 == 0");
-  if (((uintptr_t)chi | (uintptr_t)clo | (uintptr_t)y) % 16) return fail(SSM_ERR_ARG, "pointers must be 16-byte aligned");
+  if (((uintptr_t)chi | (uintptr_t)clo | (uintptr_t)y | (uintptr_t)z) % 16) return fail(SSM_ERR_ARG, "pointers must be 16-byte aligned");
+  if ((int64_t)ntb * ldk >= ((int64_t)1 << 30)) return fail(SSM_ERR_ARG, "split tables above 2^30 entries");
   hipError_t err = ssm::launch_sweep_bf16x3(e, kc, ntb, (const __bf16*)chi, (const __bf16*)clo, ldk, ntb,
+                                            (int64_t)(ntb - 1) * ldk + (kc + 7) / 8 * 8,
                                             (const float*)y, (float*)z, accumulate, k3, ntb, (hipStream_t)stream);
   return err == hipSuccess ? SSM_OK : hip_fail(err, "split sweep GEMM");
 }

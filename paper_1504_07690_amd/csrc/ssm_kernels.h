@@ -75,14 +75,16 @@ hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t
                              const float* y, float* z, int accumulate, hipStream_t stream);
 
 // Split-BF16 sweep: chi/clo [i][ldk] (k contiguous, ldk % 8 == 0, 16-byte aligned rows),
-// arows = rows of chi/clo readable from the pointers.
+// arows = rows of chi/clo readable from the pointers, a_elems = bf16 values readable from
+// each pointer (at least (arows - 1) ldk + kc rounded up to 8: rows are read in 8-value
+// pieces; reads past it return zeros).  e % 4 == 0, z 16-byte aligned.
 // k3: three products on the first k3 contraction indices of the launch (rounded up to
 // whole 32-wide k-steps), Chi^T Yhi alone on the rest; k3 >= kc: three everywhere.
 // m3: 256-row output tiles starting at or past row m3 take the single product
 // throughout (m3 >= ntb: no such tile).
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
-                               int64_t arows, const float* y, float* z, int accumulate, int k3, int m3,
-                               hipStream_t stream);
+                               int64_t arows, int64_t a_elems, const float* y, float* z, int accumulate, int k3,
+                               int m3, hipStream_t stream);
 size_t sweep_bf16x3_lds_bytes();
 hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo,
                                      int64_t ldk, int ntp, hipStream_t stream);

@@ -356,22 +356,23 @@ __global__ void __launch_bounds__(256) sweep_bf16_kernel(int64_t e, int kc, int 
 // MFMA blocks (128 accumulators, so two waves share a SIMD).  The coefficients
 // arrive pre-split in k-contiguous tables chi/clo [i][ldk]; the Y tile is split in
 // registers while being transposed (a thread reads 8 consecutive k of 2 elements and
-// writes, per element, 8 k of hi and of lo as 16-byte LDS stores; odd lanes store their
-// second element first, so that each store of a wave covers even and odd rows, which fall
-// in different halves of the bank window).  LDS holds two
-// stages of the four 256 x 32 BF16 tiles (128 KB); rows are 64 bytes and the 16-byte
-// k-chunk c of row r sits at chunk c ^ ((r >> 2) & 3), so that the 16 rows read by
-// a quarter-wave fall in distinct banks.  One barrier per k-step: the next tile's
-// global loads are issued right after it, and stored to the other stage after the
-// MFMAs of the current one.
+// writes, per element, 8 k of hi and of lo as 16-byte LDS stores).  LDS holds two stages
+// of the four 256 x 32 BF16 tiles (128 KB); rows are 64 bytes and the 16-byte k-chunk c
+// of row r sits at chunk c ^ ((r >> 2) & 3).  Element r of the Y tile lives in row
+// r ^ ((r >> 1) & 1): a store instruction (element 2t + c from lane t) then covers rows
+// of both parities, which fall in different halves of the bank window, and an operand
+// read covers the same rows as in element order, permuted within groups of four; the
+// counters show no bank conflicts for either.  One barrier per 32-degree unit.
 //
-// Three products on the first k3 degrees of the launch (rounded up to whole k-steps),
-// one (Chi^T Yhi) on the rest: past the last degree whose coefficients reach 2^-8 of
-// the largest, the single product's rounding (at most 2^-8 relative) stays under 2^-16
-// of the largest term, the level the three products leave on the leading degrees.  The
-// two kinds of k-step run as two straight loops over the same accumulators.  In the
-// transposed sweep the degrees are the output rows: tiles whose rows all lie at or past
-// m3 take the single product throughout.
+// Global loads go through buffer resources (a wave-uniform base and a 32-bit lane
+// offset), which keeps 64-bit addresses out of the vector registers.  Degrees past kc
+// get a resource with no records and read as zeros, so the coefficients there (of the
+// next chunk, or past the tables' end, which also read as zeros) meet exact zeros, and
+// every unit takes the same code.  The three-product units load one unit ahead of the
+// LDS store that consumes them; the single-product units load two units ahead into two
+// alternating register sets, with no conditions inside their loop, so that the waits of
+// a store cover only its own set's loads.
+//
 // ---------------------------------------------------------------------------
 constexpr int X3_BM = 256, X3_BN = 256, X3_BK = 32;
 constexpr int X3_TILE = 256 * X3_BK;  // bf16 per LDS tile
@@ -386,15 +387,17 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 // element offset of 16-byte chunk c (0..3) of row r in a 256 x 32 tile
 __device__ __forceinline__ int x3_off(int r, int c) { return r * X3_BK + ((c ^ ((r >> 2) & 3)) << 3); }
+// LDS row of element r of the Y tile: lane t stores elements 2t + c (c = 0, 1) into rows
+// 2t + (c ^ (t & 1)), so that each store instruction of a wave covers rows of both parities
+__device__ __forceinline__ int x3_brow(int r) { return r ^ ((r >> 1) & 1); }
 
 __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, int ntb,
                                                            const __bf16* __restrict__ chi,
                                                            const __bf16* __restrict__ clo, int64_t ldk,
-                                                           int64_t arows, const float* __restrict__ y,
+                                                           int64_t arows, int64_t a_elems, const float* __restrict__ y,
                                                            float* __restrict__ z, int accumulate, int mt,
                                                            int nt_tiles, int k3, int m3) {
   extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
-  // stage s: Ahi, Alo, Bhi, Blo at (4 s + 0..3) * X3_TILE
   __bf16* lds = (__bf16*)x3_lds;
   int m_tile, n_tile;
   tile_coords(mt, nt_tiles, m_tile, n_tile);
@@ -406,122 +409,96 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   const int wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;
 
-  // The k range runs as units: unit u < nk3 is one three-product k-step (32 degrees at
-  // 32 u); each later unit is two single-product k-steps (64 degrees), whose two hi tiles
-  // take the hi and lo slots of a stage, so the tail runs half as many barriers.
-  const int nk = (kc + X3_BK - 1) / X3_BK;
-  // three products on the first k3 degrees, and only in tiles that hold one of the
-  // first m3 output rows (the transposed sweep's rows are degrees)
-  const int nk3 = (k3 <= 0 || i0 >= m3) ? 0 : (k3 >= kc ? nk : (k3 + X3_BK - 1) / X3_BK);
-  const int nu = nk3 + (nk - nk3 + 1) / 2;
-  auto unit_k0 = [&](int u) { return u < nk3 ? X3_BK * u : X3_BK * nk3 + 2 * X3_BK * (u - nk3); };
+  const int nu = (kc + X3_BK - 1) / X3_BK;
+  const int nk3 = (k3 <= 0 || i0 >= m3) ? 0 : (k3 >= kc ? nu : (k3 + X3_BK - 1) / X3_BK);
 
-  // A staging: 256 rows x 4 chunks per tile = 1024 pieces; thread t moves pieces t and
-  // t + 512 (row = piece / 4, chunk = piece % 4): into ra_hi from chi, into ra_lo from
-  // clo (three-product unit) or from chi 32 degrees on (single-product unit)
-  u16x8 ra_hi[2], ra_lo[2];
-  // B staging: elements c2 = (t % 128) * 2, +1; k-chunk t / 128 (8 consecutive k); rb2
-  // holds the second k-step of a single-product unit
-  f32x2 rb[8], rb2[8];
-  // Loop-invariant addressing, so that a unit adds only degree offsets that are the same
-  // for the whole wave.  Rows past arows and columns past e are read from the last valid
-  // row or column: they only feed outputs that are never stored.  Degrees past kc are
-  // read from degree kc - 1 against coefficients that are zero there.
+  struct Staging {
+    u16x8 ra_hi[2], ra_lo[2];
+    f32x2 rb[8];
+  };
+  Staging S0, S1;
   const int c2 = (tid & 127) * 2;
-  const int wkb = __builtin_amdgcn_readfirstlane(tid >> 7) * 8;  // this wave's 8 degrees of B
-  const uint32_t qcol = (uint32_t)((q0 + c2 < e) ? q0 + c2 : e - 2);
-  const __bf16* a_hi[2];
-  const __bf16* a_lo[2];
-  int a_k[2];
+  const int bch = __builtin_amdgcn_readfirstlane(tid >> 7);  // this wave's 8 degrees of B: 8 bch .. 8 bch + 7
+  // Loads go through buffer resources: a lane adds a 32-bit byte offset to a wave-uniform
+  // base.  Degrees past kc get a resource with no records, so their Y values read as zero
+  // (the coefficients there are then multiplied by exact zeros); coefficient reads past the
+  // end of the tables read as zero as well.
+  const uint32_t boff = (uint32_t)(((q0 + c2 < e) ? c2 : e - 2 - q0) * 4);
+  uint32_t aoff[2];
+  const int a_k = (tid & 3) * 8;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int piece = tid + 512 * h;
     const int64_t i = (i0 + (piece >> 2) < arows) ? i0 + (piece >> 2) : arows - 1;
-    a_k[h] = (piece & 3) * 8;
-    a_hi[h] = chi + i * ldk + a_k[h];
-    a_lo[h] = clo + i * ldk + a_k[h];
+    aoff[h] = (uint32_t)((i * ldk + a_k) * 2);
   }
-  auto load_unit = [&](int u) {
-    const bool three = u < nk3;
-    const int k0 = unit_k0(u);
-    if (k0 + (three ? X3_BK : 2 * X3_BK) <= kc) {  // the whole unit lies inside the chunk
+  const int64_t abytes = a_elems * 2;  // the tables' extent from chi / clo
+  auto rsrc = [](const void* p, int64_t bytes) {
+    const int nrec = bytes <= 0 ? 0 : (bytes < 0x7FFFFFFF ? (int)bytes : 0x7FFFFFFF);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, nrec, 0x00020000);
+  };
+  auto load_t = [&](Staging& S, int u, auto three) {
+    constexpr bool THREE = decltype(three)::value;
+    const int k0 = X3_BK * u;
+    const auto rh = rsrc(chi + k0, abytes - (int64_t)k0 * 2);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        ra_hi[h] = *(const u16x8*)(a_hi[h] + k0);
-        ra_lo[h] = three ? *(const u16x8*)(a_lo[h] + k0) : *(const u16x8*)(a_hi[h] + k0 + X3_BK);
-      }
-    } else {  // the chunk's last unit: coefficients past kc belong to the next chunk
+    for (int h = 0; h < 2; ++h)
+      S.ra_hi[h] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)aoff[h], 0, 0));
+    if constexpr (THREE) {
+      const auto rl = rsrc(clo + k0, abytes - (int64_t)k0 * 2);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = k0 + a_k[h];
-        const int k2 = three ? k : k + X3_BK;
-        const __bf16* p2 = three ? a_lo[h] + k0 : a_hi[h] + k0 + X3_BK;
-        u16x8 vh = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (k < kc) {
-          vh = *(const u16x8*)(a_hi[h] + k0);
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (k + j >= kc) vh[j] = 0;
-        }
-        if (k2 < kc) {
-          vl = *(const u16x8*)p2;
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (k2 + j >= kc) vl[j] = 0;
-        }
-        ra_hi[h] = vh;
-        ra_lo[h] = vl;
-      }
+      for (int h = 0; h < 2; ++h)
+        S.ra_lo[h] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)aoff[h], 0, 0));
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int k = k0 + wkb + j;
-      const float* row = y + (int64_t)(k < kc ? k : kc - 1) * e;
-      rb[j] = *(const f32x2*)(row + qcol);
-    }
-    if (!three) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + X3_BK + wkb + j;
-        const float* row = y + (int64_t)(k < kc ? k : kc - 1) * e;
-        rb2[j] = *(const f32x2*)(row + qcol);
-      }
+      const int k = k0 + 8 * bch + j;
+      const auto rj = rsrc(y + (int64_t)(k < kc ? k : 0) * e + q0, k < kc ? 1024 : 0);
+      S.rb[j] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rj, (int)boff, 0, 0));
     }
   };
-  auto store_unit = [&](int st, int u) {
-    const bool three = u < nk3;
+  auto load_unit = [&](Staging& S, int u) {
+    if (u < nk3) load_t(S, u, std::true_type{});
+    else load_t(S, u, std::false_type{});
+  };
+  auto store_t = [&](int st, int u, Staging& S, auto three) {
+    constexpr bool THREE = decltype(three)::value;
     __bf16* ahi = lds + (4 * st + 0) * X3_TILE;
     __bf16* alo = lds + (4 * st + 1) * X3_TILE;
     __bf16* bhi = lds + (4 * st + 2) * X3_TILE;
     __bf16* blo = lds + (4 * st + 3) * X3_TILE;
+    if (X3_BK * u + X3_BK > kc) {  // the unit that straddles kc: coefficients past it are not this chunk's
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (X3_BK * u + a_k + j >= kc) S.ra_hi[h][j] = S.ra_lo[h][j] = 0;
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int piece = tid + 512 * h;
       const int o = x3_off(piece >> 2, piece & 3);
-      *(u16x8*)(ahi + o) = ra_hi[h];
-      *(u16x8*)(alo + o) = ra_lo[h];
+      *(u16x8*)(ahi + o) = S.ra_hi[h];
+      if constexpr (THREE) *(u16x8*)(alo + o) = S.ra_lo[h];
     }
-    const int ch = tid >> 7;
-    const int sw = tid & 1;  // odd lanes store their second element first
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const int cc = c ^ sw;
       bf16x8 h, l;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         __bf16 hh, ll;
-        split_bf16(cc ? rb[j][1] : rb[j][0], hh, ll);
+        split_bf16(S.rb[j][c], hh, ll);
         h[j] = hh;
-        if (three) {
-          l[j] = ll;
-        } else {
-          l[j] = (__bf16)(cc ? rb2[j][1] : rb2[j][0]);  // hi of the second k-step
-        }
+        l[j] = ll;
       }
-      const int o = x3_off(c2 + cc, ch);
+      const int o = x3_off(x3_brow(c2 + c), bch);
       *(bf16x8*)(bhi + o) = h;
-      *(bf16x8*)(blo + o) = l;
+      if constexpr (THREE) *(bf16x8*)(blo + o) = l;
     }
+  };
+  auto store_unit = [&](int st, int u, Staging& S) {
+    if (u < nk3) store_t(st, u, S, std::true_type{});
+    else store_t(st, u, S, std::false_type{});
   };
 
   f32x16 acc[4][2];
@@ -532,7 +509,6 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  // one 32-degree k-step of MFMAs on LDS tiles (ah, al) x (bh, bl)
   auto mfma_step = [&](const __bf16* ahi, const __bf16* alo, const __bf16* bhi, const __bf16* blo, auto three) {
     constexpr bool THREE = decltype(three)::value;
 #pragma unroll
@@ -541,7 +517,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       bf16x8 bh[2], bl[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int o = x3_off(wn * 64 + b * 32 + (lane & 31), ch);
+        const int o = x3_off(x3_brow(wn * 64 + b * 32 + (lane & 31)), ch);
         bh[b] = *(const bf16x8*)(bhi + o);
         if constexpr (THREE) bl[b] = *(const bf16x8*)(blo + o);
       }
@@ -551,7 +527,6 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
         const bf16x8 ah = *(const bf16x8*)(ahi + o);
         if constexpr (THREE) {
           const bf16x8 al = *(const bf16x8*)(alo + o);
-          // small products first, the three products of one block two MFMAs apart
 #pragma unroll
           for (int b = 0; b < 2; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b], acc[a][b], 0, 0, 0);
@@ -564,48 +539,102 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       }
     }
   };
-  load_unit(0);
-  store_unit(0, 0);
-  if (nu > 1) load_unit(1);
+  // Prefetch depth: the three-product units (three times the matrix work per unit) load one
+  // unit ahead of the store that consumes it; the single-product units load two units ahead,
+  // alternating between two register staging sets.
+  load_unit(S0, 0);
+  store_unit(0, 0, S0);
+  if (nu > 1) load_unit(S0, 1);
   __syncthreads();
-  // one unit: MFMAs on stage u & 1, then the next unit into the other stage (last read
-  // before the previous barrier), barrier, and the loads of the unit after it
-  auto unit = [&](int u, auto three) {
-    constexpr bool THREE = decltype(three)::value;
-    const int st = u & 1;
-    const __bf16* s0 = lds + (4 * st + 0) * X3_TILE;
-    const __bf16* s1 = lds + (4 * st + 1) * X3_TILE;
-    const __bf16* s2 = lds + (4 * st + 2) * X3_TILE;
-    const __bf16* s3 = lds + (4 * st + 3) * X3_TILE;
-    if constexpr (THREE) {
-      mfma_step(s0, s1, s2, s3, std::true_type{});
-    } else {
-      mfma_step(s0, s0, s2, s2, std::false_type{});
-      mfma_step(s1, s1, s3, s3, std::false_type{});
-    }
-    if (u + 1 < nu) store_unit(st ^ 1, u + 1);
-    __syncthreads();
-    if (u + 2 < nu) load_unit(u + 2);
-  };
   int u = 0;
-  for (; u < nk3; ++u) unit(u, std::true_type{});
-  for (; u < nu; ++u) unit(u, std::false_type{});
+  // three-product units whose next two units are three-product units as well
+  for (; u + 2 < nk3; ++u) {
+    const __bf16* s = lds + 4 * (u & 1) * X3_TILE;
+    mfma_step(s, s + X3_TILE, s + 2 * X3_TILE, s + 3 * X3_TILE, std::true_type{});
+    store_t((u + 1) & 1, u + 1, S0, std::true_type{});
+    __syncthreads();
+    load_t(S0, u + 2, std::true_type{});
+  }
+  // the last (at most two) three-product units
+  for (; u < nk3; ++u) {
+    const __bf16* s = lds + 4 * (u & 1) * X3_TILE;
+    mfma_step(s, s + X3_TILE, s + 2 * X3_TILE, s + 3 * X3_TILE, std::true_type{});
+    if (u + 1 < nu) store_unit((u + 1) & 1, u + 1, S0);
+    __syncthreads();
+    if (u + 2 < nu) load_unit(S0, u + 2);
+  }
+  // single-product units: S0 holds unit u + 1, S1 takes unit u + 2
+  load_t(S1, u + 2, std::false_type{});
+  // No conditions inside the loop (units past the chunk load as zeros and are never read), so
+  // that each store waits only for its own set's loads.
+  auto tail_unit = [&](int u, Staging& Sn) {
+    const __bf16* s = lds + 4 * (u & 1) * X3_TILE;
+    mfma_step(s, s + X3_TILE, s + 2 * X3_TILE, s + 3 * X3_TILE, std::false_type{});
+    store_t((u + 1) & 1, u + 1, Sn, std::false_type{});
+    // keep the next unit's conversions below the barrier: hoisted above it, they would wait
+    // for the loads issued one unit earlier
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+    load_t(Sn, u + 3, std::false_type{});
+  };
+  for (; u + 1 < nu; u += 2) {
+    tail_unit(u, S0);
+    tail_unit(u + 1, S1);
+  }
+  if (u < nu) {
+    const __bf16* s = lds + 4 * (u & 1) * X3_TILE;
+    mfma_step(s, s + X3_TILE, s + 2 * X3_TILE, s + 3 * X3_TILE, std::false_type{});
+  }
 
+  // Epilogue through LDS, in four passes of 64 rows: the waves holding the pass's rows write
+  // their accumulators to a 64 x 256 FP32 tile (rows padded by 4 floats), then every thread
+  // stores 16-byte pieces of whole rows, so each store instruction of a wave covers one
+  // contiguous 1 KB row segment of Z.
+  float* zt = (float*)x3_lds;
+  constexpr int ZLD = X3_BN + 4;
+  __syncthreads();  // the last unit's operand reads are done
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int pass = 0; pass < 4; ++pass) {
+    if (wm == (pass >> 1)) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int64_t col = q0 + wn * 64 + b * 32 + (lane & 31);
-      if (col >= e) continue;
+      for (int ah = 0; ah < 2; ++ah) {
+        const int a = 2 * (pass & 1) + ah;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = i0 + wm * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row < ntb) {
-          float* p = z + row * e + col;
-          *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+        for (int b = 0; b < 2; ++b) {
+          const int col = wn * 64 + b * 32 + (lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = ah * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            zt[row * ZLD + col] = acc[a][b][r];
+          }
         }
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = tid + 512 * it;  // 64 rows x 64 pieces of 4 floats
+      const int row = idx >> 6, c4 = (idx & 63) * 4;
+      const int64_t grow = i0 + 64 * pass + row;
+      const int64_t gcol = q0 + c4;
+      if (grow < ntb && gcol < e) {
+        const f32x4 v = *(const f32x4*)&zt[row * ZLD + c4];
+        float* p = z + grow * e + gcol;
+        if (gcol + 4 <= e) {
+          if (accumulate) {
+            const f32x4 old = *(const f32x4*)p;
+            *(f32x4*)p = old + v;
+          } else {
+            *(f32x4*)p = v;
+          }
+        } else {
+          for (int j = 0; j < 4 && gcol + j < e; ++j) p[j] = accumulate ? p[j] + v[j] : v[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // chi/clo[i][k] = split of the FP64 coefficient c[k][i] (i < nt, k < m1), zero padded;
@@ -655,8 +684,8 @@ hipError_t launch_sweep_f64(int64_t e, int kc, int ntb, const double* c, int64_t
 size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * 4 * X3_TILE * sizeof(__bf16); }
 
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
-                               int64_t arows, const float* y, float* z, int accumulate, int k3, int m3,
-                               hipStream_t stream) {
+                               int64_t arows, int64_t a_elems, const float* y, float* z, int accumulate, int k3,
+                               int m3, hipStream_t stream) {
   const size_t lds = sweep_bf16x3_lds_bytes();
   hipError_t err = hipFuncSetAttribute((const void*)sweep_bf16x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
@@ -666,9 +695,11 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t nt_pad = (ntiles + 7) / 8 * 8;
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  if (e < 2 || e % 2 || e >= ((int64_t)1 << 32) || arows < ntb) return hipErrorInvalidValue;  // 32-bit column offsets
+  // e % 4 == 0: 16-byte stores of Z rows; the tables' byte offsets are 32-bit resource offsets
+  if (e < 4 || e % 4 || ((uintptr_t)z % 16) || arows < ntb || a_elems < (arows - 1) * ldk + (kc + 7) / 8 * 8 || a_elems * 2 > 0x7FFFFFFF)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(sweep_bf16x3_kernel, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo, ldk,
-                     arows, y, z, accumulate, mt, (int)ntiles, k3, m3);
+                     arows, a_elems, y, z, accumulate, mt, (int)ntiles, k3, m3);
   return hipGetLastError();
 }
 
