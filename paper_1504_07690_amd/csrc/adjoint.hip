@@ -233,7 +233,12 @@ __global__ void __launch_bounds__(256) reverse_step_kernel(int64_t n, int L, int
       }
       V gv[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) gv[j] = x[(int64_t)cols[j] * L + q];
+      for (int j = 0; j < 8; ++j) {  // padded slots issue no gather
+        if (p + j < len)
+          gv[j] = x[(int64_t)cols[j] * L + q];
+        else
+          gv[j] = (V)(T)0;
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) acc += vals[j] * gv[j];
     }
@@ -251,7 +256,12 @@ __global__ void __launch_bounds__(256) reverse_step_kernel(int64_t n, int L, int
     for (int u = 0; u < 4; ++u) cols[u] = (j + u < len) ? col_idx[p0 + j + u] : (int)rs;
     V yv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) yv[u] = y[(int64_t)cols[u] * L + q];
+    for (int u = 0; u < 4; ++u) {
+      if (j + u < len)
+        yv[u] = y[(int64_t)cols[u] * L + q];
+      else
+        yv[u] = (V)(T)0;
+    }
     double sum[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {

@@ -27,8 +27,9 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // [x per_xcd, (x+1) per_xcd), swept in order.  A stencil neighbour a few planes
 // away was then gathered by the same XCD shortly before, and is found in its L2.
 // Up to 8 CSR entries of a row are fetched before their gathers are issued, so the
-// gathers of one row are in flight together.  The block read once (xprev, d) and the
-// block written are streamed with non-temporal hints, leaving the cache to the
+// gathers of one row are in flight together; the slots past the row's end are masked
+// off (a 7-entry stencil row issues 7 gathers, not 8).  The block read once (xprev, d)
+// and the block written are streamed with non-temporal hints, leaving the cache to the
 // gathered block x.
 //
 // out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null; the reverse
@@ -77,7 +78,12 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int6
     }
     V g[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) g[j] = x[(int64_t)cols[j] * nvv + q];
+    for (int j = 0; j < 8; ++j) {  // padded slots issue no gather
+      if (p + j < p1)
+        g[j] = x[(int64_t)cols[j] * nvv + q];
+      else
+        g[j] = (V)(T)0;
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
   }
