@@ -209,6 +209,15 @@ def test_stage_calls_validate(A):
     assert A.lib.ssm_geneig_trace(8, 4, 1, 1, -1.0, 1e-7, 1e-3, 1, None, 1, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_coefficients(1.0, -1.0, 0.1, 10, 1, 4, 10, 1, None, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_gaussian_block(1, 10, 8, 3, 1, None) == A.SSM_ERR_ARG
+    # split sweep: (e, kc, ntb, chi, clo, ldk, y, z, accumulate, k3, stream); every check runs
+    # on the host before any device work (the pointers below are never dereferenced)
+    ok = 1 << 20
+    assert A.lib.ssm_sweep_split(100, 4, 8, ok, ok, 8, ok, ok + 4, 0, 0, None) == A.SSM_ERR_ARG  # z misaligned
+    assert A.lib.ssm_sweep_split(100, 4, 8, ok, ok, 8, ok + 8, ok, 0, 0, None) == A.SSM_ERR_ARG  # y misaligned
+    assert A.lib.ssm_sweep_split(102, 4, 8, ok, ok, 8, ok, ok, 0, 0, None) == A.SSM_ERR_ARG      # e % 4
+    assert A.lib.ssm_sweep_split(100, 12, 8, ok, ok, 8, ok, ok, 0, 0, None) == A.SSM_ERR_ARG     # ldk < kc
+    assert A.lib.ssm_sweep_split(100, 4, 8, ok, ok, 12, ok, ok, 0, 0, None) == A.SSM_ERR_ARG     # ldk % 8
+    assert A.lib.ssm_sweep_split(100, 4, 1 << 20, ok, ok, 1 << 10, ok, ok, 0, 0, None) == A.SSM_ERR_ARG  # > 2^30
 
 
 def test_status_strings(A):
