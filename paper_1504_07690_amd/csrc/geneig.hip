@@ -137,12 +137,16 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
       __syncthreads();
       // blocks (j, k), j <= k, numbered row by row
       for (int idx = tid; idx < nblocks; idx += TH) {
-        int j = 0, rem = idx;
-        while (rem >= npairs - j) {
-          rem -= npairs - j;
+        // row j of the upper triangle starts at j P - j (j - 1) / 2 (P = npairs): the quadratic
+        // inverted in float (within one of the row for P <= 128), then corrected by one step
+        const int P2 = 2 * npairs + 1;
+        int j = (int)((P2 - sqrtf((float)(P2 * P2 - 8 * idx))) * 0.5f);
+        j = j < 0 ? 0 : (j >= npairs ? npairs - 1 : j);
+        if (j * npairs - j * (j - 1) / 2 > idx)
+          --j;
+        else if ((j + 1) * npairs - (j + 1) * j / 2 <= idx)
           ++j;
-        }
-        const int k = j + rem;
+        const int k = j + (idx - (j * npairs - j * (j - 1) / 2));
         const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
         const double cj = sh.cs[j], sj = sh.sn[j], ck = sh.cs[k], sk = sh.sn[k];
         if (qj < 0 || qk < 0) {  // a one-element pair: a row, a column or one entry
