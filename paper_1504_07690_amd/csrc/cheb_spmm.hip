@@ -48,8 +48,12 @@ __device__ __forceinline__ double vdot<f64x2>(const f64x2& u, const f64x2& v) {
 // DOTS: the workgroup also writes dots[2 lblock] = <out, x> and dots[2 lblock + 1] =
 // <x, x> over its slices (FP64 sums of exact products), for the Chebyshev moments of
 // Algorithm 2 by the product identity T_j T_k = (T_{j+k} + T_{|j-k|}) / 2.
+// Workgroups of 256 lanes: 512 and 1024 gave the same time on a ring of blocks (each step
+// reading the block the step before wrote), and 1024 slowed the FP64 and moment variants.
+constexpr int CS_THREADS = 256;
+
 template <typename T, typename V, bool DOTS>
-__global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
+__global__ void __launch_bounds__(CS_THREADS) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
                                                         const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col_idx,
                                                         const T* __restrict__ val, T a, T b, T c,
@@ -64,6 +68,9 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int6
   const int64_t gid = valid ? gid0 : 0;  // idle lanes of a DOTS block recompute slice 0 and store nothing
   const int64_t r = gid / nvv;
   const int q = (int)(gid - r * nvv);
+  V xp = (V)(T)0, dd = (V)(T)0;  // streamed operands first: they do not depend on the row's CSR
+  if (xprev) xp = __builtin_nontemporal_load(&xprev[gid]);
+  if (d) dd = __builtin_nontemporal_load(&d[gid]);
   const int p0 = row_ptr[r];
   const int p1 = row_ptr[r + 1];
   V acc = (V)(T)0;
@@ -89,15 +96,15 @@ __global__ void __launch_bounds__(256) cheb_step_kernel(int64_t n, int nvv, int6
   }
   const V xo = x[gid];
   V res = a * acc + b * xo;
-  if (xprev) res += c * __builtin_nontemporal_load(&xprev[gid]);
-  if (d) res += __builtin_nontemporal_load(&d[gid]);
+  if (xprev) res += c * xp;
+  if (d) res += dd;
   if (valid) __builtin_nontemporal_store(res, &out[gid]);
   if constexpr (DOTS) {
-    __shared__ double red[2][256];
+    __shared__ double red[2][CS_THREADS];
     red[0][threadIdx.x] = valid ? vdot<V>(res, xo) : 0.0;
     red[1][threadIdx.x] = valid ? vdot<V>(xo, xo) : 0.0;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = CS_THREADS / 2; st > 0; st >>= 1) {
       if ((int)threadIdx.x < st) {
         red[0][threadIdx.x] += red[0][threadIdx.x + st];
         red[1][threadIdx.x] += red[1][threadIdx.x + st];
@@ -164,15 +171,15 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
                   T c, const T* x, const T* xprev, const T* d, T* out, double* dots, hipStream_t stream) {
   const int nvv = nv / VEC;
   const int64_t threads = n * nvv;
-  const int64_t nblocks = (threads + 255) / 256;
+  const int64_t nblocks = (threads + CS_THREADS - 1) / CS_THREADS;
   const int64_t per_xcd = (nblocks + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (dots)
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv,
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, true>), dim3((unsigned)(per_xcd * 8)), dim3(CS_THREADS), 0, stream, n, nvv,
                        nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
                        (V*)out, dots);
   else
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, false>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, nvv,
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, false>), dim3((unsigned)(per_xcd * 8)), dim3(CS_THREADS), 0, stream, n, nvv,
                        nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
                        (V*)out, nullptr);
   return hipGetLastError();
@@ -196,7 +203,7 @@ hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const
 
 int64_t cheb_step_blocks(int64_t n, int nv, int is_f32) {
   const int nvv = nv / (is_f32 ? 4 : 2);
-  return (n * nvv + 255) / 256;
+  return (n * nvv + CS_THREADS - 1) / CS_THREADS;
 }
 
 hipError_t launch_moments(int64_t nblocks, const double* dots, int s0, int count, double* sums,
