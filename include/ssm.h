@@ -322,7 +322,8 @@ ssm_status ssm_split_coefficients(const double* c, int64_t ldc, int32_t nt, int3
  * (row i at chi + i*ldk, k = 0..kc-1 from the pointer; ldk % 8 == 0; chi, clo, y
  * and z 16-byte aligned; of row ntb-1 the first kc entries rounded up to a multiple of 8
  * are read, and ntb*ldk must stay below 2^30 entries); y and z float, e % 4 == 0;
- * SSM_ERR_ARG otherwise.
+ * SSM_ERR_ARG otherwise.  ldk % 64 == 0 (128-byte rows) is the fastest stride: the
+ * kernel reads 64-byte pieces of each row, which then never straddle two cache lines.
  * k3: degrees k < k3 (rounded up to a multiple of 32) take the three products
  * Chi^T Yhi + Chi^T Ylo + Clo^T Yhi, the others Chi^T Yhi alone; k3 >= kc: three
  * everywhere.  ssm_dos sets k3 one past the last degree whose coefficients reach
