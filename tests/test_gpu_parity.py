@@ -373,6 +373,32 @@ def test_end_to_end_small_workspace_plans(S, cfg1_oracle):
     assert np.abs(dos - full).max() <= 1e-11 * full.max()
 
 
+def test_end_to_end_small_workspace_split(S, cfg1_oracle):
+    """The split-BF16 path under budgets that force several sweep-point passes or a ring of
+    Chebyshev blocks: its sweep launches then start inside the coefficient tables (a later
+    pass's rows of the 128-byte-row tables, a later chunk's degrees) and accumulate into Z.
+    Each estimate meets the 1e-3 L1 gate against the oracle and stays within 1e-4 of the
+    maximum of the single-pass split-BF16 estimate (the chunked FP32 sums round differently)."""
+    from paper_1504_07690_amd._abi import SSMError
+    wl, ref = cfg1_oracle
+    full, *_ = _run(S, wl, "bf16x3")
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
+    need = S.workspace_size(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, nt=wl.nt,
+                            precision="bf16x3")
+    plans = []
+    for frac in (0.6, 0.35, 0.2):
+        try:
+            dos, _, _, st = _run(S, wl, "bf16x3", budget=int(frac * need))
+        except SSMError as err:
+            print(f"budget {frac} of {need} bytes: no plan ({err})")
+            continue
+        print(f"budget {frac}: {st['passes']} passes, chunk {st['chunk']}, batch {st['batch']}")
+        plans.append((st["passes"], st["chunk"]))
+        assert _l1(dos, ref["dos"]) <= 1e-3
+        assert np.abs(dos - full).max() <= 1e-4 * full.max()
+    assert any(p > 1 for p, _ in plans) and any(c < wl.degree + 1 for _, c in plans), plans
+
+
 def test_end_to_end_ragged_anderson(S):
     """16^3 Anderson lattice: ragged tiles in every kernel (N = 4096, N_v = 20, N_t = 101)."""
     a = WL.anderson_3d(16, _rng(8).uniform(-2, 2, 16 ** 3))
