@@ -82,9 +82,9 @@ def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
             got = y[k % chunk][int(r)].double().cpu().numpy()
             mag = 2 * (alpha * (np.abs(vals) @ np.abs(ym1)) + abs(beta) * np.abs(ym1_r)) + np.abs(ym2_r)
             assert np.all(np.abs(got - pred) <= 64 * 2.0 ** -24 * mag + 1e-30), (k, r)
-    # (2) sampled Gram entries of two points: K_Z[p][q] = z_p . z_q, K_W[p][q] from the upper
-    # 16 x 16 blocks of W^T Z (w_p . z_q when p's block precedes q's)
-    from gram_completion import entry
+    # (2) sampled Gram entries of two points against the oracle's K_Z = Z^T Z and
+    # K_W = (W^T Z + Z^T W)/2; the kernel forms only the upper 16 x 16 blocks of W^T Z, so K_W
+    # may also differ by half the asymmetry |w_p . z_q - w_q . z_p| / 2 of the rounded Z
     z = v["z"]
     w = v["w"]
     for i in (0, len(t) - 1):
@@ -92,20 +92,106 @@ def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
             zi = z[i][:, [p, q]].double().cpu().numpy()
             wi = w[:, [p, q]].double().cpu().numpy()
             zp, zq = zi[:, 0], zi[:, 1]
+            wp, wq = wi[:, 0], wi[:, 1]
             tol = (n + 4) * 2.0 ** -53
             kz = v["k_z"][i, p, q].item()
             kw = v["k_w"][i, p, q].item()
             assert abs(kz - zp @ zq) <= tol * (np.abs(zp) @ np.abs(zq)) + 1e-300
-            wp, wq = wi[:, 0], wi[:, 1]
-            ref_w = entry(wp, wq, zp, zq, p, q)
-            mag_w = entry(np.abs(wp), np.abs(wq), np.abs(zp), np.abs(zq), p, q)
-            assert abs(kw - ref_w) <= tol * mag_w + 1e-300
+            ref_w = 0.5 * (wp @ zq + wq @ zp)
+            mag_w = 0.5 * (np.abs(wp) @ np.abs(zq) + np.abs(wq) @ np.abs(zp))
+            asym = 0.5 * abs(wp @ zq - wq @ zp)
+            assert abs(kw - ref_w) <= tol * mag_w + asym + 1e-300
     # (3) Algorithm 4 on every point from the device's Gram matrices
     kw = v["k_w"].cpu().numpy()
     kz = v["k_z"].cpu().numpy()
     ref = np.array([O.geneig_trace(kw[i], kz[i], gmax)[0] for i in range(len(t))])
     bad = np.abs(dos - ref) > 1e-9 * gmax
     assert bad.sum() <= 1, np.nonzero(bad)
+    # (4) where the plan keeps every block: rows of Z against the oracle's sweep of the
+    # device's own blocks
+    if chunk == m + 1 and v["batch"] == len(t):
+        rows_t = torch.as_tensor(rng.integers(0, n, 4), device=DEV)
+        yr = y[:, rows_t, :].double().cpu().numpy()
+        zr = z[:, rows_t, :].double().cpu().numpy()
+        mu = O.dgc_coefficients(t, m, wl.sigma, n, wl.lo, wl.hi)
+        _assert_z_rows(zr, mu, yr, ctx.precision, ctx.stats()["split_k3"])
+
+
+def _assert_z_rows(zr, mu, yr, precision, k3):
+    """Rows of Z (points x rows x N_v) against the oracle's sweep (Algorithm 5 steps 6-8)
+    of the same rows of the device's blocks yr ((M+1) x rows x N_v), within the rounding
+    bound of the sweep's arithmetic: FP32 products and sums; for split BF16 at most
+    2^-16 |mu||y| per term below k3 (three products, each operand carried to 2^-17) and
+    2^-7 |mu||y| past it (one product of two 8-bit operands), plus the FP32 sums."""
+    kk = mu.shape[0]
+    pred = O.sweep(mu, iter(yr))
+    mag = O.sweep(np.abs(mu), iter(np.abs(yr)))
+    sums = (kk + 3) * 2.0 ** -24 * mag
+    if precision == "bf16x3":
+        k3 = max(0, min(k3, kk))
+        lead = O.sweep(np.abs(mu[:k3]), iter(np.abs(yr[:k3]))) if k3 else 0.0
+        tail = O.sweep(np.abs(mu[k3:]), iter(np.abs(yr[k3:]))) if k3 < kk else 0.0
+        tol = 2.0 ** -16 * lead + 2.0 ** -7 * tail + sums
+    elif precision == "fp32":
+        tol = sums
+    else:
+        tol = 2.0 ** -7 * mag + sums  # plain BF16 operands
+    err = np.abs(zr - pred)
+    assert np.all(err <= tol + 1e-30), float((err / (tol + 1e-30)).max())
+
+
+@pytest.mark.parametrize("cfg,degree", [(3, 64), (5, 32)])
+def test_large_split_sweep_z_rows(S, cfg, degree):
+    """The split-BF16 sweep where N N_v is so large (28 N N_v + 1024 >= 2^31) that each degree
+    of Y takes its own buffer resource: the random-graph and 27-point workloads at full N and
+    N_v with a reduced degree, eight strided sweep points.  Rows of Z against the oracle's
+    sweep of the device's own blocks, first with every block resident (one sweep launch),
+    then with a ring of fewer blocks (launches from mid-table degrees that accumulate into
+    Z); the recurrence is deterministic, so both runs see the same blocks."""
+    wl = WL.make_workload(cfg, degree=degree)
+    n, nv, m = wl.a.n, wl.nv, degree
+    assert 28 * n * nv + 1024 >= 2 ** 31
+    t = wl.t[wl.nt // 16::wl.nt // 8]
+    rng = np.random.default_rng(100 + cfg)
+    rows_t = torch.as_tensor(np.sort(rng.choice(n, 6, replace=False)), device=DEV)
+    mu = O.dgc_coefficients(t, m, wl.sigma, n, wl.lo, wl.hi)
+    csr, ctx = _ctx(S, wl, "bf16x3", t)
+    st = ctx.stats()
+    assert st["passes"] == 1 and st["chunk"] == m + 1, st
+    dos1, r1, r2 = ctx.dos()
+    v = ctx.views()
+    yr = v["y"][:, rows_t, :].double().cpu().numpy()
+    z1 = v["z"][:, rows_t, :].double().cpu().numpy()
+    k3 = ctx.stats()["split_k3"]
+    full = S.workspace_size(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, nt=len(t),
+                            precision="bf16x3", seed=wl.seed)
+    ctx.close()
+    del ctx, v
+    _free()
+    print(f"{wl.name} M={m}: resident plan, k3 {k3}, DOS max {dos1.max():.3e}")
+    _assert_z_rows(z1, mu, yr, "bf16x3", k3)
+    # a ring of fewer blocks: launches start at degrees that are multiples of 16 and add into Z
+    e_bytes = n * nv * 4
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=t, precision="bf16x3",
+                seed=wl.seed, budget=full - 17 * e_bytes, device=DEV)
+    st = ctx.stats()
+    assert st["passes"] == 1 and 16 <= st["chunk"] < m + 1 and st["chunk"] % 16 == 0, st
+    dos2, _, _ = ctx.dos()
+    st = ctx.stats()
+    assert st["sweep_launches"] == -(-(m + 1) // st["chunk"])
+    v = ctx.views()
+    k_first = (m // st["chunk"]) * st["chunk"]
+    y_last = v["y"][:, rows_t, :].double().cpu().numpy()
+    for k in range(k_first, m + 1):  # the ring's last blocks are the resident run's
+        assert np.array_equal(y_last[k % st["chunk"]], yr[k]), k
+    z2 = v["z"][:, rows_t, :].double().cpu().numpy()
+    ctx.close()
+    del ctx, v, csr
+    _free()
+    print(f"ring {st['chunk']}: {st['sweep_launches']} sweep launches; DOS L1 vs the resident plan "
+          f"{np.abs(dos2 - dos1).sum() / np.abs(dos1).sum():.2e}")
+    _assert_z_rows(z2, mu, yr, "bf16x3", k3)
+    assert np.abs(dos2 - dos1).sum() <= 1e-3 * np.abs(dos1).sum()
 
 
 @pytest.mark.parametrize("cfg,precision", [(3, "bf16x3"), (3, "bf16"), (5, "bf16x3")])

@@ -66,6 +66,27 @@ def test_fullsize_fp64_matches_golden(setup):
     assert np.array_equal(r2[pts][sig], np.array(g["r2"])[sig])
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16"])
+def test_fullsize_mixed_sweep_matches_golden(setup, precision):
+    """The benchmark's default path (split-BF16 sweep) and the plain BF16 sweep, in the
+    benchmark's plan, against the stored oracle values: split BF16 within the relative L1
+    gate of 1e-3; plain BF16 (8-bit operands) is reported against the same values and
+    held only to 2e-2."""
+    S, wl, g = setup
+    ctx = _ctx(S, wl, precision)
+    dos, r1, r2 = ctx.dos()
+    st = ctx.stats()
+    ctx.close()
+    del ctx
+    _free()
+    assert st["passes"] == 1 and st["chunk"] == wl.degree + 1 and st["batch"] == wl.nt
+    pts = np.array(g["points"])
+    ref = np.array(g["dos"])
+    l1 = np.abs(dos[pts] - ref).sum() / np.abs(ref).sum()
+    print(f"{precision} vs FP64 oracle at {pts.size} points: relative L1 {l1:.3e}; k3 {st['split_k3']}")
+    assert l1 <= (1e-3 if precision == "bf16x3" else 2e-2)
+
+
 def test_fullsize_fp32_matches_golden_and_stages(setup):
     S, wl, g = setup
     ctx = _ctx(S, wl, "fp32")
@@ -109,19 +130,21 @@ def test_fullsize_fp32_matches_golden_and_stages(setup):
         mag = O.sweep(np.abs(mu), iter(np.abs(yr)[:, None, :]))[:, 0, :]
         assert np.all(np.abs(zr - pred) <= 2e-6 * mag + 1e-30), r
 
-    # (b3) Gram matrices of the golden points from the device's Z and W (K_W completed from
-    # the upper blocks of W^T Z, as the kernel forms it)
-    from gram_completion import upper_completion
+    # (b3) Gram matrices of the golden points from the device's Z and W against the oracle's
+    # K_W = (W^T Z + Z^T W)/2 and K_Z = Z^T Z.  The kernel forms only the upper 16 x 16 blocks
+    # of W^T Z (the same matrix while W^T Z is symmetric, as it is in exact arithmetic), so K_W
+    # may also differ by half the asymmetry |W^T Z - Z^T W| / 2 of the device's rounded Z.
     wh = v["w"].double().cpu().numpy()
     for j, p in enumerate(pts):
         zp = z[p].double().cpu().numpy()
-        _, rz = O.gram(wh, zp)
-        _, mz = O.gram(np.abs(wh), np.abs(zp))
-        rw = upper_completion(wh.T @ zp)
-        mw = upper_completion(np.abs(wh).T @ np.abs(zp))
+        rw, rz = O.gram(wh, zp)
+        mw, mz = O.gram(np.abs(wh), np.abs(zp))
+        asym = 0.5 * np.abs(wh.T @ zp - zp.T @ wh)
         tol = (n + 4) * 2.0 ** -53
-        assert np.all(np.abs(v["k_w"][p].cpu().numpy() - rw) <= tol * mw + 1e-300), p
+        assert np.all(np.abs(v["k_w"][p].cpu().numpy() - rw) <= tol * mw + asym + 1e-300), p
         assert np.all(np.abs(v["k_z"][p].cpu().numpy() - rz) <= tol * mz + 1e-300), p
+        # the asymmetry is the rounding of Z, far below K_W itself
+        assert asym.max() <= 1e-5 * np.abs(rw).max(), p
 
     # (b4) Algorithm 4 on every point, from the device's Gram matrices
     kw = v["k_w"].cpu().numpy()

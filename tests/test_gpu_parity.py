@@ -232,6 +232,9 @@ def test_sweep_split_tail_single_product(S, kc, ntb, n, nv, k3):
                                            (33, 4, 1, 1), (2048, 64, 2, 7), (3000, 128, 2, 3), (1500, 256, 2, 2),
                                            (501, 200, 1, 1)])
 def test_gram(S, precision, n, nv, ntb, nseg):
+    """The stage call on independent W and Z, where W^T Z is not symmetric: the matrix the
+    call documents (the upper 16 x 16 blocks of W^T Z, mirrored, diagonal blocks
+    averaged with their transposes) and K_Z = Z^T Z."""
     rng = _rng(n + nv)
     dt = torch.float64 if precision == "fp64" else torch.float32
     w = rng.standard_normal((n, nv))
@@ -252,6 +255,36 @@ def test_gram(S, precision, n, nv, ntb, nseg):
         assert np.all(np.abs(kz[i].cpu().numpy() - rz) <= tol * mz)
         assert np.array_equal(kz[i].cpu().numpy(), kz[i].cpu().numpy().T)
         assert np.array_equal(kw[i].cpu().numpy(), kw[i].cpu().numpy().T)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nv,ntb,nseg", [(1000, 40, 3, 1), (2048, 80, 2, 3), (1500, 128, 2, 2), (700, 256, 1, 1)])
+def test_gram_against_oracle_symmetrised(S, precision, n, nv, ntb, nseg):
+    """Gram matrices on the method's path, where W^T Z is symmetric in exact arithmetic
+    (Z_i = B_i W with B_i symmetric, as g(t_i I - A) is): against the oracle's
+    K_W = (W^T Z + Z^T W)/2 and K_Z = Z^T Z, up to the FP64 sums and half the asymmetry
+    |W^T Z - Z^T W| / 2 that the rounding of Z leaves (the kernel forms the upper blocks of
+    W^T Z only)."""
+    rng = _rng(3 * n + nv)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    w = rng.standard_normal((n, nv))
+    z = np.empty((ntb, n, nv))
+    for i in range(ntb):
+        b = rng.standard_normal((n, n)) / np.sqrt(n)
+        z[i] = (b + b.T) @ w
+    if dt == torch.float32:
+        w, z = w.astype(np.float32).astype(np.float64), z.astype(np.float32).astype(np.float64)
+    kw = torch.empty(ntb, nv, nv, dtype=torch.float64, device=DEV)
+    kz = torch.empty_like(kw)
+    S.gram(precision, torch.tensor(w, dtype=dt, device=DEV), torch.tensor(z, dtype=dt, device=DEV), kw, kz, nseg)
+    tol = (n + 4) * 2.0 ** -53
+    for i in range(ntb):
+        rw, rz = O.gram(w, z[i])
+        mw, mz = O.gram(np.abs(w), np.abs(z[i]))
+        asym = 0.5 * np.abs(w.T @ z[i] - z[i].T @ w)
+        assert asym.max() <= (1e-13 if precision == "fp64" else 1e-5) * np.abs(rw).max()
+        assert np.all(np.abs(kw[i].cpu().numpy() - rw) <= tol * mw + asym + 1e-300)
+        assert np.all(np.abs(kz[i].cpu().numpy() - rz) <= tol * mz + 1e-300)
 
 
 # ----------------------------------------------------------------------------
