@@ -92,11 +92,12 @@ typedef struct ssm_params {
   int32_t nt;              /* number of sweep points N_t >= 1 */
   int32_t precision;       /* an ssm_precision */
   uint64_t seed;           /* key of the Philox generator for W when ssm_create gets no W */
-  int32_t ckpt_every;      /* s: 0, or s >= 4.  s > 0 plans for ssm_backward: one recurrence
-                              pass (every Z_i resident), and when the ring holds fewer than M+1
-                              blocks, ssm_dos also keeps the pairs (Y_0, Y_1) and (Y_{js-1},
-                              Y_{js}) (Y_k = T_k(A~)W, 1 <= j <= M/s) and the ring keeps >= s
-                              blocks, so that the backward recomputes the rest segment by segment */
+  int32_t ckpt_every;      /* s: 0, or s >= 4.  s > 0 plans for ssm_backward with a ring of fewer
+                              than M+1 blocks: the first pass of ssm_dos also keeps the pairs
+                              (Y_0, Y_1) and (Y_{js-1}, Y_{js}) (Y_k = T_k(A~)W, 1 <= j <= M/s),
+                              from which the backward recomputes the blocks segment by segment
+                              (directly into the ring when it holds s blocks, else through a
+                              second level of pairs every K_c degrees) */
   int32_t dgc;             /* nonzero: ssm_dos also forms the DGC estimate of Algorithm 2 from the
                               same recurrence (same W, M and sweep points); read it with ssm_dgc
                               (SSM_SS_DGC only) */
@@ -105,6 +106,21 @@ typedef struct ssm_params {
   int32_t nv_hybrid;       /* N~_v of Algorithm 7: 0, or a multiple of 4 with nv + nv_hybrid <= 256
                               (SSM_RESS_DGC only; 0 for SSM_SS_DGC).  The block W of ssm_create
                               then has nv + nv_hybrid columns: W, then W~ */
+  double floor_scale;      /* eta of the rounding floor of Algorithm 4's truncation (SSM_SS_DGC):
+                              step 2 also drops s_j < eta ||mu(t_i)||_2 ||W||_F^2 / sqrt(N N_v),
+                              the size of the error that the sweep's rounding leaves in W^T Z(t_i)
+                              (||mu(t_i)||_2 over l = 0..M).  Where Z(t_i) is below that error
+                              (sweep points outside the spectrum or at its far edges) K_W and K_Z
+                              are rounding and their pencil has arbitrary eigenvalues, in range
+                              included; the floor keeps nothing there.  0 selects the precision's
+                              default: none for SSM_FP64, 2^-22 for SSM_FP32, 2^-16 for
+                              SSM_FP32_BF16X3, 2^-7 for SSM_FP32_BF16SWEEP; < 0: no floor */
+  int32_t plan_batch;      /* 0: the planner chooses; > 0: sweep points per batch (pass), a
+                              multiple of 8 when below nt (SSM_SS_DGC) */
+  int32_t plan_chunk;      /* 0: the planner chooses; > 0: blocks in the ring (capped at M+1), a
+                              multiple of 16 when below M+1 (SSM_SS_DGC).  With either set,
+                              ssm_workspace_size and ssm_create return SSM_ERR_WORKSPACE when
+                              that plan does not fit the budget */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)
@@ -196,6 +212,8 @@ typedef struct ssm_views {
                         (N_v' = nv + nv_hybrid); NULL otherwise.  z is NULL and chunk
                         counts the ring's slots. */
   double* coeff_sq;  /* SSM_RESS_DGC: nu_l(t_i) of Proposition 1, same layout as coeff */
+  double* s_floor;   /* SSM_SS_DGC with a rounding floor: the nt floors of the last ssm_dos
+                        (see ssm_params.floor_scale); NULL otherwise */
 } ssm_views;
 ssm_status ssm_get_views(const ssm_ctx* ctx, ssm_views* out);
 
@@ -221,12 +239,18 @@ ssm_status ssm_destroy(ssm_ctx* ctx);
  * Arithmetic: Algorithm 4's backward and Kbar in FP64; Zbar, Ybar and Lambda in
  * the context's block type, Ybar by the context's sweep kernel; the gradient's
  * dot products and sums in FP64.
- * Needs a single-pass plan (every Z_i resident) that holds every T_k(A~)W or
- * was made with ckpt_every > 0 (SSM_ERR_UNSUPPORTED otherwise), and a previous
- * ssm_dos (SSM_ERR_STATE).  With checkpoints, T_k(A~)W of each segment of s
- * degrees is recomputed from its checkpoint pair into the context's ring
- * (M (s-2)/s extra block products).  It overwrites the context's Z blocks (and
- * ring), so the next backward needs a new ssm_dos.
+ * Needs a plan whose ring holds every T_k(A~)W or one made with ckpt_every > 0
+ * (SSM_ERR_UNSUPPORTED otherwise), and a previous ssm_dos (SSM_ERR_STATE).
+ * Batches: with several sweep-point batches (passes), each batch's Zbar feeds its
+ * own reverse recurrence and the gradients add up (the map is linear in Ybar);
+ * the batch that ssm_dos left in Z goes first, every other batch's Z is formed
+ * again by the forward recurrence and sweep (bit-identical to ssm_dos's).
+ * Checkpoints: T_k(A~)W of each segment of s degrees is recomputed from its
+ * checkpoint pair into the context's ring (M (s-2)/s extra block products); when
+ * the ring holds K_c < s blocks, a replay of the segment first keeps a pair every
+ * K_c degrees in the backward workspace (about M more block products per batch).
+ * The recomputed blocks are bit-identical to the forward's.  The backward
+ * overwrites the context's Z blocks (and ring); a later backward forms them again.
  * grad_dev: nnz doubles (device), overwritten.  workspace: device memory of
  * at least ssm_backward_workspace_size bytes, 256-byte aligned.  Synchronises. */
 ssm_status ssm_backward_workspace_size(const ssm_ctx* ctx, size_t* bytes);
@@ -238,8 +262,11 @@ ssm_status ssm_backward(ssm_ctx* ctx, const double* dos_bar_host, double* grad_d
  * recurrence with the SDDMM. */
 typedef struct ssm_backward_stats {
   double ms_total, ms_geneig, ms_zbar, ms_ybar, ms_recompute, ms_reverse;
-  int32_t segments;        /* k-segments of the reverse sweep */
-  int32_t recomputed;      /* blocks T_k(A~)W recomputed from checkpoints */
+  int32_t segments;        /* degree segments of the reverse sweep, summed over the batches */
+  int32_t recomputed;      /* blocks T_k(A~)W recomputed from checkpoints (both levels) */
+  double ms_forward;       /* forward passes that regenerated Z of the other batches */
+  int32_t passes;          /* sweep-point batches */
+  int32_t levels;          /* 0: every block resident; 1: checkpoints; 2: two checkpoint levels */
 } ssm_backward_stats;
 ssm_status ssm_get_backward_stats(const ssm_ctx* ctx, ssm_backward_stats* out);
 

@@ -29,6 +29,9 @@ Readings where the paper is silent (each also listed in the design notes):
   run's N_theta) and sets the rest to 0; M must be even (Proposition 1).
 * Algorithm 7's truncation also drops eigenvalues of K_W below the rounding
   level of its moment sum, 1e-12 sum_l |mu_l(t_i)| max|X_W,l| (see ress_dgc).
+* A sweep in limited precision leaves an error in W^T Z; Algorithm 4's truncation
+  then also drops eigenvalues of K_W below that error (rounding_floor).  The
+  oracle itself is FP64 and takes no floor unless one is passed in.
 * Algorithm 8 deconvolves with the unit-mass Gaussian (N times g_sigma),
   periodically on [-1, 1] in the rescaled variable, dropping wavenumbers k
   with exp(-(sigma^ pi k)^2 / 2) < eta (eta = 1e-10).
@@ -209,6 +212,21 @@ def gram(w: np.ndarray, z: np.ndarray):
     """K_W = (W^T Z + Z^T W)/2 and K_Z = Z^T Z for one sweep point (Eq. tracelr)."""
     wz = w.T @ z
     return 0.5 * (wz + wz.T), z.T @ z
+
+
+def rounding_floor(mu: np.ndarray, w: np.ndarray, eta: float) -> np.ndarray:
+    """Rounding floor of Algorithm 4's truncation for a sweep in limited precision
+    (a reading; the paper works in exact arithmetic): per sweep point,
+    eta * ||mu(t_i)||_2 * ||W||_F^2 / sqrt(N N_v), with ||mu(t_i)||_2 over l = 0..M.
+
+    When every term mu_l T_l(A~) W of the sweep carries a relative rounding of about eta,
+    Z(t_i) carries an error of rms size eta ||mu(t_i)||_2 per entry (the blocks' entries
+    are O(1): ||T_l(A~) W||_F <= ||W||_F), and W^T Z(t_i) one of spectral norm about
+    eta ||mu(t_i)||_2 ||W||_F^2 / sqrt(N N_v).  Eigenvalues of K_W below that are rounding;
+    step 2 of Algorithm 4 drops them with s_floor = this value.  ``mu`` has shape
+    (M + 1, N_t)."""
+    n, nv = w.shape
+    return eta * np.sqrt((np.asarray(mu) ** 2).sum(axis=0)) * float(np.sum(w * w)) / math.sqrt(n * nv)
 
 
 # ----------------------------------------------------------------------------

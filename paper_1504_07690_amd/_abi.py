@@ -32,7 +32,8 @@ class ssm_params(C.Structure):
     _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
                 ("range_slack", C.c_double), ("nv", C.c_int32), ("degree", C.c_int32), ("nt", C.c_int32),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("ckpt_every", C.c_int32), ("dgc", C.c_int32),
-                ("method", C.c_int32), ("nv_hybrid", C.c_int32)]
+                ("method", C.c_int32), ("nv_hybrid", C.c_int32), ("floor_scale", C.c_double),
+                ("plan_batch", C.c_int32), ("plan_chunk", C.c_int32)]
 
 
 class ssm_stats(C.Structure):
@@ -45,14 +46,15 @@ class ssm_stats(C.Structure):
 class ssm_backward_stats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_geneig", C.c_double), ("ms_zbar", C.c_double),
                 ("ms_ybar", C.c_double), ("ms_recompute", C.c_double), ("ms_reverse", C.c_double),
-                ("segments", C.c_int32), ("recomputed", C.c_int32)]
+                ("segments", C.c_int32), ("recomputed", C.c_int32), ("ms_forward", C.c_double),
+                ("passes", C.c_int32), ("levels", C.c_int32)]
 
 
 class ssm_views(C.Structure):
     _fields_ = [("w", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("k_w", C.c_void_p),
                 ("k_z", C.c_void_p), ("coeff", C.c_void_p), ("chunk", C.c_int32), ("batch", C.c_int32),
                 ("first_point_of_last_batch", C.c_int32), ("elem_bytes", C.c_int32),
-                ("moments", C.c_void_p), ("coeff_sq", C.c_void_p)]
+                ("moments", C.c_void_p), ("coeff_sq", C.c_void_p), ("s_floor", C.c_void_p)]
 
 
 SCALAR_FN = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)

@@ -85,6 +85,48 @@ hipError_t launch_square_coefficients(const double* mu, int64_t ldc, int nt, int
   return hipGetLastError();
 }
 
+namespace {
+
+// mun[i] = sqrt(sum_l c[l][i]^2): 64 points per workgroup, four waves splitting the degrees
+// in interleaved quarters, summed in a fixed order (deterministic)
+__global__ void __launch_bounds__(256) coefficient_norms_kernel(const double* __restrict__ c, int64_t ldc, int nt,
+                                                                int m1, double* __restrict__ mun) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (i < nt)
+    for (int l = q; l < m1; l += 4) {
+      const double v = c[(int64_t)l * ldc + i];
+      acc += v * v;
+    }
+  part[q][lane] = acc;
+  __syncthreads();
+  if (q == 0 && i < nt) mun[i] = sqrt(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+}
+
+__global__ void __launch_bounds__(256) rounding_floor_kernel(const double* __restrict__ mun, int nt, double eta,
+                                                             const double* __restrict__ w_sumsq, double inv_sqrt_e,
+                                                             double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nt) out[i] = eta * mun[i] * (w_sumsq[0] * inv_sqrt_e);
+}
+
+}  // namespace
+
+hipError_t launch_coefficient_norms(const double* c, int64_t ldc, int nt, int m1, double* mun, hipStream_t stream) {
+  hipLaunchKernelGGL(coefficient_norms_kernel, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, stream, c, ldc, nt, m1,
+                     mun);
+  return hipGetLastError();
+}
+
+hipError_t launch_rounding_floor(const double* mun, int nt, double eta, const double* w_sumsq, double inv_sqrt_e,
+                                 double* floor_out, hipStream_t stream) {
+  hipLaunchKernelGGL(rounding_floor_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, mun, nt, eta,
+                     w_sumsq, inv_sqrt_e, floor_out);
+  return hipGetLastError();
+}
+
 size_t coefficient_lds_bytes(int n_theta) { return 2 * (size_t)(n_theta + 1) * sizeof(double); }
 
 hipError_t launch_coefficients(double c0, double hw, double sigma, double inv_norm, const double* t, int nt,

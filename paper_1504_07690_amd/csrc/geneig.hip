@@ -377,7 +377,8 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
                                                                      const double* __restrict__ phibar,
                                                                      double* __restrict__ kw_bar,
                                                                      double* __restrict__ kz_bar,
-                                                                     double* __restrict__ scratch) {
+                                                                     double* __restrict__ scratch,
+                                                                     const double* __restrict__ s_floor) {
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
@@ -412,8 +413,9 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
     double smax = -INFINITY;
     for (int j = 0; j < n; ++j) smax = fmax(smax, sh.s[j]);
     int r1 = 0;
+    const double thr = s_floor ? fmax(tau * smax, s_floor[i]) : tau * smax;
     for (int j = 0; j < n; ++j) {
-      const bool keep = smax > 0.0 && sh.s[j] >= tau * smax;
+      const bool keep = smax > 0.0 && sh.s[j] >= thr;
       f[j] = keep ? 1.0 / sqrt(sh.s[j]) : 0.0;
       if (keep) sh.kidx[r1++] = j;
     }
@@ -549,12 +551,12 @@ size_t geneig_lds_bytes(int nv) {
 template <int TH>
 hipError_t launch_backward_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                              double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
-                             size_t lds, hipStream_t stream) {
+                             const double* s_floor, size_t lds, hipStream_t stream) {
   hipError_t err = hipFuncSetAttribute((const void*)geneig_backward_kernel<TH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_backward_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho,
-                     phibar, kw_bar, kz_bar, scratch);
+                     phibar, kw_bar, kz_bar, scratch, s_floor);
   return hipGetLastError();
 }
 
@@ -573,17 +575,19 @@ hipError_t launch_trace_t(int nv, int ntb, const double* k_w, const double* k_z,
 
 hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                                   double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
-                                  hipStream_t stream) {
+                                  hipStream_t stream, const double* s_floor) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   const size_t lds = geneig_lds_bytes(nv);
   switch (geneig_threads(nv)) {
     case 256:
-      return launch_backward_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, lds, stream);
+      return launch_backward_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
+                                    stream);
     case 512:
-      return launch_backward_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, lds, stream);
+      return launch_backward_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
+                                    stream);
     default:
       return launch_backward_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch,
-                                               lds, stream);
+                                               s_floor, lds, stream);
   }
 }
 

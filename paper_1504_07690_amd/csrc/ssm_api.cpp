@@ -67,6 +67,7 @@ ssm_status check_params(const ssm_params* p) {
     return fail(SSM_ERR_ARG, "need finite lo < hi (got %g, %g)", p->lo, p->hi);
   if (!std::isfinite(p->sigma) || !(p->sigma > 0)) return fail(SSM_ERR_ARG, "sigma must be finite and > 0");
   if (!std::isfinite(p->tau) || !std::isfinite(p->range_slack)) return fail(SSM_ERR_ARG, "tau, rho must be finite");
+  if (!std::isfinite(p->floor_scale)) return fail(SSM_ERR_ARG, "floor_scale must be finite");
   if (p->tau >= 1.0) return fail(SSM_ERR_ARG, "tau must be < 1");
   if (p->nv < 4 || p->nv % 4 != 0) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4 (got %d)", p->nv);
   if (p->nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d is not implemented in this build", kMaxNv);
@@ -76,6 +77,11 @@ ssm_status check_params(const ssm_params* p) {
   if (p->precision < SSM_FP64 || p->precision > SSM_FP32_BF16X3)
     return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
   if (p->ckpt_every != 0 && p->ckpt_every < 4) return fail(SSM_ERR_ARG, "ckpt_every must be 0 or >= 4");
+  if (p->plan_batch < 0 || p->plan_chunk < 0) return fail(SSM_ERR_ARG, "plan_batch and plan_chunk must be >= 0");
+  if (p->plan_batch > 0 && p->plan_batch < p->nt && p->plan_batch % 8)
+    return fail(SSM_ERR_ARG, "plan_batch below nt must be a multiple of 8 (got %d)", p->plan_batch);
+  if (p->plan_chunk > 0 && p->plan_chunk <= p->degree && p->plan_chunk % kMinChunk)
+    return fail(SSM_ERR_ARG, "plan_chunk below M+1 must be a multiple of %d (got %d)", kMinChunk, p->plan_chunk);
   if (p->method != SSM_SS_DGC && p->method != SSM_RESS_DGC) return fail(SSM_ERR_ARG, "unknown method %d", p->method);
   if (p->method == SSM_SS_DGC) {
     if (p->nv_hybrid != 0) return fail(SSM_ERR_ARG, "nv_hybrid applies to SSM_RESS_DGC only");
@@ -89,12 +95,29 @@ ssm_status check_params(const ssm_params* p) {
       return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC runs in FP64 only in this build (precision SSM_FP64)");
     if (p->ckpt_every) return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC has no adjoint in this build (ckpt_every must be 0)");
     if (p->dgc) return fail(SSM_ERR_UNSUPPORTED, "the DGC by-product is built for SSM_SS_DGC only");
+    if (p->plan_batch || p->plan_chunk) return fail(SSM_ERR_ARG, "plan_batch and plan_chunk apply to SSM_SS_DGC");
   }
   return SSM_OK;
 }
 
 double eff_tau(const ssm_params* p) { return p->tau > 0 ? p->tau : 1e-7; }
 double eff_rho(const ssm_params* p) { return p->range_slack >= 0 ? p->range_slack : 1e-3; }
+
+// eta of the rounding floor of Algorithm 4's truncation (SS-DGC): about two to four times the
+// relative rounding that one term mu_l(t_i) T_l(A~)W of the sweep carries in the precision's
+// arithmetic (FP32 products and blocks 2^-24; split BF16 about 2^-17 on the three-product
+// degrees and below 2^-16 of the largest term on the others; BF16 operands 2^-8).  FP64 takes
+// none: its floor would sit far below the tau test.
+double eff_floor_scale(const ssm_params* p) {
+  if (p->method != SSM_SS_DGC || p->floor_scale < 0) return 0.0;
+  if (p->floor_scale > 0) return p->floor_scale;
+  switch (p->precision) {
+    case SSM_FP32: return std::ldexp(1.0, -22);
+    case SSM_FP32_BF16X3: return std::ldexp(1.0, -16);
+    case SSM_FP32_BF16SWEEP: return std::ldexp(1.0, -7);
+    default: return 0.0;
+  }
+}
 
 struct Plan {
   int passes = 1, chunk = 1, batch = 1, nseg = 1;
@@ -107,7 +130,7 @@ struct Plan {
   // RESS-DGC: chunk = new blocks per round, ring of chunk + 1 slots
   bool ress = false;
   size_t off_nu = 0, off_kc = 0, off_trw = 0, off_hscr = 0, off_pw = 0, off_pz = 0, off_x = 0, off_kmu = 0,
-         off_knu = 0, off_xmax = 0, off_floor = 0;
+         off_knu = 0, off_xmax = 0, off_floor = 0, off_mun = 0;
 };
 
 // Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
@@ -173,6 +196,8 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_dos = take(p->nt * 8);
   pl.off_ranks = take(2 * (size_t)p->nt * 4);
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
+  pl.off_mun = take((size_t)p->nt * 8);
+  pl.off_floor = take((size_t)p->nt * 8);
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * pl.batch * 2 * nn * 8);
   pl.off_z = take((size_t)pl.batch * e * es);
   pl.off_y = take((size_t)pl.chunk * e * es);
@@ -256,10 +281,13 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
   Plan best;
   double best_cost = -1.0;
   const int m1 = p->degree + 1;
-  for (int passes = 1; passes <= p->nt; ++passes) {
-    if (p->ckpt_every > 0 && passes > 1) break;  // the adjoint needs every Z_i resident: one pass only
+  const int forced_passes = p->plan_batch > 0 ? (p->nt + p->plan_batch - 1) / p->plan_batch : 0;
+  for (int passes = forced_passes ? forced_passes : 1; passes <= p->nt; ++passes) {
     int batch = (p->nt + passes - 1) / passes;
-    if (passes > 1) batch = (batch + 3) / 4 * 4;  // batch starts stay 16-byte aligned in the coefficient table
+    // batch starts stay 16-byte aligned in the coefficient tables (the adjoint's transposed
+    // BF16 tables hold the points of a degree contiguously)
+    if (passes > 1) batch = (batch + 7) / 8 * 8;
+    if (forced_passes) batch = std::min(p->plan_batch, p->nt);
     if ((p->nt + batch - 1) / batch != passes) continue;  // same batch as a smaller pass count
     Plan pl;
     pl.ldc = (p->nt + 3) / 4 * 4;
@@ -272,8 +300,8 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
     pl.chunk = 0;
     layout(pl, a, p, own_w);
     const size_t fixed = pl.total;
-    int chunk = m1;
-    if (budget) {
+    int chunk = p->plan_chunk > 0 ? std::min(p->plan_chunk, m1) : m1;
+    if (budget && !p->plan_chunk) {
       const double room = (double)budget - (double)fixed;
       chunk = room > 0 ? (int)std::min<double>(m1, std::floor(room / ((double)e * es))) : 0;
       for (; chunk >= 1; --chunk) {  // the ring's size is rounded up to the alignment
@@ -283,18 +311,19 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
       }
       if (chunk < m1) chunk -= chunk % kMinChunk;  // chunk starts stay 16-byte aligned in the split tables
       if (chunk < std::min(m1, kMinChunk)) continue;
-      if (p->ckpt_every > 0 && chunk < std::min(m1, p->ckpt_every)) continue;  // the ring holds a segment
     }
     pl.chunk = chunk;
     layout(pl, a, p, own_w);
     if (budget && pl.total > budget) continue;
     const int nchunks = (m1 + chunk - 1) / chunk;
-    const double cost = passes * (p->degree * spmm_bytes) + passes * (2.0 * nchunks - 1.0) * batch * e * es;
+    // a ring that holds every block forms them in the first pass only
+    const double cost = (chunk == m1 ? 1 : passes) * (p->degree * spmm_bytes) +
+                        passes * (2.0 * nchunks - 1.0) * batch * e * es;
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;
       best = pl;
     }
-    if (!budget) break;
+    if (!budget || forced_passes) break;
     if (passes > 4096) break;
   }
   if (best_cost < 0) return fail(SSM_ERR_WORKSPACE, "no plan fits in %zu bytes of workspace", budget);
@@ -341,7 +370,9 @@ struct ssm_ctx {
   double* kmu = nullptr;    // nt x N_v'^2
   double* knu = nullptr;    // nt x N_v'^2
   double* xmax = nullptr;   // max |X_l[:N_v, :N_v]|, l <= M/2
-  double* sfloor = nullptr; // rounding floor of Algorithm 4's truncation per point
+  double* sfloor = nullptr; // rounding floor of Algorithm 4's truncation per point (null: none)
+  double* mun = nullptr;    // SS-DGC: sqrt(sum_l mu_l(t_i)^2) per point
+  double eta = 0.0;         // SS-DGC: scale of the rounding floor (0: no floor)
   std::vector<double> dos_host;
   bool have_dos = false;
   bool have_dgc = false;
@@ -421,6 +452,11 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->dos = (double*)(c->ws + pl.off_dos);
   c->ranks = (int32_t*)(c->ws + pl.off_ranks);
   c->norm = (double*)(c->ws + pl.off_norm);
+  c->eta = eff_floor_scale(p);
+  if (c->eta > 0) {
+    c->mun = (double*)(c->ws + pl.off_mun);
+    c->sfloor = (double*)(c->ws + pl.off_floor);
+  }
   if (pl.dgc_group) {
     c->dpart = (double*)(c->ws + pl.off_dpart);
     c->dsums = (double*)(c->ws + pl.off_dsums);
@@ -460,6 +496,9 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   if ((e = ssm::launch_coefficients(c0, hw, p->sigma, inv_norm, c->t, p->nt, p->degree, n_theta_for(p->degree),
                                     c->c64, c->c32, pl.ldc, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "coefficient kernel"));
+  if (c->mun && (e = ssm::launch_coefficient_norms(c->c64, pl.ldc, p->nt, p->degree + 1, c->mun, c->stream)) !=
+                    hipSuccess)
+    return bail(hip_fail(e, "coefficient norm kernel"));
   if (c->chi) {
     if ((e = ssm::launch_split_coefficients(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, pl.ldk, p->nt,
                                             c->stream)) != hipSuccess)
@@ -503,9 +542,26 @@ namespace {
 ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host);
 }
 
-ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
-  if (!c || !dos_host) return fail(SSM_ERR_ARG, "ctx and dos_host must be non-NULL");
-  if (c->pl.ress) return ress_dos(c, dos_host, ranks_host);
+namespace {
+
+struct Span { size_t b, en; int kind; };  // kind 0 recurrence, 1 sweep, 2 Gram, 3 Algorithm 4
+
+// Event bookkeeping of one ssm_dos (the context's events, recorded in order).
+struct Timeline {
+  size_t next = 0;
+  std::vector<Span> spans;
+  size_t mark() { return next++; }
+};
+
+// One pass of Algorithm 5 over sweep-point batch `pass`: the recurrence (steps 3, 9-10)
+// chunk by chunk into the ring, each chunk followed by its sweep (steps 6-8) into the
+// batch's Z.  A plan whose ring holds every block forms the blocks in its first pass only.
+// `first`: the first pass of an ssm_dos, which also keeps the checkpoint pairs and the
+// inner products of Algorithm 2.  The backward calls it again to regenerate a batch's Z:
+// the same launches in the same order, so the blocks and Z are bit-identical to the
+// forward's.  tl (may be null) records the recurrence and sweep spans.
+ssm_status forward_pass(ssm_ctx* c, int pass, bool first, Timeline* tl, int64_t& spmm_launches,
+                        int64_t& sweep_launches) {
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
   const int64_t n = c->a.n;
@@ -517,33 +573,19 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
   const int m = p.degree;
   hipStream_t st = c->stream;
-
-  // events: [0] start, then (begin, end) pairs per timed launch group
   const int nchunks = (m + 1 + pl.chunk - 1) / pl.chunk;
-  const size_t need = 2 + (size_t)pl.passes * (2 * nchunks + 2) * 2 + 4;
-  while (c->events.size() < need) {
-    hipEvent_t ev;
-    SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
-    c->events.push_back(ev);
-  }
-  size_t evi = 0;
-  struct Span { size_t b, en; int kind; };  // kind 0 rec, 1 sweep, 2 gram, 3 eig
-  std::vector<Span> spans;
-  auto mark = [&]() -> size_t { return evi++; };
-  const size_t ev_start = mark();
-  SSM_HIP(hipEventRecord(c->events[ev_start], st), "hipEventRecord");
-  int64_t spmm_launches = 0, sweep_launches = 0;
-
+  const bool resident = pl.chunk == m + 1;
   auto y_slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % pl.chunk) * e * es; };
+  auto record = [&](size_t i) { return tl ? hipEventRecord(c->events[i], st) : hipSuccess; };
   const int64_t dgc_nblocks = ssm::cheb_step_blocks(n, nv, !f64);
-  for (int pass = 0; pass < pl.passes; ++pass) {
-    const int p0 = pass * pl.batch;
-    const int nb = std::min(pl.batch, p.nt - p0);
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const int k_first = ch * pl.chunk;
-      const int k_last = std::min(m, k_first + pl.chunk - 1);
-      Span rs{mark(), 0, 0};
-      SSM_HIP(hipEventRecord(c->events[rs.b], st), "hipEventRecord");
+  const int p0 = pass * pl.batch;
+  const int nb = std::min(pl.batch, p.nt - p0);
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int k_first = ch * pl.chunk;
+    const int k_last = std::min(m, k_first + pl.chunk - 1);
+    if (!resident || pass == 0) {
+      Span rs{tl ? tl->mark() : 0, 0, 0};
+      SSM_HIP(record(rs.b), "hipEventRecord");
       for (int k = k_first; k <= k_last; ++k) {
         char* out = y_slot(k);
         hipError_t err;
@@ -556,15 +598,15 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
           const double b = (k == 1) ? beta : 2.0 * beta;
           const double cc = (k == 1) ? 0.0 : -1.0;
           const int s_step = k - 1;  // this step forms Y_{s+1} from Y_s
-          const bool moments = pl.dgc_group && pass == 0 && s_step < dgc_steps(m);
+          const bool moments = first && pl.dgc_group && s_step < dgc_steps(m);
           double* dots = moments ? c->dpart + (size_t)(s_step % pl.dgc_group) * 2 * dgc_nblocks : nullptr;
           if (f64)
             err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
                                             (const double*)x, (const double*)xp, nullptr, (double*)out, st, dots);
           else
             err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
-                                            (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out,
-                                            st, dots);
+                                            (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr,
+                                            (float*)out, st, dots);
           ++spmm_launches;
           if (err == hipSuccess && moments &&
               (s_step % pl.dgc_group == pl.dgc_group - 1 || s_step == dgc_steps(m) - 1)) {
@@ -573,45 +615,89 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
           }
         }
         if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
-        if (pl.ckpt && pass == 0) {  // keep the checkpoint pairs for the adjoint
+        if (pl.ckpt && first) {  // keep the checkpoint pairs for the adjoint
           const int j = (k + 1) / pl.ckpt;
-          const int first = ckpt_first(j, pl.ckpt);
-          if ((k == first || k == first + 1) && j < ckpt_pairs(m, pl.ckpt)) {
-            err = hipMemcpyAsync(c->ckpt + (size_t)(2 * j + (k - first)) * e * es, out, e * es,
+          const int cf = ckpt_first(j, pl.ckpt);
+          if ((k == cf || k == cf + 1) && j < ckpt_pairs(m, pl.ckpt)) {
+            err = hipMemcpyAsync(c->ckpt + (size_t)(2 * j + (k - cf)) * e * es, out, e * es,
                                  hipMemcpyDeviceToDevice, st);
             if (err != hipSuccess) return hip_fail(err, "checkpoint copy");
           }
         }
       }
-      rs.en = mark();
-      SSM_HIP(hipEventRecord(c->events[rs.en], st), "hipEventRecord");
-      spans.push_back(rs);
-      // sweep over this chunk
-      Span ss{rs.en, mark(), 1};
-      const int kc = k_last - k_first + 1;
-      hipError_t err;
-      if (f64)
-        err = ssm::launch_sweep_f64(e, kc, nb, c->c64 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0, (const double*)c->y,
-                                    (double*)c->z, ch > 0, st);
-      else if (p.precision == SSM_FP32_BF16X3)
-        err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
-                                       c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0,
-                                       (int64_t)(p.nt - p0) * pl.ldk - k_first, (const float*)c->y, (float*)c->z,
-                                       ch > 0, c->k3 - k_first, nb, st);
-      else if (p.precision == SSM_FP32)
-        err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
-                                    (const float*)c->y, (float*)c->z, ch > 0, st);
-      else
-        err = ssm::launch_sweep_bf16(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
-                                     (const float*)c->y, (float*)c->z, ch > 0, st);
-      if (err != hipSuccess) return hip_fail(err, "sweep GEMM");
-      ++sweep_launches;
-      SSM_HIP(hipEventRecord(c->events[ss.en], st), "hipEventRecord");
-      spans.push_back(ss);
+      rs.en = tl ? tl->mark() : 0;
+      SSM_HIP(record(rs.en), "hipEventRecord");
+      if (tl) tl->spans.push_back(rs);
     }
+    // sweep over this chunk
+    Span ss{tl ? tl->mark() : 0, 0, 1};
+    SSM_HIP(record(ss.b), "hipEventRecord");
+    const int kc = k_last - k_first + 1;
+    hipError_t err;
+    if (f64)
+      err = ssm::launch_sweep_f64(e, kc, nb, c->c64 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
+                                  (const double*)y_slot(k_first), (double*)c->z, ch > 0, st);
+    else if (p.precision == SSM_FP32_BF16X3)
+      err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
+                                     c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0,
+                                     (int64_t)(p.nt - p0) * pl.ldk - k_first, (const float*)y_slot(k_first),
+                                     (float*)c->z, ch > 0, c->k3 - k_first, nb, st);
+    else if (p.precision == SSM_FP32)
+      err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
+                                  (const float*)y_slot(k_first), (float*)c->z, ch > 0, st);
+    else
+      err = ssm::launch_sweep_bf16(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
+                                   (const float*)y_slot(k_first), (float*)c->z, ch > 0, st);
+    if (err != hipSuccess) return hip_fail(err, "sweep GEMM");
+    ++sweep_launches;
+    ss.en = tl ? tl->mark() : 0;
+    SSM_HIP(record(ss.en), "hipEventRecord");
+    if (tl) tl->spans.push_back(ss);
+  }
+  return SSM_OK;
+}
+
+}  // namespace
+
+ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
+  if (!c || !dos_host) return fail(SSM_ERR_ARG, "ctx and dos_host must be non-NULL");
+  if (c->pl.ress) return ress_dos(c, dos_host, ranks_host);
+  const ssm_params& p = c->p;
+  const Plan& pl = c->pl;
+  const int64_t n = c->a.n;
+  const int nv = p.nv;
+  const int64_t e = n * nv;
+  const size_t es = elem_bytes(p.precision);
+  const bool f64 = p.precision == SSM_FP64;
+  const int m = p.degree;
+  hipStream_t st = c->stream;
+
+  // events: [0] start, then (begin, end) pairs per timed launch group
+  const int nchunks = (m + 1 + pl.chunk - 1) / pl.chunk;
+  const size_t need = 2 + (size_t)pl.passes * (2 * nchunks + 2) * 2 + 4;
+  while (c->events.size() < need) {
+    hipEvent_t ev;
+    SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
+    c->events.push_back(ev);
+  }
+  Timeline tl;
+  auto mark = [&]() -> size_t { return tl.mark(); };
+  const size_t ev_start = mark();
+  SSM_HIP(hipEventRecord(c->events[ev_start], st), "hipEventRecord");
+  int64_t spmm_launches = 0, sweep_launches = 0;
+  c->z_valid = false;
+
+  auto y_slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % pl.chunk) * e * es; };
+  for (int pass = 0; pass < pl.passes; ++pass) {
+    const int p0 = pass * pl.batch;
+    const int nb = std::min(pl.batch, p.nt - p0);
+    ssm_status fs = forward_pass(c, pass, pass == 0, &tl, spmm_launches, sweep_launches);
+    if (fs != SSM_OK) return fs;
     if (pass == 0) {  // bound check inputs: ||W||_F^2 and ||T_M(A~) W||_F^2
       hipError_t err = ssm::launch_sumsq(c->w, e, !f64, c->norm + 8, c->norm + 0, st);
       if (err == hipSuccess) err = ssm::launch_sumsq(y_slot(m), e, !f64, c->norm + 8, c->norm + 1, st);
+      if (err == hipSuccess && c->sfloor)  // eta ||mu(t_i)||_2 ||W||_F^2 / sqrt(N N_v)
+        err = ssm::launch_rounding_floor(c->mun, p.nt, c->eta, c->norm + 0, 1.0 / std::sqrt((double)e), c->sfloor, st);
       if (err != hipSuccess) return hip_fail(err, "norm kernel");
     }
     Span gs{mark(), mark(), 2};
@@ -620,17 +706,17 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
                                       c->kz + (int64_t)p0 * nv * nv, pl.nseg, c->gpart, st);
     if (err != hipSuccess) return hip_fail(err, "Gram kernel");
     SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
-    spans.push_back(gs);
+    tl.spans.push_back(gs);
     c->last_batch_start = p0;
   }
   const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
   Span es_{mark(), mark(), 3};
   SSM_HIP(hipEventRecord(c->events[es_.b], st), "hipEventRecord");
   hipError_t err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks,
-                                            c->escr, st);
+                                            c->escr, st, 0, nullptr, nullptr, nullptr, c->sfloor);
   if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
   SSM_HIP(hipEventRecord(c->events[es_.en], st), "hipEventRecord");
-  spans.push_back(es_);
+  tl.spans.push_back(es_);
   if (pl.dgc_group) {
     err = ssm::launch_dgc(c->c64, pl.ldc, p.nt, m + 1, nv, c->dsums, c->dgc, c->dgc + p.nt, st);
     if (err != hipSuccess) return hip_fail(err, "Algorithm 2 kernel");
@@ -646,7 +732,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 
   ssm_stats& S = c->stats;
   S.ms_recurrence = S.ms_sweep = S.ms_gram = S.ms_geneig = 0.0;
-  for (const Span& sp : spans) {
+  for (const Span& sp : tl.spans) {
     float ms = 0.f;
     SSM_HIP(hipEventElapsedTime(&ms, c->events[sp.b], c->events[sp.en]), "hipEventElapsedTime");
     double* dst = sp.kind == 0 ? &S.ms_recurrence : sp.kind == 1 ? &S.ms_sweep : sp.kind == 2 ? &S.ms_gram : &S.ms_geneig;
@@ -825,16 +911,27 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kBackwardSegment = 256;  // Ybar blocks formed per transposed-sweep launch (no checkpoints)
+constexpr int kBackwardSegment = 256;  // Ybar blocks formed per transposed-sweep launch (resident blocks)
 
+// How the backward walks the degrees.  Level-1 segments are [j S, min((j+1) S - 1, M)] for
+// the forward's checkpoint interval S (one segment [0, M] when every block is resident).
+// Each is cut into sub-segments of at most `sub` reverse steps, top first; a sub-segment's
+// blocks T_{k-1}(A~)W come from the resident ring, or are recomputed into the ring from the
+// pair (Y_{b0}, Y_{b0+1}), b0 = first degree - 1: the level-1 checkpoint pair for a
+// segment's first sub-segment, else a level-2 pair that a replay of the segment from its
+// level-1 pair left in the backward workspace (two levels when the ring holds fewer than
+// S blocks).
 struct BackwardLayout {
-  size_t phibar, kwb, kzb, gescr, ct64, ct32, chit, clot, lam, ybar, total;
+  size_t phibar, kwb, kzb, gescr, ct64, ct32, chit, clot, lam, ybar, pairs2, total;
   int64_t ldct, ldkt;
-  int seg;
+  int sub;      // reverse steps per sub-segment (and Ybar blocks per transposed sweep, + 3)
+  int levels;   // 0: blocks resident; 1: checkpoints, segment recomputed into the ring; 2: two levels
+  int npairs2;  // level-2 pairs per level-1 segment
 };
 
 BackwardLayout backward_layout(const ssm_ctx* c) {
   const ssm_params& p = c->p;
+  const Plan& pl = c->pl;
   const size_t es = elem_bytes(p.precision);
   const size_t e = (size_t)c->a.n * p.nv;
   const size_t nn = (size_t)p.nv * p.nv;
@@ -842,7 +939,17 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   BackwardLayout L{};
   L.ldct = (m1 + 3) / 4 * 4;
   L.ldkt = (p.nt + 63) / 64 * 64;  // 128-byte rows, as the forward tables
-  L.seg = c->pl.ckpt ? c->pl.ckpt : std::min(kBackwardSegment, m1);
+  if (!pl.ckpt) {
+    L.levels = 0;
+    L.sub = std::min(kBackwardSegment, m1);
+  } else if (pl.chunk >= pl.ckpt) {
+    L.levels = 1;
+    L.sub = pl.ckpt;
+  } else {
+    L.levels = 2;
+    L.sub = pl.chunk;
+    L.npairs2 = (pl.ckpt + L.sub - 1) / L.sub;
+  }
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -858,7 +965,8 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   L.chit = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);
   L.clot = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);
   L.lam = take(3 * e * es);
-  L.ybar = take((size_t)(L.seg + 3) * e * es);  // + 3: a segment's rows start at a multiple of 4
+  L.ybar = take((size_t)(L.sub + 3) * e * es);  // + 3: a sub-segment's rows start at a multiple of 4
+  L.pairs2 = take((size_t)2 * L.npairs2 * e * es);
   L.total = o;
   return L;
 }
@@ -883,10 +991,10 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   const Plan& pl = c->pl;
   const int m = p.degree, m1 = m + 1;
   if (pl.ress) return fail(SSM_ERR_UNSUPPORTED, "no adjoint for RESS-DGC in this build");
-  if (pl.passes != 1 || (pl.chunk != m1 && !pl.ckpt))
+  if (pl.chunk != m1 && !pl.ckpt)
     return fail(SSM_ERR_UNSUPPORTED,
-                "the adjoint needs a single-pass plan holding every T_k(A~)W, or one made with ckpt_every > 0");
-  if (!c->have_dos || !c->z_valid) return fail(SSM_ERR_STATE, "ssm_backward needs a preceding ssm_dos");
+                "the adjoint needs a plan whose ring holds every T_k(A~)W, or one made with ckpt_every > 0");
+  if (!c->have_dos) return fail(SSM_ERR_STATE, "ssm_backward needs a preceding ssm_dos");
   for (int i = 0; i < p.nt; ++i)
     if (!std::isfinite(dos_bar_host[i])) return fail(SSM_ERR_ARG, "dos_bar[%d] is not finite", i);
   const BackwardLayout L = backward_layout(c);
@@ -896,7 +1004,9 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   const int64_t n = c->a.n;
   const int nv = p.nv;
   const int64_t e = n * nv;
+  const int64_t nn = (int64_t)nv * nv;
   const size_t es = elem_bytes(p.precision);
+  const size_t bb = (size_t)e * es;  // bytes per block
   const bool f64 = p.precision == SSM_FP64;
   const double alpha = 2.0 / (p.hi - p.lo);
   const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
@@ -908,136 +1018,197 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   double* gescr = (double*)(ws + L.gescr);
   char* lam = ws + L.lam;
   char* ybar = ws + L.ybar;
-  auto lam_slot = [&](int k) { return lam + (size_t)(k % 3) * e * es; };
-  auto cheb = [&](const void* x, const void* xp, const void* d, void* out) {
+  char* pairs2 = ws + L.pairs2;
+  char* ring = (char*)c->y;
+  auto lam_slot = [&](int k) { return lam + (size_t)(k % 3) * bb; };
+  // Y_{b} from Y_{b-1} (x) and Y_{b-2} (xp): b = 1 takes a = alpha, b = beta, no xp
+  auto cheb = [&](const void* x, const void* xp, void* out) {
+    const double a = xp ? 2 * alpha : alpha, b = xp ? 2 * beta : beta, cc = xp ? -1.0 : 0.0;
     if (f64)
-      return ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
-                                       2 * beta, xp ? -1.0 : 0.0, (const double*)x, (const double*)xp,
-                                       (const double*)d, (double*)out, st);
-    return ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)(2 * alpha),
-                                     (float)(2 * beta), xp ? -1.0f : 0.0f, (const float*)x, (const float*)xp,
-                                     (const float*)d, (float*)out, st);
+      return ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
+                                       (const double*)x, (const double*)xp, nullptr, (double*)out, st);
+    return ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
+                                     (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out, st);
   };
 
-  hipEvent_t ev[7] = {};
+  hipEvent_t ev[2] = {};
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 7; ++i)
+      for (int i = 0; i < 2; ++i)
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } guard{ev};
   for (auto& x : ev) SSM_HIP(hipEventCreate(&x), "hipEventCreate");
-  SSM_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
-  SSM_HIP(hipMemcpyAsync(phibar, dos_bar_host, sizeof(double) * p.nt, hipMemcpyHostToDevice, st), "copy dos_bar");
-  hipError_t err = ssm::launch_geneig_backward(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, phibar, kwb, kzb,
-                                               gescr, st);
-  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 backward kernel");
-  SSM_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
-  err = ssm::launch_zbar(!f64, n, nv, p.nt, c->w, c->z, kwb, kzb, st);
-  if (err != hipSuccess) return hip_fail(err, "Zbar kernel");
-  c->z_valid = false;
-  SSM_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
-  // transposed coefficient tables for Ybar = C Zbar
-  if (p.precision == SSM_FP32_BF16X3)
-    err = ssm::launch_split_rows(c->c64, pl.ldc, p.nt, m1, (__bf16*)(ws + L.chit), (__bf16*)(ws + L.clot), L.ldkt, st);
-  else
-    err = ssm::launch_transpose_coefficients(c->c64, pl.ldc, p.nt, m1, f64 ? (double*)(ws + L.ct64) : nullptr,
-                                             f64 ? nullptr : (float*)(ws + L.ct32), L.ldct, st);
-  if (err != hipSuccess) return hip_fail(err, "adjoint set-up kernels");
-  SSM_HIP(hipMemsetAsync(grad_dev, 0, sizeof(double) * c->a.nnz, st), "clear gradient");
+  // time of the launches enqueued by f, on the stream (synchronises)
+  auto timed = [&](float& acc, auto f) -> ssm_status {
+    SSM_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
+    ssm_status s2 = f();
+    if (s2 != SSM_OK) return s2;
+    SSM_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
+    SSM_HIP(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+    float t = 0.f;
+    SSM_HIP(hipEventElapsedTime(&t, ev[0], ev[1]), "hipEventElapsedTime");
+    acc += t;
+    return SSM_OK;
+  };
+  float ms_ge = 0.f, ms_zb = 0.f, ms_ybar = 0.f, ms_rc = 0.f, ms_rev = 0.f, ms_fwd = 0.f;
+  int recomputed = 0, subsegs = 0;
+  ssm_status s0;
 
-  // Segments [k_lo, k_hi] = [j seg, min((j+1) seg - 1, M)], last first.  Each: the seeds
-  // Ybar_{a_lo..k_hi} (a_lo = k_lo rounded down to a multiple of 4), with checkpoints the
-  // blocks Y_{b0+2..k_hi-1}, then Lambda_k and the SDDMM with Y_{k-1} for k = k_hi..max(k_lo, 1).
-  float ms_ybar = 0.f, ms_rc = 0.f, ms_rev = 0.f;
-  int recomputed = 0;
-  const int nseg = m / L.seg + 1;
-  for (int j = nseg - 1; j >= 0; --j) {
-    const int k_lo = j * L.seg;
-    const int k_hi = std::min(m, k_lo + L.seg - 1);
-    const int a_lo = k_lo & ~3;
-    const int len = k_hi - a_lo + 1;
-    SSM_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
-    if (p.precision == SSM_FP64)
-      err = ssm::launch_sweep_f64(e, p.nt, len, (const double*)(ws + L.ct64) + a_lo, L.ldct, L.ldct - a_lo,
-                                  (const double*)c->z, (double*)ybar, 0, st);
-    else if (p.precision == SSM_FP32)
-      err = ssm::launch_sweep_f32(e, p.nt, len, (const float*)(ws + L.ct32) + a_lo, L.ldct, L.ldct - a_lo,
-                                  (const float*)c->z, (float*)ybar, 0, st);
-    else if (p.precision == SSM_FP32_BF16SWEEP)
-      err = ssm::launch_sweep_bf16(e, p.nt, len, (const float*)(ws + L.ct32) + a_lo, L.ldct, L.ldct - a_lo,
-                                   (const float*)c->z, (float*)ybar, 0, st);
+  // Algorithm 4 backward for every sweep point (K_W, K_Z of all batches are kept), the
+  // transposed coefficient tables for Ybar = C Zbar, and the gradient cleared
+  s0 = timed(ms_ge, [&]() -> ssm_status {
+    SSM_HIP(hipMemcpyAsync(phibar, dos_bar_host, sizeof(double) * p.nt, hipMemcpyHostToDevice, st), "copy dos_bar");
+    hipError_t err = ssm::launch_geneig_backward(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, phibar, kwb,
+                                                 kzb, gescr, st, c->sfloor);
+    if (err != hipSuccess) return hip_fail(err, "Algorithm 4 backward kernel");
+    if (p.precision == SSM_FP32_BF16X3)
+      err = ssm::launch_split_rows(c->c64, pl.ldc, p.nt, m1, (__bf16*)(ws + L.chit), (__bf16*)(ws + L.clot), L.ldkt,
+                                   st);
     else
-      err = ssm::launch_sweep_bf16x3(e, p.nt, len, (const __bf16*)(ws + L.chit) + (int64_t)a_lo * L.ldkt,
-                                     (const __bf16*)(ws + L.clot) + (int64_t)a_lo * L.ldkt, L.ldkt, m1 - a_lo,
-                                     (int64_t)(m1 - a_lo) * L.ldkt, (const float*)c->z, (float*)ybar, 0, p.nt,
-                                     c->k3 - a_lo, st);
-    if (err != hipSuccess) return hip_fail(err, "transposed sweep");
-    SSM_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
-    if (pl.ckpt) {
-      const int seg_first = ckpt_first(j, pl.ckpt);
-      // the pair of this segment sits at checkpoint slots 2j, 2j+1; Y_b (b >= seg_first + 2)
-      // goes to ring slot b - seg_first - 2
-      char* pair = c->ckpt + (size_t)(2 * j) * e * es;
-      auto yb = [&](int b) -> const char* {
-        if (b == seg_first) return pair;
-        if (b == seg_first + 1) return pair + (size_t)e * es;
-        return (const char*)c->y + (size_t)(b - seg_first - 2) * e * es;
-      };
-      for (int b = seg_first + 2; b <= k_hi - 1; ++b) {
-        err = cheb(yb(b - 1), yb(b - 2), nullptr, (void*)yb(b));
-        if (err != hipSuccess) return hip_fail(err, "recomputation of T_k(A~)W");
-        ++recomputed;
-      }
+      err = ssm::launch_transpose_coefficients(c->c64, pl.ldc, p.nt, m1, f64 ? (double*)(ws + L.ct64) : nullptr,
+                                               f64 ? nullptr : (float*)(ws + L.ct32), L.ldct, st);
+    if (err != hipSuccess) return hip_fail(err, "adjoint set-up kernels");
+    SSM_HIP(hipMemsetAsync(grad_dev, 0, sizeof(double) * c->a.nnz, st), "clear gradient");
+    return SSM_OK;
+  });
+  if (s0 != SSM_OK) return s0;
+
+  // the batches: the one whose Z the last ssm_dos left resident first, then the others
+  // with Z regenerated by the forward pass
+  const int resident_pass = c->last_batch_start / pl.batch;
+  for (int bi = 0; bi < pl.passes; ++bi) {
+    const int pass = bi == 0 ? resident_pass : (bi - 1 < resident_pass ? bi - 1 : bi);
+    const int p0 = pass * pl.batch;
+    const int nb = std::min(pl.batch, p.nt - p0);
+    if (bi > 0 || !c->z_valid) {
+      int64_t n_spmm = 0, n_sweep = 0;
+      s0 = timed(ms_fwd, [&]() { return forward_pass(c, pass, false, nullptr, n_spmm, n_sweep); });
+      if (s0 != SSM_OK) return s0;
     }
-    SSM_HIP(hipEventRecord(ev[5], st), "hipEventRecord");
-    for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
-      const char* ybk = ybar + (size_t)(k - a_lo) * e * es;
-      const void* x = k < m ? (const void*)lam_slot(k + 1) : nullptr;
-      const void* xp = k + 2 <= m ? (const void*)lam_slot(k + 2) : nullptr;
-      const char* yk1 = (const char*)c->y + (size_t)(k - 1) * e * es;
-      if (pl.ckpt) {
-        const int b = k - 1, first = ckpt_first(j, pl.ckpt);
-        const char* pair = c->ckpt + (size_t)(2 * j) * e * es;
-        yk1 = b == first ? pair : b == first + 1 ? pair + (size_t)e * es
-                                                 : (const char*)c->y + (size_t)(b - first - 2) * e * es;
-      }
-      const double coef = (k == 1 ? 1.0 : 2.0) * alpha;
-      if (f64)
-        err = ssm::launch_reverse_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, 2 * alpha,
-                                           2 * beta, -1.0, (const double*)x, (const double*)xp, (const double*)ybk,
-                                           (double*)lam_slot(k), (const double*)yk1, coef, grad_dev, st);
+    c->z_valid = false;  // Zbar overwrites Z
+    s0 = timed(ms_zb, [&]() -> ssm_status {
+      hipError_t err = ssm::launch_zbar(!f64, n, nv, nb, c->w, c->z, kwb + p0 * nn, kzb + p0 * nn, st);
+      return err == hipSuccess ? SSM_OK : hip_fail(err, "Zbar kernel");
+    });
+    if (s0 != SSM_OK) return s0;
+
+    // Ybar_k = sum over the batch's points of mu_k(t_i) Zbar_i for k in [a_lo, k_hi]
+    auto ybar_range = [&](int a_lo, int len) -> ssm_status {
+      hipError_t err;
+      if (p.precision == SSM_FP64)
+        err = ssm::launch_sweep_f64(e, nb, len, (const double*)(ws + L.ct64) + (int64_t)p0 * L.ldct + a_lo, L.ldct,
+                                    L.ldct - a_lo, (const double*)c->z, (double*)ybar, 0, st);
+      else if (p.precision == SSM_FP32)
+        err = ssm::launch_sweep_f32(e, nb, len, (const float*)(ws + L.ct32) + (int64_t)p0 * L.ldct + a_lo, L.ldct,
+                                    L.ldct - a_lo, (const float*)c->z, (float*)ybar, 0, st);
+      else if (p.precision == SSM_FP32_BF16SWEEP)
+        err = ssm::launch_sweep_bf16(e, nb, len, (const float*)(ws + L.ct32) + (int64_t)p0 * L.ldct + a_lo, L.ldct,
+                                     L.ldct - a_lo, (const float*)c->z, (float*)ybar, 0, st);
       else
-        err = ssm::launch_reverse_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
-                                           (float)(2 * alpha), (float)(2 * beta), -1.0f, (const float*)x,
-                                           (const float*)xp, (const float*)ybk, (float*)lam_slot(k),
-                                           (const float*)yk1, coef, grad_dev, st);
-      if (err != hipSuccess) return hip_fail(err, "reverse recurrence step");
+        err = ssm::launch_sweep_bf16x3(e, nb, len, (const __bf16*)(ws + L.chit) + (int64_t)a_lo * L.ldkt + p0,
+                                       (const __bf16*)(ws + L.clot) + (int64_t)a_lo * L.ldkt + p0, L.ldkt, m1 - a_lo,
+                                       (int64_t)(m1 - a_lo) * L.ldkt - p0, (const float*)c->z, (float*)ybar, 0, nb,
+                                       c->k3 - a_lo, st);
+      return err == hipSuccess ? SSM_OK : hip_fail(err, "transposed sweep");
+    };
+
+    const int S = pl.ckpt ? pl.ckpt : m1;
+    const int nseg1 = pl.ckpt ? m / S + 1 : 1;
+    for (int j = nseg1 - 1; j >= 0; --j) {
+      const int k_lo = j * S;
+      const int k_hi = std::min(m, k_lo + S - 1);
+      const char* pair1 = pl.ckpt ? c->ckpt + (size_t)(2 * j) * bb : nullptr;  // (Y_{k_lo - 1}, Y_{k_lo}) or (Y_0, Y_1)
+      const int nsub = (k_hi - k_lo + L.sub) / L.sub;
+      if (L.levels == 2 && nsub > 1) {
+        // replay the segment from its level-1 pair, keeping (Y_{b0}, Y_{b0+1}) of every
+        // sub-segment q >= 1 (b0 = k_lo + q sub - 1) in the level-2 slots; the other
+        // blocks rotate through three ring slots
+        const int f = ckpt_first(j, S);
+        const int b_last = k_lo + (nsub - 1) * L.sub;  // Y_{b0+1} of the last sub-segment
+        auto where = [&](int b) -> char* {
+          if (b == f) return (char*)pair1;
+          if (b == f + 1) return (char*)pair1 + bb;
+          const int q = (b - k_lo + 1) / L.sub, r = (b - k_lo + 1) % L.sub;
+          if (q >= 1 && q < nsub && r <= 1) return pairs2 + (size_t)(2 * q + r) * bb;
+          return ring + (size_t)(b % 3) * bb;
+        };
+        s0 = timed(ms_rc, [&]() -> ssm_status {
+          for (int b = f + 2; b <= b_last; ++b) {
+            hipError_t err = cheb(where(b - 1), where(b - 2), where(b));
+            if (err != hipSuccess) return hip_fail(err, "replay of T_k(A~)W for the level-2 pairs");
+            ++recomputed;
+          }
+          return SSM_OK;
+        });
+        if (s0 != SSM_OK) return s0;
+      }
+      for (int q = nsub - 1; q >= 0; --q) {
+        const int k2_lo = k_lo + q * L.sub;
+        const int k2_hi = std::min(k_hi, k2_lo + L.sub - 1);
+        const int b0 = k2_lo == 0 ? 0 : k2_lo - 1;
+        const char* pair = q == 0 ? pair1 : pairs2 + (size_t)(2 * q) * bb;
+        // block b = k - 1 of this sub-segment
+        auto y_of = [&](int b) -> const char* {
+          if (!pl.ckpt) return ring + (size_t)b * bb;
+          if (b == b0) return pair;
+          if (b == b0 + 1) return pair + bb;
+          return ring + (size_t)(b - b0 - 2) * bb;
+        };
+        if (pl.ckpt) {
+          s0 = timed(ms_rc, [&]() -> ssm_status {
+            for (int b = b0 + 2; b <= k2_hi - 1; ++b) {
+              hipError_t err = cheb(y_of(b - 1), y_of(b - 2), (void*)y_of(b));
+              if (err != hipSuccess) return hip_fail(err, "recomputation of T_k(A~)W");
+              ++recomputed;
+            }
+            return SSM_OK;
+          });
+          if (s0 != SSM_OK) return s0;
+        }
+        const int a_lo = k2_lo & ~3;
+        s0 = timed(ms_ybar, [&]() { return ybar_range(a_lo, k2_hi - a_lo + 1); });
+        if (s0 != SSM_OK) return s0;
+        s0 = timed(ms_rev, [&]() -> ssm_status {
+          for (int k = k2_hi; k >= std::max(k2_lo, 1); --k) {
+            const char* ybk = ybar + (size_t)(k - a_lo) * bb;
+            const void* x = k < m ? (const void*)lam_slot(k + 1) : nullptr;
+            const void* xp = k + 2 <= m ? (const void*)lam_slot(k + 2) : nullptr;
+            const char* yk1 = y_of(k - 1);
+            const double coef = (k == 1 ? 1.0 : 2.0) * alpha;
+            hipError_t err;
+            if (f64)
+              err = ssm::launch_reverse_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values,
+                                                 2 * alpha, 2 * beta, -1.0, (const double*)x, (const double*)xp,
+                                                 (const double*)ybk, (double*)lam_slot(k), (const double*)yk1, coef,
+                                                 grad_dev, st);
+            else
+              err = ssm::launch_reverse_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
+                                                 (float)(2 * alpha), (float)(2 * beta), -1.0f, (const float*)x,
+                                                 (const float*)xp, (const float*)ybk, (float*)lam_slot(k),
+                                                 (const float*)yk1, coef, grad_dev, st);
+            if (err != hipSuccess) return hip_fail(err, "reverse recurrence step");
+          }
+          return SSM_OK;
+        });
+        if (s0 != SSM_OK) return s0;
+        ++subsegs;
+      }
     }
-    SSM_HIP(hipEventRecord(ev[6], st), "hipEventRecord");
-    SSM_HIP(hipEventSynchronize(ev[6]), "hipEventSynchronize");
-    float a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    SSM_HIP(hipEventElapsedTime(&a1, ev[3], ev[4]), "hipEventElapsedTime");
-    SSM_HIP(hipEventElapsedTime(&a2, ev[4], ev[5]), "hipEventElapsedTime");
-    SSM_HIP(hipEventElapsedTime(&a3, ev[5], ev[6]), "hipEventElapsedTime");
-    ms_ybar += a1;
-    ms_rc += a2;
-    ms_rev += a3;
   }
   SSM_HIP(hipStreamSynchronize(st), "ssm_backward sync");
-  float t_all = 0.f, t_ge = 0.f, t_zb = 0.f;
-  SSM_HIP(hipEventElapsedTime(&t_ge, ev[0], ev[1]), "hipEventElapsedTime");
-  SSM_HIP(hipEventElapsedTime(&t_zb, ev[1], ev[2]), "hipEventElapsedTime");
-  SSM_HIP(hipEventElapsedTime(&t_all, ev[0], ev[6]), "hipEventElapsedTime");
-  c->bstats.ms_total = t_all;
-  c->bstats.ms_geneig = t_ge;
-  c->bstats.ms_zbar = t_zb;
+  c->bstats.ms_geneig = ms_ge;
+  c->bstats.ms_zbar = ms_zb;
   c->bstats.ms_ybar = ms_ybar;
   c->bstats.ms_recompute = ms_rc;
   c->bstats.ms_reverse = ms_rev;
-  c->bstats.segments = nseg;
+  c->bstats.ms_forward = ms_fwd;
+  c->bstats.ms_total = ms_ge + ms_zb + ms_ybar + ms_rc + ms_rev + ms_fwd;
+  c->bstats.segments = subsegs;
   c->bstats.recomputed = recomputed;
+  c->bstats.passes = pl.passes;
+  c->bstats.levels = L.levels;
   return SSM_OK;
 }
 
@@ -1085,6 +1256,7 @@ ssm_status ssm_get_views(const ssm_ctx* c, ssm_views* out) {
   out->elem_bytes = (int32_t)elem_bytes(c->p.precision);
   out->moments = c->xm;
   out->coeff_sq = c->nu;
+  out->s_floor = c->pl.ress ? nullptr : c->sfloor;
   if (c->pl.ress) out->chunk = c->pl.chunk + 1;
   return SSM_OK;
 }

@@ -131,10 +131,18 @@ hipError_t launch_ress_extract(int nt, int nv, int nvh, const double* kmu, const
 hipError_t launch_ress_floor(int nv, int nvp, int h, const double* x, const double* mu, int64_t ldc, int nt,
                              double eta, double* xmax, double* floor_out, hipStream_t stream);
 size_t geneig_lds_bytes(int nv);
-// Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z.
+// Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z,
+// the kept sets taken as in the forward kernel (s_floor as there, may be null).
 // scratch: 3 * ntb * nv * nv doubles.
 hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                                   double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
-                                  hipStream_t stream);
+                                  hipStream_t stream, const double* s_floor = nullptr);
+// Rounding floor of Algorithm 4's truncation for a sweep of limited precision:
+// mun[i] = sqrt(sum_{l<m1} c[l*ldc + i]^2) (launch_coefficient_norms), then
+// floor[i] = eta * mun[i] * (*w_sumsq) * inv_sqrt_e (launch_rounding_floor), with
+// w_sumsq = ||W||_F^2 on the device and inv_sqrt_e = 1 / sqrt(N N_v).
+hipError_t launch_coefficient_norms(const double* c, int64_t ldc, int nt, int m1, double* mun, hipStream_t stream);
+hipError_t launch_rounding_floor(const double* mun, int nt, double eta, const double* w_sumsq, double inv_sqrt_e,
+                                 double* floor_out, hipStream_t stream);
 
 }  // namespace ssm

@@ -53,16 +53,20 @@ METHOD = {"ss": 0, "ress": 1}
 
 
 def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0, dgc=False, method="ss",
-            nv_hybrid=0) -> A.ssm_params:
+            nv_hybrid=0, floor_scale=0.0, plan=None) -> A.ssm_params:
+    batch, chunk = plan if plan is not None else (0, 0)
     return A.ssm_params(float(lo), float(hi), float(sigma), float(tau), float(rho), int(nv), int(degree),
                         int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF, int(ckpt_every),
-                        int(bool(dgc)), int(METHOD[method]), int(nv_hybrid))
+                        int(bool(dgc)), int(METHOD[method]), int(nv_hybrid), float(floor_scale), int(batch),
+                        int(chunk))
 
 
 def workspace_size(csr: DeviceCSR, *, lo, hi, sigma, nv, degree, nt, precision="fp32", tau=1e-7, rho=1e-3,
-                   seed=0, budget=0, ckpt_every=0, dgc=False, method="ss", nv_hybrid=0) -> int:
+                   seed=0, budget=0, ckpt_every=0, dgc=False, method="ss", nv_hybrid=0, floor_scale=0.0,
+                   plan=None) -> int:
     out = C.c_size_t(0)
-    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc, method, nv_hybrid)
+    p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc, method, nv_hybrid,
+                floor_scale, plan)
     A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(p), C.c_size_t(budget), C.byref(out)),
             "ssm_workspace_size")
     return int(out.value)
@@ -75,7 +79,7 @@ class SSM:
 
     def __init__(self, csr: DeviceCSR, *, lo, hi, sigma, nv, degree, t, precision="fp32", tau=1e-7, rho=1e-3,
                  seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, dgc=False, method="ss",
-                 nv_hybrid=0, device="cuda:0"):
+                 nv_hybrid=0, floor_scale=0.0, plan=None, device="cuda:0"):
         self.csr = csr
         self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         self.nt = int(self.t.size)
@@ -92,7 +96,7 @@ class SSM:
         self.method = method
         self.nv_hybrid = int(nv_hybrid)
         self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every, dgc,
-                              method, nv_hybrid)
+                              method, nv_hybrid, floor_scale, plan)
         size = C.c_size_t(0)
         A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(self.params), C.c_size_t(budget),
                                          C.byref(size)), "ssm_workspace_size")
@@ -161,12 +165,15 @@ class SSM:
         if v.moments:
             out["moments"] = self._view(v.moments, m1 * nvp * nvp, torch.float64).view(m1, nvp, nvp)
             out["coeff_sq"] = self._view(v.coeff_sq, m1 * ldc, torch.float64).view(m1, ldc)[:, :nt]
+        if v.s_floor:
+            out["s_floor"] = self._view(v.s_floor, nt, torch.float64)
         out["w"] = self.w_in if self.w_in is not None else self._view(v.w, e, self.elem).view(n, nvp)
         return out
 
     def backward(self, dos_bar) -> torch.Tensor:
         """Gradient of sum_i dos_bar[i] dos[i] w.r.t. the stored values (ssm_backward):
-        a float64 device tensor of nnz entries.  Consumes the Z blocks of the last dos()."""
+        a float64 device tensor of nnz entries.  Overwrites the context's Z blocks; a later
+        backward forms them again."""
         dos_bar = np.ascontiguousarray(np.asarray(dos_bar, dtype=np.float64))
         assert dos_bar.shape == (self.nt,)
         size = C.c_size_t(0)

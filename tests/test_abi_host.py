@@ -149,10 +149,12 @@ def test_checkpoint_interval_validated(A, s):
     assert st == A.SSM_ERR_ARG
 
 
-def test_checkpoint_plan_keeps_one_pass(A):
-    """ckpt_every > 0 keeps every Z_i resident (one recurrence pass) and, when the
-    blocks T_k W do not all fit, stores 2 (M/s + 1) checkpoint blocks beside a ring of
-    at least s blocks; without checkpoints the same budget gives a multi-pass plan."""
+def test_checkpoint_plan(A):
+    """ckpt_every > 0: when the blocks T_k W do not all fit, the plan stores 2 (M/s + 1)
+    checkpoint blocks beside its ring (of at least 16 blocks, a multiple of 16, not
+    necessarily s: the backward adds a second level of pairs); a budget too small for Z,
+    the pairs and a ring gives a plan with several sweep-point batches; with room for
+    every block no checkpoint is kept."""
     n, nv, m, nt, s = 100000, 8, 200, 64, 20
     csr = _dummy_csr(A, n)
     e = n * nv * 4
@@ -167,12 +169,15 @@ def test_checkpoint_plan_keeps_one_pass(A):
     assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), budget, C.byref(got)) == 0
     assert got.value <= budget
     ring = (got.value - fixed - (nt + 2 * pairs) * e) / e
-    assert s <= ring <= 48 + 1
-    # a budget that holds Z but not Z + checkpoints + a ring of s blocks
+    assert ring == 48, ring
+    # a ring smaller than s (16 blocks) is a valid plan
+    small = fixed + (nt + 2 * pairs + 16) * e + (1 << 20)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), small, C.byref(got)) == 0
+    assert (got.value - fixed - (nt + 2 * pairs) * e) / e == 16
+    # a budget that holds Z but not Z + checkpoints + a ring: several batches
     tight = fixed + (nt + s) * e
-    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), tight, C.byref(got)) == A.SSM_ERR_WORKSPACE
-    p0 = _params(A, nv=nv, degree=m, nt=nt)
-    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p0), tight, C.byref(got)) == 0
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), tight, C.byref(got)) == 0
+    assert got.value <= tight
     # with room for every block no checkpoint is kept
     assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(got)) == 0
     assert got.value == full.value
@@ -302,3 +307,28 @@ def test_trace_weights_validate():
     with pytest.raises(SSMError):
         S.trace_weights(lambda x: math.log(x) if x > 0 else float("nan"), lo=-1.0, hi=1.0, nt=100, n=10,
                         sigma=0.01)
+
+
+def test_plan_overrides(A):
+    """plan_batch / plan_chunk pin the plan: validated (multiples of 8 and 16 below nt and
+    M + 1), sized exactly (Z of plan_batch points, a ring of plan_chunk blocks), and refused
+    when the budget cannot hold them."""
+    n, nv, m, nt = 100000, 8, 200, 64
+    csr = _dummy_csr(A, n)
+    e = n * nv * 4
+    out = C.c_size_t(0)
+    for kw in (dict(plan_batch=12), dict(plan_chunk=20), dict(plan_batch=-8), dict(plan_chunk=-16)):
+        p = _params(A, nv=nv, degree=m, nt=nt, **kw)
+        assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == A.SSM_ERR_ARG, kw
+    full = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(_params(A, nv=nv, degree=m, nt=nt)), 0, C.byref(full)) == 0
+    p = _params(A, nv=nv, degree=m, nt=nt, plan_batch=16, plan_chunk=32)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == 0
+    assert abs((full.value - out.value) - ((nt - 16) + (m + 1 - 32)) * e) < 4 << 20
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), out.value - (8 << 20), C.byref(out)) == \
+        A.SSM_ERR_WORKSPACE
+    # values at or above nt / M + 1 need no alignment and mean one batch / every block
+    p = _params(A, nv=nv, degree=m, nt=nt, plan_batch=nt + 3, plan_chunk=m + 5)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == 0 and out.value == full.value
+    p = _params(A, nv=nv, degree=50, nt=nt, precision=0, method=1, plan_chunk=16)
+    assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == A.SSM_ERR_ARG

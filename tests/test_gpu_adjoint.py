@@ -26,13 +26,13 @@ def S():
     return ssm
 
 
-def _ctx(S, wl, precision, w=None, t=None, budget=0, ckpt_every=0):
+def _ctx(S, wl, precision, w=None, t=None, budget=0, ckpt_every=0, plan=None):
     dt = torch.float64 if precision == "fp64" else torch.float32
     csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
     wd = None if w is None else torch.tensor(w, dtype=dt, device=DEV)
     return S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree,
                  t=wl.t if t is None else t, precision=precision, seed=wl.seed, w=wd, budget=budget,
-                 ckpt_every=ckpt_every, device=DEV)
+                 ckpt_every=ckpt_every, plan=plan, device=DEV)
 
 
 def test_adjoint_identity_probe_exact_gradient(S):
@@ -133,30 +133,89 @@ def test_autograd_function(S, cfg1_case):
     assert torch.allclose(vals.grad, g, rtol=0, atol=1e-12 * g.abs().max().item())
 
 
-def test_backward_requires_forward_and_single_pass(S, cfg1_case):
-    from paper_1504_07690_amd._abi import SSMError, SSM_ERR_STATE, SSM_ERR_UNSUPPORTED
+def test_backward_requires_forward(S, cfg1_case):
+    """No backward before the first ssm_dos; a second backward forms the consumed Z again
+    and gives the same gradient, bit for bit."""
+    from paper_1504_07690_amd._abi import SSMError, SSM_ERR_STATE
     wl, dos_bar = cfg1_case
     ctx = _ctx(S, wl, "fp64")
     with pytest.raises(SSMError) as ei:
         ctx.backward(dos_bar)
     assert ei.value.status == SSM_ERR_STATE
     ctx.dos()
-    ctx.backward(dos_bar)
-    with pytest.raises(SSMError) as ei:  # Z was consumed
-        ctx.backward(dos_bar)
-    assert ei.value.status == SSM_ERR_STATE
+    g1 = ctx.backward(dos_bar).cpu().numpy()
+    g2 = ctx.backward(dos_bar).cpu().numpy()  # Z was consumed by the first
+    assert ctx.backward_stats()["ms_forward"] > 0
     ctx.close()
-    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=DEV)
-    kw = dict(lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, precision="fp64", seed=wl.seed)
-    full = S.workspace_size(csr, nt=wl.nt, **kw)
-    small = S.SSM(csr, t=wl.t, budget=int(0.45 * full), device=DEV, **kw)
-    st = small.stats()
-    assert st["passes"] > 1 or st["chunk"] < wl.degree + 1
-    small.dos()
-    with pytest.raises(SSMError) as ei:
-        small.backward(dos_bar)
-    assert ei.value.status == SSM_ERR_UNSUPPORTED
-    small.close()
+    assert np.array_equal(g1, g2)
+
+
+MULTI = [  # precision, ring, s, batch, levels
+    ("fp64", 201, 0, 24, 0),    # every block resident, three batches: Z formed again by the sweep
+    ("fp64", 64, 50, 24, 1),    # checkpoints, ring holds a segment, three batches
+    ("fp64", 16, 50, 64, 2),    # two checkpoint levels, one batch
+    ("fp64", 32, 64, 32, 2),    # two levels and two batches
+    ("fp32", 16, 50, 32, 2),
+    ("bf16x3", 16, 40, 24, 2),
+]
+
+
+@pytest.mark.parametrize("precision,ring,s,batch,levels", MULTI)
+def test_multipass_adjoint_matches_resident(S, cfg1_case, precision, ring, s, batch, levels):
+    """Plans with several sweep-point batches and rings of fewer blocks than M + 1: every
+    batch's Z formed again by the forward pass, blocks recomputed from one or two levels of
+    checkpoint pairs.  The gradient against the resident single-batch plan's: FP64 to 1e-10
+    (the forward chunking and the per-batch Ybar sums change only the rounding), FP32 and
+    split BF16 to 1e-4."""
+    wl, dos_bar = cfg1_case
+    w = wl.w() if precision == "fp64" else wl.w().astype(np.float32).astype(np.float64)
+    ctx = _ctx(S, wl, precision, w=w)
+    d_full, _, _ = ctx.dos()
+    g_full = ctx.backward(dos_bar).cpu().numpy()
+    ctx.close()
+    ctx = _ctx(S, wl, precision, w=w, ckpt_every=s, plan=(batch, ring))
+    st = ctx.stats()
+    d, _, _ = ctx.dos()
+    g = ctx.backward(dos_bar).cpu().numpy()
+    bs = ctx.backward_stats()
+    ctx.close()
+    rel = np.linalg.norm(g - g_full) / np.linalg.norm(g_full)
+    print(f"{precision} ring {st['chunk']} batch {st['batch']} passes {st['passes']} s={s}: levels {bs['levels']}, "
+          f"{bs['segments']} sub-segments, {bs['recomputed']} blocks recomputed, forward {bs['ms_forward']:.1f} ms; "
+          f"rel diff {rel:.2e}")
+    assert st["chunk"] == min(ring, wl.degree + 1) and bs["levels"] == levels, (st, bs)
+    assert st["passes"] == -(-wl.nt // batch) and bs["passes"] == st["passes"]
+    assert (bs["ms_forward"] > 0) == (st["passes"] > 1)
+    assert np.abs(d - d_full).max() <= (1e-12 if precision == "fp64" else 1e-5) * d_full.max()
+    assert rel <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+def test_multipass_two_level_adjoint_central_differences(S, cfg1_case):
+    """Two batches, two checkpoint levels: the FP64 gradient along symmetric directions
+    against central differences of the oracle."""
+    wl, dos_bar = cfg1_case
+    ctx = _ctx(S, wl, "fp64", w=wl.w(), ckpt_every=64, plan=(32, 32))
+    assert ctx.stats()["passes"] == 2
+    ctx.dos()
+    g = ctx.backward(dos_bar).cpu().numpy()
+    assert ctx.backward_stats()["levels"] == 2
+    ctx.close()
+    h = 1e-6 * np.abs(wl.a.values).max()
+    checked = 0
+    for seed in range(6):
+        e = _sym_direction(wl.a, seed)
+        lp, rp = _oracle_objective(wl, wl.a.values + h * e, dos_bar)
+        lm, rm = _oracle_objective(wl, wl.a.values - h * e, dos_bar)
+        if not (np.array_equal(rp["r1"], rm["r1"]) and np.array_equal(rp["r2"], rm["r2"])):
+            continue
+        fd = (lp - lm) / (2 * h)
+        ad = g @ e
+        print(f"direction {seed}: adjoint {ad:.12e}  central difference {fd:.12e}")
+        assert abs(ad - fd) <= 1e-5 * abs(fd)
+        checked += 1
+        if checked == 2:
+            break
+    assert checked >= 1
 
 
 @pytest.mark.parametrize("precision,s", [("fp64", 13), ("fp64", 50), ("fp32", 21)])
@@ -170,14 +229,8 @@ def test_checkpointed_adjoint_matches_resident(S, cfg1_case, precision, s):
     ctx.dos()
     g_full = ctx.backward(dos_bar).cpu().numpy()
     ctx.close()
-    es = 8 if precision == "fp64" else 4
-    e = wl.a.n * wl.nv * es
-    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64 if es == 8 else torch.float32, device=DEV)
-    full = S.workspace_size(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, nt=wl.nt,
-                            precision=precision, seed=wl.seed)
     m1 = wl.degree + 1
-    room = 2 * (wl.degree // s + 1) + 16 * (-(-s // 16)) + 8  # checkpoints + a ring of >= s blocks
-    ctx = _ctx(S, wl, precision, w=w, budget=full - (m1 - room) * e, ckpt_every=s)
+    ctx = _ctx(S, wl, precision, w=w, ckpt_every=s, plan=(wl.nt, 16 * (-(-s // 16))))  # a ring of >= s blocks
     st = ctx.stats()
     assert st["passes"] == 1 and s <= st["chunk"] < m1, st
     ctx.dos()
@@ -198,9 +251,7 @@ def test_adjoint_without_checkpoints_needs_resident_blocks(S, cfg1_case):
     wl, dos_bar = cfg1_case
     csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=DEV)
     kw = dict(lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, precision="fp64", seed=wl.seed)
-    full = S.workspace_size(csr, nt=wl.nt, **kw)
-    e = wl.a.n * wl.nv * 8
-    ctx = S.SSM(csr, t=wl.t, budget=full - 100 * e, device=DEV, **kw)
+    ctx = S.SSM(csr, t=wl.t, plan=(wl.nt, 96), device=DEV, **kw)
     assert ctx.stats()["passes"] == 1 and ctx.stats()["chunk"] < wl.degree + 1
     ctx.dos()
     with pytest.raises(SSMError) as ei:

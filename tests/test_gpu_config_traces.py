@@ -9,9 +9,9 @@ only), through the C ABI:
   f floored at half the Gershgorin bound, with Algorithm 8's weights.
 
 Gates: the device trace against the oracle's on the same W, 1e-6 relative in FP64 (the
-tolerance for FP64 traces) and 1e-3 for the FP32 and split-BF16 paths; exp(-A), whose trace
-sits in the zero mode at the bottom edge of the spectrum, takes 1e-2 in FP32 and is only
-reported for split BF16 (see the parameter list).  Against the exact
+tolerance for FP64 traces) and 1e-3 for the FP32 and split-BF16 paths, whose rounding floor
+of Algorithm 4's truncation keeps the rounding of Z out of the estimate where the weights are
+largest (see the parameter list).  Against the exact
 trace (dense eigenvalues) the errors are printed; for exp(-A) the estimate is within 1e-6.
 The gradient of each trace (all sweep points weighted) is checked in FP64 against central
 differences of the device's own trace along a symmetric direction, and for log(A) with
@@ -70,13 +70,12 @@ def _ctx(S, a, rec, precision, ckpt_every=0, budget=0):
 
 
 # exp(-A) of the stencil is dominated by its zero mode at the bottom edge of a spectrum 216
-# wide (Tr = 1.18 of N = 1728), where the weights are largest and the DOS smallest: the FP32
-# recurrence's rounding there gives 4.8e-3 (gate 1e-2), and the split-BF16 sweep, whose
-# single-product tail errs by up to 2^-8 of each small term, 1.2e-1.  That path is reported
-# for this trace, not gated: it is built for the DOS's L1 tolerance, not for exponential
-# weights at the spectrum's edge.
+# wide (Tr = 1.18 of N = 1728), where the weights are largest (up to 2e5 at the sweep points
+# 10 sigma below it) and the DOS smallest.  There Z(t_i) is below the sweep's rounding, and
+# without the rounding floor of Algorithm 4's truncation the reduced-precision paths would
+# report that rounding as DOS: 3.4e-3 (FP32) and 1.1e-1 (split BF16) off the oracle's trace.
 @pytest.mark.parametrize("name,precision,tol", [
-    ("exp_stencil27", "fp64", 1e-6), ("exp_stencil27", "fp32", 1e-2), ("exp_stencil27", "bf16x3", None),
+    ("exp_stencil27", "fp64", 1e-6), ("exp_stencil27", "fp32", 1e-3), ("exp_stencil27", "bf16x3", 1e-3),
     ("log_shifted_spd", "fp64", 1e-6), ("log_shifted_spd", "fp32", 1e-3), ("log_shifted_spd", "bf16x3", 1e-3)])
 def test_config_trace_matches_oracle(golden, name, precision, tol):
     from paper_1504_07690_amd import ssm as S
@@ -90,8 +89,7 @@ def test_config_trace_matches_oracle(golden, name, precision, tol):
     print(f"{name} {precision}: device {tr:.10e} oracle {rec['trace']:.10e} rel {rel:.2e}; exact {rec['exact']:.10e} "
           f"(device error {abs(tr - rec['exact']) / abs(rec['exact']):.2e})")
     assert np.isfinite(tr)
-    if tol is not None:
-        assert rel <= tol
+    assert rel <= tol
     if name == "exp_stencil27" and precision == "fp64":
         assert abs(tr - rec["exact"]) <= 1e-6 * abs(rec["exact"])
 

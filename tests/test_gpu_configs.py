@@ -104,7 +104,8 @@ def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
     # (3) Algorithm 4 on every point from the device's Gram matrices
     kw = v["k_w"].cpu().numpy()
     kz = v["k_z"].cpu().numpy()
-    ref = np.array([O.geneig_trace(kw[i], kz[i], gmax)[0] for i in range(len(t))])
+    fl = _floors(wl, ctx, v, t)
+    ref = np.array([O.geneig_trace(kw[i], kz[i], gmax, s_floor=fl[i])[0] for i in range(len(t))])
     bad = np.abs(dos - ref) > 1e-9 * gmax
     assert bad.sum() <= 1, np.nonzero(bad)
     # (4) where the plan keeps every block: rows of Z against the oracle's sweep of the
@@ -115,6 +116,24 @@ def _check_sampled_stages(wl, ctx, t, dos, r1, r2, rng):
         zr = z[:, rows_t, :].double().cpu().numpy()
         mu = O.dgc_coefficients(t, m, wl.sigma, n, wl.lo, wl.hi)
         _assert_z_rows(zr, mu, yr, ctx.precision, ctx.stats()["split_k3"])
+
+
+ETA = {"fp64": 0.0, "fp32": 2.0 ** -22, "bf16x3": 2.0 ** -16, "bf16": 2.0 ** -7}
+
+
+def _floors(wl, ctx, v, t):
+    """The rounding floors of Algorithm 4's truncation that the device used, checked against
+    the oracle's formula eta ||mu(t_i)||_2 ||W||_F^2 / sqrt(N N_v) on the device's W."""
+    eta = ETA[ctx.precision]
+    if eta == 0.0:
+        assert "s_floor" not in v
+        return np.zeros(len(t))
+    fl = v["s_floor"].cpu().numpy()
+    wsq = float(torch.sum(v["w"].double() ** 2).item())
+    mu = O.dgc_coefficients(t, wl.degree, wl.sigma, wl.a.n, wl.lo, wl.hi)
+    ref = eta * np.sqrt((mu ** 2).sum(axis=0)) * wsq / np.sqrt(wl.a.n * wl.nv)
+    assert np.allclose(fl, ref, rtol=1e-9, atol=0)
+    return fl
 
 
 def _assert_z_rows(zr, mu, yr, precision, k3):
@@ -249,10 +268,9 @@ def test_spd_workload_checkpointed_adjoint(S):
     ctx.close()
     del ctx, csr
     _free()
-    e = wl.a.n * wl.nv * 4
-    full = _budget(40)
-    budget = min(full, int((wl.nt + 2 * (wl.degree // 50 + 1) + 200) * e * 1.02) + (2 << 30))
-    csr, ctx = _ctx(S, wl, "fp32", wl.t, budget=budget, ckpt_every=50)
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision="fp32",
+                seed=wl.seed, ckpt_every=50, plan=(wl.nt, 208), device=DEV)
     st = ctx.stats()
     assert st["passes"] == 1 and 50 <= st["chunk"] < wl.degree + 1, st
     ctx.dos()
@@ -280,3 +298,65 @@ def test_spd_workload_checkpointed_adjoint(S):
     ctx.close()
     del ctx, csr
     _free()
+
+
+def _sym_hash_direction(a, seed):
+    """A symmetric direction on the pattern of a (the value of entry (r, c) equals that of
+    (c, r)), from a multiplicative hash of the unordered pair: vectorised for large nnz."""
+    rows = np.repeat(np.arange(a.n, dtype=np.int64), np.diff(a.row_ptr))
+    cols = a.col_idx.astype(np.int64)
+    key = np.minimum(rows, cols) * a.n + np.maximum(rows, cols) + seed * 0x9E3779B1
+    h = (key * 0x2545F491) & 0xFFFFFFFF
+    h = (h ^ (h >> 15)) * 0x2C1B3C6D & 0xFFFFFFFF
+    return (h ^ (h >> 12)).astype(np.float64) / 2.0 ** 32 - 0.5
+
+
+def test_stencil27_adjoint_two_level_checkpoints(S):
+    """The adjoint at the 27-point workload's full size (N = 128^3, N_v = 256, M = 4000,
+    FP32), on eight strided sweep points: checkpoint pairs every 250 degrees and a ring of
+    16 blocks, so that the backward recomputes each segment through a second level of pairs
+    (one level of checkpoints would need more than the GPU's memory).  The gradient of
+    sum_i dos_bar_i phi~(t_i), dos_bar weighting the resolved points, is finite and matches a
+    central difference of the device's FP32 DOS along one symmetric direction (step
+    1e-3 max|a|, tolerance 1e-2: the FP32 estimate's rounding over the step)."""
+    wl = WL.make_workload(5)
+    n, nv, m = wl.a.n, wl.nv, wl.degree
+    t = wl.t[wl.nt // 16::wl.nt // 8]
+    s, ring = 250, 16
+    bb = n * nv * 4
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
+    kw = dict(lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, precision="fp32", seed=wl.seed)
+    ctx = S.SSM(csr, t=t, ckpt_every=s, plan=(len(t), ring), device=DEV, **kw)
+    st = ctx.stats()
+    assert st["passes"] == 1 and st["chunk"] == ring, st
+    dos, r1, r2 = ctx.dos()
+    keep = dos > 1e-2 * dos.max()
+    assert keep.sum() >= 2
+    dos_bar = np.random.default_rng(11).uniform(0.5, 1.0, len(t)) * keep
+    g = ctx.backward(dos_bar)
+    bs = ctx.backward_stats()
+    print(f"{wl.name} adjoint: ring {st['chunk']}, checkpoints every {s}: levels {bs['levels']}, "
+          f"{bs['recomputed']} blocks recomputed; {bs['ms_total'] / 1e3:.1f} s (recompute "
+          f"{bs['ms_recompute'] / 1e3:.1f}, reverse {bs['ms_reverse'] / 1e3:.1f}, Ybar {bs['ms_ybar'] / 1e3:.1f})")
+    assert bs["levels"] == 2 and bs["recomputed"] > m
+    assert bool(torch.isfinite(g).all().item())
+    g = g.cpu().numpy()
+    e = _sym_hash_direction(wl.a, 1)
+    h = 1e-3 * np.abs(wl.a.values).max()
+    base = csr.values.clone()
+    ed = torch.tensor(e, dtype=torch.float32, device=DEV)
+    csr.values.copy_(base + h * ed)
+    lp, p1, p2 = ctx.dos()
+    csr.values.copy_(base - h * ed)
+    lm, q1, q2 = ctx.dos()
+    csr.values.copy_(base)
+    ctx.close()
+    del ctx, csr, base, ed
+    _free()
+    same = np.array_equal(p1[keep], q1[keep]) and np.array_equal(p2[keep], q2[keep])
+    fd = dos_bar @ (lp - lm) / (2 * h)
+    ad = g @ e
+    print(f"direction: adjoint {ad:.6e}  central difference {fd:.6e}  rel {abs(ad - fd) / abs(fd):.2e}; kept sets "
+          f"{'unchanged' if same else 'changed'}")
+    assert same
+    assert abs(ad - fd) <= 1e-2 * abs(fd)

@@ -143,14 +143,18 @@ def test_fullsize_fp32_matches_golden_and_stages(setup):
         tol = (n + 4) * 2.0 ** -53
         assert np.all(np.abs(v["k_w"][p].cpu().numpy() - rw) <= tol * mw + asym + 1e-300), p
         assert np.all(np.abs(v["k_z"][p].cpu().numpy() - rz) <= tol * mz + 1e-300), p
-        # the asymmetry is the rounding of Z, far below K_W itself
-        assert asym.max() <= 1e-5 * np.abs(rw).max(), p
+        # at resolved points the asymmetry is the rounding of Z, far below K_W itself (outside
+        # the spectrum Z is rounding and so is all of K_W)
+        if ref[j] > 1e-3 * ref.max():
+            assert asym.max() <= 1e-5 * np.abs(rw).max(), p
 
     # (b4) Algorithm 4 on every point, from the device's Gram matrices
     kw = v["k_w"].cpu().numpy()
     kz = v["k_z"].cpu().numpy()
     gmax = O.range_bound(wl.sigma, n)
-    ref_all = np.array([O.geneig_trace(kw[i], kz[i], gmax)[0] for i in range(wl.nt)])
+    from test_gpu_configs import _floors
+    fl = _floors(wl, ctx, v, wl.t)
+    ref_all = np.array([O.geneig_trace(kw[i], kz[i], gmax, s_floor=fl[i])[0] for i in range(wl.nt)])
     bad = np.abs(dos - ref_all) > 1e-9 * gmax
     assert bad.sum() <= 2, np.nonzero(bad)
     ctx.close()

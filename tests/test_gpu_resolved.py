@@ -10,7 +10,8 @@ the whole interval, the spectrum's edges and the empty margins included.
 Each path runs end to end through the C ABI on the oracle's W and is compared with the
 oracle's FP64 SS-DGC on the same W (relative L1 gate 1e-3 for the reduced-precision paths,
 1e-9 of the largest value for FP64) and with the exact regularised DOS from a dense
-eigen-decomposition; the kept ranks r1 are printed.
+eigen-decomposition; the kept ranks r1 are printed.  The reduced-precision paths run with
+the rounding floor of Algorithm 4's truncation (their default) and, for the record, without.
 """
 import numpy as np
 import pytest
@@ -47,8 +48,22 @@ def test_rank_resolved_paths(case, precision):
     ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision=precision,
                 w=wd, device=DEV)
     dos, r1, r2 = ctx.dos()
-    ctx.close()
     gmax = O.range_bound(wl.sigma, wl.a.n)
+    # Algorithm 4 on the device's Gram matrices, with the floors it used
+    from test_gpu_configs import _floors
+    v = ctx.views()
+    fl = _floors(wl, ctx, v, wl.t)
+    kw, kz = v["k_w"].cpu().numpy(), v["k_z"].cpu().numpy()
+    alg4 = np.array([O.geneig_trace(kw[i], kz[i], gmax, s_floor=fl[i])[0] for i in range(wl.nt)])
+    assert np.abs(dos - alg4).max() <= 1e-9 * gmax
+    ctx.close()
+    if precision != "fp64":  # the same path without the rounding floor, for the record
+        ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
+                    precision=precision, w=wd, floor_scale=-1.0, device=DEV)
+        d_nf, r1_nf, _ = ctx.dos()
+        ctx.close()
+        print(f"{precision} without the rounding floor: L1 vs oracle {_l1(d_nf, ref['dos']):.2e}, vs exact "
+              f"{_l1(d_nf, exact):.2e}")
     inside = ref["dos"] > 1e-3 * ref["dos"].max()
     print(f"{precision}: L1 vs oracle {_l1(dos, ref['dos']):.2e}, vs exact {_l1(dos, exact):.2e} "
           f"(oracle vs exact {_l1(ref['dos'], exact):.2e}); r1 inside the spectrum "

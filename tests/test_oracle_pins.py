@@ -378,6 +378,54 @@ def test_ress_floor_silences_points_outside_the_spectrum():
     assert np.abs(without[out]).max() > 1e-2 * ref.max()
 
 
+@pytest.mark.parametrize("which", ["stencil8", "lap16"])
+def test_rounding_floor_covers_fp32_sweep_error(which):
+    """The rounding floor of Algorithm 4's truncation against a sweep carried out in FP32
+    arithmetic (float32 coefficients and blocks, float32 matrix product) on two small
+    matrices whose interval leaves 20 sigma of empty margin.  Pins of the floor's formula:
+    - at the points where the exact regularised DOS is below 1e-12 of its maximum, the
+      floor at eta = 2^-22 lies between 1 and 10 times the measured error
+      ||K_W(FP32 Z) - K_W(FP64 Z)||_2 (a factor of N, N_v or ||W||_F off would miss by far);
+    - there the FP32 estimate without the floor reports rounding (far above the FP64
+      estimate's 1e-13 of the maximum) and with it exactly 0;
+    - at the resolved points the floor stays below 1e-5 of max s, and the relative L1
+      against the FP64 estimate does not grow."""
+    if which == "stencil8":
+        a, nv = WL.stencil27_lognormal(8, np.random.default_rng(5)), 48
+    else:
+        a, nv = WL.laplacian_2d_dirichlet(16, np.random.default_rng(3).uniform(-1, 1, 256)), 32
+    m, nt = 2000, 128
+    wl = WL.make_workload(1, a=a, nv=nv, degree=m, nt=nt, sigma_hat=0.005)
+    w = wl.w()
+    n = a.n
+    mu = O.dgc_coefficients(wl.t, m, wl.sigma, n, wl.lo, wl.hi)
+    ys = np.array([v for _, v in O.chebyshev_blocks(a, w, m, wl.lo, wl.hi)]).reshape(m + 1, -1)
+    z64 = (mu.T @ ys).reshape(nt, n, nv)
+    z32 = (mu.astype(np.float32).T @ ys.astype(np.float32)).astype(np.float64).reshape(nt, n, nv)
+    gmax = O.range_bound(wl.sigma, n)
+    ex = O.exact_dos(np.linalg.eigvalsh(a.to_dense()), wl.t, wl.sigma)
+    empty = ex < 1e-12 * ex.max()
+    assert empty.sum() >= 20
+    fl = O.rounding_floor(mu, w, 2.0 ** -22)
+    d64, d0, df, noise, smax = (np.zeros(nt) for _ in range(5))
+    for i in range(nt):
+        k64, k32 = O.gram(w, z64[i]), O.gram(w, z32[i])
+        noise[i] = np.linalg.norm(k32[0] - k64[0], 2)
+        smax[i] = np.linalg.eigvalsh(k64[0]).max()
+        d64[i] = O.geneig_trace(*k64, gmax)[0]
+        d0[i] = O.geneig_trace(*k32, gmax)[0]
+        df[i] = O.geneig_trace(*k32, gmax, s_floor=fl[i])[0]
+    ratio = fl[empty] / noise[empty]
+    assert ratio.min() >= 1.0 and ratio.max() <= 10.0, (ratio.min(), ratio.max())
+    assert d64[empty].max() <= 1e-13 * d64.max()
+    assert d0[empty].max() >= 1e-8 * d64.max()
+    assert np.all(df[empty] == 0.0)
+    resolved = d64 > 1e-2 * d64.max()
+    assert np.all(fl[resolved] <= 1e-5 * smax[resolved])
+    l1 = lambda x: np.abs(x - d64).sum() / np.abs(d64).sum()
+    assert l1(df) <= l1(d0) <= 1e-5
+
+
 def test_ress_correction_vanishes_when_sampled_enough():
     """With N_v above the numerical rank the low-rank part is exact (Theorem 3), so the
     hybrid correction is at rounding level and both estimates agree."""
