@@ -376,6 +376,21 @@ ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, 
 ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
                     double* k_w, double* k_z, int32_t nseg, double* scratch, void* stream);
 
+/* ssm_gram for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same computation and result,
+ * with no scratch argument.  The partial sums go to a device array of
+ * SSM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends; its address is looked up on the first call on each device (with the
+ * current device being the one stream runs on).  The call allocates nothing.
+ * SSM_ERR_UNSUPPORTED when the partial sums, 4 nseg ntb 2 nv^2 doubles, exceed the array.
+ * Every call on one GPU shares that GPU's array and leaves its own partial sums in it
+ * (each call writes every partial sum it reads, so nothing needs clearing): calls on one
+ * stream are ordered, but calls that overlap on one GPU (other streams, other threads)
+ * race. */
+#define SSM_NOALLOC_SCRATCH_BYTES (32 << 20)
+ssm_status ssm_gram_noalloc(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
+                            double* k_w, double* k_z, int32_t nseg, void* stream);
+
 /* Algorithm 4 and the trace, for ntb points: for point i, eig(k_w[i]) = U S U^T,
  * keep s_j >= tau max_j s_j (nothing if max s <= 0), B = S~^-1/2 U~^T k_z[i]
  * U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi in [0, (1 + rho) g_max];

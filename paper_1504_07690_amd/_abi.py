@@ -90,6 +90,7 @@ _SIGS = {
     "ssm_sweep_split": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P, _P, C.c_int64, _P, _P, C.c_int32, C.c_int32,
                                  _P]),
     "ssm_gram": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P]),
+    "ssm_gram_noalloc": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
     "ssm_geneig_trace": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P,
                                    _P, _P]),
 }

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,33 @@ ssm_status hip_fail(hipError_t e, const char* what) {
     hipError_t e_ = (call);                        \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
+
+// Scratch of ssm_gram_noalloc: the Gram kernel's partial sums, in a device array that
+// every GPU the library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device address): the
+// address comes from hipGetSymbolAddress, once per device with that device current.
+static __device__ __align__(256) double scratch[SSM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+ssm_status noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SSM_ERR_UNSUPPORTED, "device %d beyond the %d handled", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+    if (!p) return fail(SSM_ERR_HIP, "hipGetSymbolAddress gave no address for the scratch array");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SSM_OK;
+}
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -1447,24 +1475,46 @@ ssm_status ssm_sweep_split(int64_t e, int32_t kc, int32_t ntb, const void* chi, 
   return err == hipSuccess ? SSM_OK : hip_fail(err, "split sweep GEMM");
 }
 
-ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z, double* k_w,
-                    double* k_z, int32_t nseg, double* scratch, void* stream) {
-  if (!w || !z || !k_w || !k_z || !scratch) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+static ssm_status check_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
+                             double* k_w, double* k_z, int32_t nseg) {
+  if (!w || !z || !k_w || !k_z) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
   if (n < 1 || ntb < 1 || nseg < 1) return fail(SSM_ERR_ARG, "need n, ntb, nseg >= 1");
   if (nv < 4 || nv % 4) return fail(SSM_ERR_ARG, "nv must be a positive multiple of 4");
   if (nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d", kMaxNv);
   if (precision < SSM_FP64 || precision > SSM_FP32_BF16X3) return fail(SSM_ERR_ARG, "bad precision");
-  hipError_t err = ssm::launch_gram(precision != SSM_FP64, n, nv, ntb, w, z, k_w, k_z, nseg, scratch, (hipStream_t)stream);
+  return SSM_OK;
+}
+
+ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z, double* k_w,
+                    double* k_z, int32_t nseg, double* work, void* stream) {
+  ssm_status s = check_gram(precision, n, nv, ntb, w, z, k_w, k_z, nseg);
+  if (s != SSM_OK) return s;
+  if (!work) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+  hipError_t err = ssm::launch_gram(precision != SSM_FP64, n, nv, ntb, w, z, k_w, k_z, nseg, work, (hipStream_t)stream);
+  return err == hipSuccess ? SSM_OK : hip_fail(err, "Gram kernel");
+}
+
+ssm_status ssm_gram_noalloc(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
+                            double* k_w, double* k_z, int32_t nseg, void* stream) {
+  ssm_status s = check_gram(precision, n, nv, ntb, w, z, k_w, k_z, nseg);
+  if (s != SSM_OK) return s;
+  const double need = (double)ssm::gram_scratch_slots(nseg) * ntb * 2.0 * nv * nv * sizeof(double);
+  if (need > (double)SSM_NOALLOC_SCRATCH_BYTES)
+    return fail(SSM_ERR_UNSUPPORTED, "ssm_gram_noalloc: %.0f bytes of partial sums exceed the %d-byte scratch array "
+                "(use fewer points or segments per call)", need, SSM_NOALLOC_SCRATCH_BYTES);
+  double* ptr = nullptr;
+  if ((s = noalloc_scratch(&ptr)) != SSM_OK) return s;
+  hipError_t err = ssm::launch_gram(precision != SSM_FP64, n, nv, ntb, w, z, k_w, k_z, nseg, ptr, (hipStream_t)stream);
   return err == hipSuccess ? SSM_OK : hip_fail(err, "Gram kernel");
 }
 
 ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max, double tau,
-                            double rho, double* dos_dev, int32_t* ranks_dev, double* scratch, void* stream) {
-  if (!k_w || !k_z || !dos_dev || !scratch) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
+                            double rho, double* dos_dev, int32_t* ranks_dev, double* work, void* stream) {
+  if (!k_w || !k_z || !dos_dev || !work) return fail(SSM_ERR_ARG, "pointers must be non-NULL");
   if (nv < 1 || ntb < 1) return fail(SSM_ERR_ARG, "need nv, ntb >= 1");
   if (nv > kMaxNv) return fail(SSM_ERR_UNSUPPORTED, "nv > %d", kMaxNv);
   if (!(g_max > 0) || !std::isfinite(tau) || !std::isfinite(rho)) return fail(SSM_ERR_ARG, "bad g_max/tau/rho");
-  hipError_t err = ssm::launch_geneig_trace(nv, ntb, k_w, k_z, g_max, tau, rho, dos_dev, ranks_dev, scratch,
+  hipError_t err = ssm::launch_geneig_trace(nv, ntb, k_w, k_z, g_max, tau, rho, dos_dev, ranks_dev, work,
                                             (hipStream_t)stream);
   return err == hipSuccess ? SSM_OK : hip_fail(err, "Algorithm 4 kernel");
 }

@@ -324,6 +324,15 @@ def gram(precision, w: torch.Tensor, z: torch.Tensor, k_w: torch.Tensor, k_z: to
     return scratch
 
 
+def gram_noalloc(precision, w: torch.Tensor, z: torch.Tensor, k_w: torch.Tensor, k_z: torch.Tensor, nseg=1):
+    """ssm_gram_noalloc: the Gram stage call with the library's own static scratch array."""
+    _require_cuda(w, z, k_w, k_z)
+    n, nv = w.shape
+    ntb = z.shape[0]
+    A.check(A.lib.ssm_gram_noalloc(PRECISION[precision], int(n), int(nv), int(ntb), _ptr(w), _ptr(z), _ptr(k_w),
+                                   _ptr(k_z), int(nseg), _stream()), "ssm_gram_noalloc")
+
+
 def geneig_trace(k_w: torch.Tensor, k_z: torch.Tensor, g_max, tau, rho, dos: torch.Tensor,
                  ranks: torch.Tensor | None = None):
     _require_cuda(k_w, k_z, dos, ranks)

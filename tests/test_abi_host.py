@@ -332,3 +332,13 @@ def test_plan_overrides(A):
     assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == 0 and out.value == full.value
     p = _params(A, nv=nv, degree=50, nt=nt, precision=0, method=1, plan_chunk=16)
     assert A.lib.ssm_workspace_size(C.byref(csr), C.byref(p), 0, C.byref(out)) == A.SSM_ERR_ARG
+
+
+def test_gram_noalloc_limit_checked_on_the_host(A):
+    """ssm_gram_noalloc refuses partial sums beyond its static array (4 nseg ntb 2 nv^2
+    doubles over SSM_NOALLOC_SCRATCH_BYTES) and bad arguments before any device work."""
+    assert A.lib.ssm_gram_noalloc(1, 64, 256, 1, 1, 1, 1, 1, 9, None) == A.SSM_ERR_UNSUPPORTED
+    assert A.lib.ssm_gram_noalloc(1, 64, 256, 2000, 1, 1, 1, 1, 1, None) == A.SSM_ERR_UNSUPPORTED
+    assert A.lib.ssm_gram_noalloc(1, 64, 6, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_gram_noalloc(1, 64, 8, 1, None, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_gram_noalloc(9, 64, 8, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
