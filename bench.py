@@ -5,14 +5,18 @@ disorder uniform in [-2, 2]), N_v = 80, Chebyshev degree M = 1000, N_t = 1000
 midpoint sweep points, sigma = 0.01 in the rescaled variable.  Default path: FP32
 recurrence, split-BF16 (three BF16 MFMA products, FP32 accumulation) sweep, FP64
 Gram / Algorithm 4; the FP64, FP32 and plain-BF16 paths are timed beside it with
-their DOS L1 against the FP64 path.  One step = one full ssm_dos (coefficients and
-W are set up once, outside the timed region).  The adjoint (ssm_backward) of the
+their DOS L1 against the FP64 path.  One step = the whole path: ssm_create's set-up on
+the context's workspace (the coefficients of Algorithm 1, W, the split tables) and one
+ssm_dos.  The adjoint (ssm_backward) of the
 measured path is timed once after the steps, and so is one ssm_dos that also forms the
 DGC estimate of Algorithm 2 from the same recurrence, and RESS-DGC (Algorithm 7, FP64)
-with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6).
+with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6), the random-graph
+workload's whole DOS and the 27-point workload's recurrence rate.  The oracle's baseline
+runs first, on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
                     [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint] [--no-dgc] [--no-ress]
+                    [--no-large]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -56,41 +60,95 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, sample_steps=30, sample_points=2):
-    """The oracle, as it stands, on a bounded sample of the same workload, one thread;
-    extrapolated to the full DOS (seconds per DOS)."""
+def _oracle_point_worker(args):
+    """One sweep point of the oracle on the first `steps` blocks (a process of the pool):
+    seconds for its coefficients, per block of its sweep, and for its Gram matrices and
+    Algorithm 4.  One thread per process."""
+    cfg, point, steps = args
     from threadpoolctl import threadpool_limits
 
     from oracle import ssm_oracle as O
+    from paper_1504_07690_amd import workloads as WL
+    with threadpool_limits(1):
+        wl = WL.make_workload(cfg)
+        w = wl.w()
+        blocks = [v for _, v in O.chebyshev_blocks(wl.a, w, steps, wl.lo, wl.hi)]
+        t0 = time.perf_counter()
+        mu = O.dgc_coefficients(wl.t[[point]], wl.degree, wl.sigma, wl.a.n, wl.lo, wl.hi)
+        t_coef = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        z = O.sweep(mu[: steps + 1], iter(blocks))
+        t_axpy = (time.perf_counter() - t0) / (steps + 1)
+        t0 = time.perf_counter()
+        kw, kz = O.gram(w, z[0])
+        O.geneig_trace(kw, kz, O.range_bound(wl.sigma, wl.a.n))
+        t_point = time.perf_counter() - t0
+    return t_coef, t_axpy, t_point
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(cfg, sample_steps=16, max_workers=16):
+    """The oracle, as it stands, on a bounded sample of the same workload, on the host's
+    cores (run before anything touches the GPU: the pool forks).  The recurrence's sparse
+    products are sequential (the oracle's, one core): timed on `sample_steps` steps.  The
+    sweep points are independent given the blocks: one point per process of a pool of up to
+    16 processes (the host's share), each timing its coefficients, its sweep over the sample
+    blocks and its Gram matrices and Algorithm 4 while the others run.  Extrapolated to M
+    steps and N_t points (seconds per DOS)."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ssm_oracle as O
+    from paper_1504_07690_amd import workloads as WL
+    model, nproc = host_cpu()
+    workers = max(1, min(max_workers, nproc))
+    wl = WL.make_workload(cfg)
     with threadpool_limits(1):
         w = wl.w()
-        pts = np.linspace(0, wl.nt - 1, sample_points).astype(int)
+        it = O.chebyshev_blocks(wl.a, w, sample_steps, wl.lo, wl.hi)
+        next(it)
         t0 = time.perf_counter()
-        mu = O.dgc_coefficients(wl.t[pts], wl.degree, wl.sigma, wl.a.n, wl.lo, wl.hi)
-        t_coef = (time.perf_counter() - t0) / sample_points
-        blocks = []
-        t0 = time.perf_counter()
-        for l, v in O.chebyshev_blocks(wl.a, w, sample_steps, wl.lo, wl.hi):
-            blocks.append(v)
+        for _ in it:
+            pass
         t_step = (time.perf_counter() - t0) / sample_steps
-        t0 = time.perf_counter()
-        z = O.sweep(mu[: sample_steps + 1], iter(blocks))
-        t_axpy = (time.perf_counter() - t0) / ((sample_steps + 1) * sample_points)
-        t0 = time.perf_counter()
-        g_max = O.range_bound(wl.sigma, wl.a.n)
-        for i in range(sample_points):
-            kw, kz = O.gram(w, z[i])
-            O.geneig_trace(kw, kz, g_max)
-        t_point = (time.perf_counter() - t0) / sample_points
+    del w, it
+    pts = np.linspace(0, wl.nt - 1, workers).astype(int)
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_point_worker, [(cfg, int(p), sample_steps) for p in pts])
+    t_coef, t_axpy, t_point = (float(np.mean([r[k] for r in res])) for k in range(3))
     m1 = wl.degree + 1
-    total = t_coef * wl.nt + t_step * wl.degree + t_axpy * m1 * wl.nt + t_point * wl.nt
+    per_point = t_coef + t_axpy * m1 + t_point
+    total = t_step * wl.degree + per_point * wl.nt / workers
     return {
-        "value": total, "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"{sample_steps} Chebyshev steps, the sweep of {sample_points} points over them, "
-                   f"Gram + Algorithm 4 for {sample_points} points; extrapolated to M={wl.degree}, "
-                   f"N_t={wl.nt}: coeff {t_coef:.3g} s/point, step {t_step:.3g} s, axpy {t_axpy:.3g} s, "
-                   f"Gram+eig {t_point:.3g} s/point"),
+        "value": total, "unit": "s", "cores": workers, "kind": "oracle",
+        "sample": (f"host {model}, {nproc} cores visible, {workers} used: {sample_steps} Chebyshev steps "
+                   f"(sequential sparse products, {t_step:.3g} s/step); {workers} sweep points in {workers} "
+                   f"processes (one thread each), each its coefficients ({t_coef:.3g} s), its sweep over the "
+                   f"{sample_steps + 1} blocks ({t_axpy:.3g} s/block), Gram + Algorithm 4 ({t_point:.3g} s); "
+                   f"extrapolated to M={wl.degree} steps and N_t={wl.nt} points over {workers} processes"),
     }
+
+
+def spmm_bytes_models(n, nnz, nv, es):
+    """Bytes of one Chebyshev step: compulsory (Y_k and Y_{k-1} read once, Y_{k+1} written,
+    the CSR read once) and gather-inclusive (Y_k read once per stored entry instead)."""
+    e = n * nv
+    compulsory = 3 * e * es + nnz * (4 + es) + (n + 1) * 4
+    gather = compulsory - e * es + nnz * nv * es
+    return compulsory, gather
 
 
 def main():
@@ -105,6 +163,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the timing of the adjoint (ssm_backward)")
     ap.add_argument("--no-dgc", action="store_true", help="skip the run with the DGC moments (Algorithm 2)")
     ap.add_argument("--no-ress", action="store_true", help="skip the RESS-DGC runs (Algorithm 7)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the random-graph DOS and the 27-point recurrence rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -113,6 +173,14 @@ def main():
         print("bench.py runs on one GPU only: the sweep-point batches would shard across GPUs with no "
               "communication until a final gather, and that path is not built; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's baseline first: its process pool forks before anything touches the GPU
+    baseline = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample on the host cores ...")
+        t0 = time.time()
+        baseline = cpu_baseline(2)
+        log(f"oracle baseline: {baseline['value']:.4g} s per DOS extrapolated ({time.time() - t0:.1f} s)")
 
     import torch
 
@@ -135,23 +203,31 @@ def main():
     e = n * nv
 
     adjoint = {}
-
     dgc_out = {}
 
     def run(precision, steps, warmup, budget=0, with_adjoint=False, dgc=False):
+        """`steps` timed steps, each the whole path: ssm_create's set-up on the context's
+        workspace (coefficients of Algorithm 1, W, split tables) and ssm_dos."""
         dt = torch.float64 if precision == "fp64" else torch.float32
         csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=dev)
         ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=wl.t, precision=precision,
-                    seed=wl.seed, budget=budget, dgc=dgc, device=dev)
+                    seed=wl.seed, budget=budget, dgc=dgc, lattice=wl.lattice, device=dev)
         for _ in range(warmup):
+            ctx.reset()
             ctx.dos()
         torch.cuda.synchronize()
+        t_setup = 0.0
         t_start = time.perf_counter()
         for _ in range(steps):
+            t_s = time.perf_counter()
+            ctx.reset()  # ssm_create synchronises before it returns
+            t_setup += time.perf_counter() - t_s
             dos, r1, r2 = ctx.dos()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t_start) * 1e3 / max(steps, 1)
+        ms_setup = t_setup * 1e3 / max(steps, 1)
         st = ctx.stats()
+        st["ms_setup"] = ms_setup
         if dgc:
             dgc_out["dos"], _ = ctx.dgc()
         if with_adjoint:
@@ -171,27 +247,27 @@ def main():
         ctx.close()
         del ctx, csr
         torch.cuda.empty_cache()
-        log(f"{precision}: {ms:.1f} ms/DOS  phases {st}")
+        log(f"{precision}: {ms:.1f} ms per step (set-up {ms_setup:.2f} ms + DOS)  phases {st}")
         return ms, dos, r1, r2, st
 
-    def budget_left():
+    def budget_left(reserve_gib=6):
         free, _ = torch.cuda.mem_get_info()
-        return int(free - 6 * (1 << 30))
+        return int(free - reserve_gib * (1 << 30))
 
     ms, dos, r1, r2, st = run(args.precision, args.steps, args.warmup, budget=0,
                               with_adjoint=not args.no_adjoint)
     es = 8 if args.precision == "fp64" else 4
 
-    # Chebyshev block-SpMM: compulsory bytes per launch = Y_k, Y_{k-1} read, Y_{k+1}
-    # written, CSR read once
-    spmm_bytes = 3 * e * es + wl.a.nnz * (4 + es) + (n + 1) * 4
+    spmm_bytes, _ = spmm_bytes_models(n, wl.a.nnz, nv, es)
     spmm_us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
     spmm_gbps = spmm_bytes / (spmm_us * 1e-6) / 1e9
     # sweep GEMM: 2 e (M+1) N_t flops
     sweep_flops = 2.0 * e * (m + 1) * wl.nt
     sweep_tflops = sweep_flops / (st["ms_sweep"] * 1e-3) / 1e12
-    gram_flops = 3.0 * n * nv * nv * wl.nt  # W^T Z (2 n nv^2) + the symmetric Z^T Z (n nv^2), per point
-    phases = {k: st[k] for k in ("ms_total", "ms_recurrence", "ms_sweep", "ms_gram", "ms_geneig")}
+    # Gram: the symmetric K_Z and K_W need N N_v (N_v + 1) multiply-adds each per point; the
+    # kernel issues the upper 16 x 16 blocks (2 N N_v (N_v + 16) flops per point)
+    gram_flops = 2.0 * n * nv * (nv + 1) * wl.nt
+    phases = {k: st[k] for k in ("ms_setup", "ms_total", "ms_recurrence", "ms_sweep", "ms_gram", "ms_geneig")}
     dom = max(("sweep", st["ms_sweep"]), ("spmm", st["ms_recurrence"]), ("gram", st["ms_gram"]),
               key=lambda kv: kv[1])[0]
     if dom == "sweep":
@@ -221,11 +297,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n": n, "nnz": wl.a.nnz, "nv": nv, "degree": m, "nt": wl.nt,
                    "sigma_hat": wl.sigma_hat, "recurrence_sweep": args.precision, "gram_eig": "fp64",
+                   "lattice": list(wl.lattice),
+                   "step": "ssm_create set-up (coefficients, W, split tables) + ssm_dos",
                    "plan": {"passes": st["passes"], "chunk": st["chunk"], "batch": st["batch"]}},
         "spmm": {"GBps": spmm_gbps, "frac_hbm": spmm_gbps / HBM_PEAK_GBPS, "bytes_per_launch": spmm_bytes,
                  "us_per_launch": spmm_us, "launches": st["spmm_launches"]},
         "sweep": {"TFLOPs": sweep_tflops, "frac_mfma": sweep_tflops / MFMA_PEAK_TFLOPS[args.precision],
                   "three_product_degrees": st["split_k3"] if args.precision == "bf16x3" else None},
+        "gram": {"TFLOPs": gram_flops / (st["ms_gram"] * 1e-3) / 1e12,
+                 "frac_mfma_fp64": gram_flops / (st["ms_gram"] * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp64"]},
         "phases_ms": phases,
         "roofline": roof,
     }
@@ -259,7 +339,8 @@ def main():
         for nvr, nvh in ((80, 0), (40, 40)):
             csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=dev)
             ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nvr, degree=m, t=wl.t, precision="fp64",
-                        seed=wl.seed, method="ress", nv_hybrid=nvh, budget=budget_left(), device=dev)
+                        seed=wl.seed, method="ress", nv_hybrid=nvh, budget=budget_left(), lattice=wl.lattice,
+                        device=dev)
             ctx.dos()
             torch.cuda.synchronize()
             t_r = time.perf_counter()
@@ -281,10 +362,67 @@ def main():
     out["comparisons"] = comparisons
     if adjoint:
         out["adjoint"] = adjoint
-    if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(wl)
+    if not args.no_large:
+        out["large"] = large_workloads(S, WL, torch, dev, budget_left)
+    if baseline is not None:
+        out["cpu_baseline"] = baseline
     print(json.dumps(out), flush=True)
+
+
+def large_workloads(S, WL, torch, dev, budget_left):
+    """The random-graph workload's whole DOS (split-BF16 sweep, sweep-point batches as
+    planned in the free memory; its DOS against the stored oracle values when present), and
+    the 27-point workload's recurrence rate (N_v = 256, a run of 400 steps on 8 points)."""
+    res = {}
+    wl = WL.make_workload(3)
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision="bf16x3",
+                seed=wl.seed, budget=budget_left(12), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.reset()
+    dos, r1, r2 = ctx.dos()
+    s_dos = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    torch.cuda.empty_cache()
+    comp, gath = spmm_bytes_models(wl.a.n, wl.a.nnz, wl.nv, 4)
+    us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
+    entry = {"workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv, "degree": wl.degree, "nt": wl.nt,
+             "precision": "bf16x3", "s_per_dos": s_dos,
+             "plan": {"passes": st["passes"], "chunk": st["chunk"], "batch": st["batch"]},
+             "phases_ms": {k: st[k] for k in ("ms_recurrence", "ms_sweep", "ms_gram", "ms_geneig")},
+             "spmm_us_per_step": us, "spmm_GBps_compulsory": comp / (us * 1e-6) / 1e9,
+             "spmm_GBps_gather_inclusive": gath / (us * 1e-6) / 1e9}
+    golden = os.path.join(ROOT, "tests", "golden", "er_graph_2p20_fp64_oracle.json")
+    if os.path.exists(golden):
+        with open(golden) as fh:
+            g = json.load(fh)
+        pts, ref = np.array(g["points"]), np.array(g["dos"])
+        entry["dos_l1_vs_oracle_points"] = float(np.abs(dos[pts] - ref).sum() / np.abs(ref).sum())
+    res["random_graph_dos"] = entry
+    log(f"random graph: {s_dos:.2f} s per DOS, plan {entry['plan']}, {us:.0f} us per step")
+
+    wl = WL.make_workload(5, degree=400)
+    t = wl.t[wl.nt // 16::wl.nt // 8]
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=t, precision="bf16x3",
+                seed=wl.seed, budget=budget_left(12), lattice=wl.lattice, device=dev)
+    ctx.dos()
+    ctx.dos()
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    torch.cuda.empty_cache()
+    comp, _ = spmm_bytes_models(wl.a.n, wl.a.nnz, wl.nv, 4)
+    us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
+    res["stencil27_recurrence"] = {"workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv,
+                                   "steps": st["spmm_launches"], "us_per_step": us,
+                                   "GBps_compulsory": comp / (us * 1e-6) / 1e9,
+                                   "frac_hbm": comp / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+    log(f"27-point recurrence: {us:.0f} us per step, {res['stencil27_recurrence']['GBps_compulsory']:.0f} GB/s")
+    return res
 
 
 if __name__ == "__main__":

@@ -121,6 +121,11 @@ typedef struct ssm_params {
                               multiple of 16 when below M+1 (SSM_SS_DGC).  With either set,
                               ssm_workspace_size and ssm_create return SSM_ERR_WORKSPACE when
                               that plan does not fit the budget */
+  int32_t lattice[3];      /* 0, 0, 0, or (nx, ny, nz) with nx ny nz = N when row x + nx (y + ny z)
+                              is point (x, y, z) of a lattice (a stencil matrix): the recurrence then
+                              computes the rows tile by tile of the x-y plane, each tile through
+                              every z, so that the rows a stencil gathers stay in the L2.  The
+                              results do not depend on it (a visiting order only) */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)

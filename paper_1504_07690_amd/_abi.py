@@ -33,7 +33,7 @@ class ssm_params(C.Structure):
                 ("range_slack", C.c_double), ("nv", C.c_int32), ("degree", C.c_int32), ("nt", C.c_int32),
                 ("precision", C.c_int32), ("seed", C.c_uint64), ("ckpt_every", C.c_int32), ("dgc", C.c_int32),
                 ("method", C.c_int32), ("nv_hybrid", C.c_int32), ("floor_scale", C.c_double),
-                ("plan_batch", C.c_int32), ("plan_chunk", C.c_int32)]
+                ("plan_batch", C.c_int32), ("plan_chunk", C.c_int32), ("lattice", C.c_int32 * 3)]
 
 
 class ssm_stats(C.Structure):

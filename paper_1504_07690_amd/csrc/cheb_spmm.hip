@@ -37,6 +37,13 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 //
 // out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null; the reverse
 // recurrence of the adjoint uses d for its direct seed).
+//
+// Rows of a lattice (row x + nx (y + ny z)) are visited tile by tile: tiles of tx x ty
+// points of the x-y plane, each swept through every z, XCD x taking a contiguous eighth
+// of the tiles.  The rows a stencil gathers for a tile's plane z are then the tile's planes
+// z - 1, z, z + 1 and a one-point halo, a few hundred KB that the XCD's L2 keeps between
+// the planes that reuse them; in plain row order the reuse spans two whole planes
+// (16 MB at 128^2 points of 256 FP32 values), beyond the L2.
 template <typename V>
 __device__ __forceinline__ double vdot(const V& u, const V& v);
 template <>
@@ -55,28 +62,76 @@ __device__ __forceinline__ double vdot<f64x2>(const f64x2& u, const f64x2& v) {
 // reading the block the step before wrote), and 1024 slowed the FP64 and moment variants.
 constexpr int CS_THREADS = 256;
 
-template <typename T, typename V, bool DOTS, bool KEEP>
+// row visited at position rho of the tiled order
+__device__ __forceinline__ int64_t tiled_row(int64_t rho, const RowOrder& o) {
+  const int tile_rows = o.tx * o.ty;
+  const int64_t col_rows = (int64_t)tile_rows * o.nz;  // a tile swept through every z
+  const int tile = (int)(rho / col_rows);
+  const int64_t rem = rho - (int64_t)tile * col_rows;
+  const int z = (int)(rem / tile_rows);
+  const int in = (int)(rem - (int64_t)z * tile_rows);
+  const int yy = in / o.tx, xx = in - yy * o.tx;
+  const int tiles_x = o.nx / o.tx;
+  const int ty_i = tile / tiles_x, tx_i = tile - ty_i * tiles_x;
+  return (int64_t)(tx_i * o.tx + xx) + (int64_t)o.nx * ((int64_t)(ty_i * o.ty + yy) + (int64_t)o.ny * z);
+}
+
+// WAVE_ROW (N_v elements of a row fill whole waves, 1 KB and more): the row index is the
+// same on every lane of a wave, so its CSR entries are read through the scalar cache (one
+// scalar load per entry or per 8 entries) instead of by 64 lanes reading the same address:
+// a 27-point row then issues 27 vector gathers instead of 81 vector loads.
+template <typename T, typename V, bool DOTS, bool KEEP, bool TILED, bool WAVE_ROW>
 __global__ void __launch_bounds__(CS_THREADS) cheb_step_kernel(int64_t n, int nvv, int64_t nblocks, int64_t per_xcd,
                                                         const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col_idx,
                                                         const T* __restrict__ val, T a, T b, T c,
                                                         const V* __restrict__ x, const V* __restrict__ xprev,
                                                         const V* __restrict__ d, V* __restrict__ out,
-                                                        double* __restrict__ dots) {
+                                                        double* __restrict__ dots, RowOrder order) {
   const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (lblock >= nblocks) return;  // uniform over the workgroup
   const int64_t gid0 = lblock * blockDim.x + threadIdx.x;
   const bool valid = gid0 < n * (int64_t)nvv;
   if (!DOTS && !valid) return;
-  const int64_t gid = valid ? gid0 : 0;  // idle lanes of a DOTS block recompute slice 0 and store nothing
-  const int64_t r = gid / nvv;
-  const int q = (int)(gid - r * nvv);
+  const int64_t vid = valid ? gid0 : 0;  // idle lanes of a DOTS block recompute slice 0 and store nothing
+  const int64_t rho = vid / nvv;
+  const int q = (int)(vid - rho * nvv);
+  const int64_t r = TILED ? tiled_row(rho, order) : rho;
+  const int64_t gid = r * nvv + q;
   V xp = (V)(T)0, dd = (V)(T)0;  // streamed operands first: they do not depend on the row's CSR
   if (xprev) xp = __builtin_nontemporal_load(&xprev[gid]);
   if (d) dd = __builtin_nontemporal_load(&d[gid]);
+  V acc = (V)(T)0;
+  if constexpr (WAVE_ROW) {
+    const int ru = __builtin_amdgcn_readfirstlane((int)r);
+    const int p0 = row_ptr[ru];
+    const int p1 = row_ptr[ru + 1];
+    for (int p = p0; p < p1; p += 8) {
+      const int cnt = p1 - p;  // uniform
+      int cols[8];
+      T vals[8];
+      if (cnt >= 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          cols[j] = col_idx[p + j];
+          vals[j] = val[p + j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          cols[j] = j < cnt ? col_idx[p + j] : ru;
+          vals[j] = j < cnt ? val[p + j] : (T)0;
+        }
+      }
+      V g[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[j] = (j < cnt) ? x[(int64_t)cols[j] * nvv + q] : (V)(T)0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
+    }
+  } else {
   const int p0 = row_ptr[r];
   const int p1 = row_ptr[r + 1];
-  V acc = (V)(T)0;
   for (int p = p0; p < p1; p += 8) {
     int cols[8];
     T vals[8];
@@ -96,6 +151,7 @@ __global__ void __launch_bounds__(CS_THREADS) cheb_step_kernel(int64_t n, int nv
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc += vals[j] * g[j];
+  }
   }
   const V xo = x[gid];
   V res = a * acc + b * xo;
@@ -174,9 +230,31 @@ __global__ void __launch_bounds__(256) dgc_kernel(const double* __restrict__ c, 
   out[i] = acc;
 }
 
+template <typename T, typename V, bool TILED, bool WR>
+hipError_t launch_v(dim3 grid, bool keep, int64_t n, int nvv, int64_t nblocks, int64_t per_xcd, const int32_t* row_ptr,
+                    const int32_t* col_idx, const T* val, T a, T b, T c, const T* x, const T* xprev, const T* d, T* out,
+                    double* dots, const RowOrder& o, hipStream_t stream) {
+  const dim3 block(CS_THREADS);
+  if (dots && keep)
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, true, true, TILED, WR>), grid, block, 0, stream, n, nvv, nblocks, per_xcd,
+                       row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, dots, o);
+  else if (dots)
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, true, false, TILED, WR>), grid, block, 0, stream, n, nvv, nblocks, per_xcd,
+                       row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, dots, o);
+  else if (keep)
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, false, true, TILED, WR>), grid, block, 0, stream, n, nvv, nblocks, per_xcd,
+                       row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, nullptr, o);
+  else
+    hipLaunchKernelGGL((cheb_step_kernel<T, V, false, false, TILED, WR>), grid, block, 0, stream, n, nvv, nblocks,
+                       per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out,
+                       nullptr, o);
+  return hipGetLastError();
+}
+
 template <typename T, typename V, int VEC>
 hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx, const T* val, T a, T b,
-                  T c, const T* x, const T* xprev, const T* d, T* out, double* dots, hipStream_t stream) {
+                  T c, const T* x, const T* xprev, const T* d, T* out, double* dots, const RowOrder& o,
+                  hipStream_t stream) {
   const int nvv = nv / VEC;
   const int64_t threads = n * nvv;
   const int64_t nblocks = (threads + CS_THREADS - 1) / CS_THREADS;
@@ -184,20 +262,21 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
   if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
   // the written block is kept in the caches up to 128 MiB (see the store above)
   const bool keep = n * nv * (int64_t)sizeof(T) <= ((int64_t)128 << 20);
-  const dim3 grid((unsigned)(per_xcd * 8)), block(CS_THREADS);
-  if (dots && keep)
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, true, true>), grid, block, 0, stream, n, nvv, nblocks, per_xcd, row_ptr,
-                       col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, dots);
-  else if (dots)
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, true, false>), grid, block, 0, stream, n, nvv, nblocks, per_xcd, row_ptr,
-                       col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, dots);
-  else if (keep)
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, false, true>), grid, block, 0, stream, n, nvv, nblocks, per_xcd, row_ptr,
-                       col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, nullptr);
-  else
-    hipLaunchKernelGGL((cheb_step_kernel<T, V, false, false>), grid, block, 0, stream, n, nvv, nblocks, per_xcd, row_ptr,
-                       col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, nullptr);
-  return hipGetLastError();
+  const dim3 grid((unsigned)(per_xcd * 8));
+  if (o.nx > 0) {
+    if (!(o.tx > 0 && o.ty > 0 && o.nx % o.tx == 0 && o.ny % o.ty == 0 && (int64_t)o.nx * o.ny * o.nz == n))
+      return hipErrorInvalidValue;
+    if (nvv % 64 == 0)
+      return launch_v<T, V, true, true>(grid, keep, n, nvv, nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, x, xprev,
+                                        d, out, dots, o, stream);
+    return launch_v<T, V, true, false>(grid, keep, n, nvv, nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, x, xprev,
+                                       d, out, dots, o, stream);
+  }
+  if (nvv % 64 == 0)
+    return launch_v<T, V, false, true>(grid, keep, n, nvv, nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, x, xprev,
+                                       d, out, dots, o, stream);
+  return launch_v<T, V, false, false>(grid, keep, n, nvv, nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, x, xprev,
+                                      d, out, dots, o, stream);
 }
 
 }  // namespace
@@ -205,15 +284,15 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
                                 const double* xprev, const double* d, double* out, hipStream_t stream,
-                                double* dots) {
-  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, stream);
+                                double* dots, const RowOrder& order) {
+  return launch<double, f64x2, 2>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, order, stream);
 }
 
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
                                 const float* xprev, const float* d, float* out, hipStream_t stream,
-                                double* dots) {
-  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, stream);
+                                double* dots, const RowOrder& order) {
+  return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, order, stream);
 }
 
 int64_t cheb_step_blocks(int64_t n, int nv, int is_f32) {

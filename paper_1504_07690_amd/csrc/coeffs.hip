@@ -105,6 +105,22 @@ __global__ void __launch_bounds__(256) coefficient_norms_kernel(const double* __
   if (q == 0 && i < nt) mun[i] = sqrt(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
+// kmax[l] = max_i |c[l][i]|: one workgroup per degree
+__global__ void __launch_bounds__(256) coefficient_row_max_kernel(const double* __restrict__ c, int64_t ldc, int nt,
+                                                                  double* __restrict__ kmax) {
+  __shared__ double red[256];
+  const double* row = c + (int64_t)blockIdx.x * ldc;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nt; i += 256) m = fmax(m, fabs(row[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) kmax[blockIdx.x] = red[0];
+}
+
 __global__ void __launch_bounds__(256) rounding_floor_kernel(const double* __restrict__ mun, int nt, double eta,
                                                              const double* __restrict__ w_sumsq, double inv_sqrt_e,
                                                              double* __restrict__ out) {
@@ -117,6 +133,12 @@ __global__ void __launch_bounds__(256) rounding_floor_kernel(const double* __res
 hipError_t launch_coefficient_norms(const double* c, int64_t ldc, int nt, int m1, double* mun, hipStream_t stream) {
   hipLaunchKernelGGL(coefficient_norms_kernel, dim3((unsigned)((nt + 63) / 64)), dim3(256), 0, stream, c, ldc, nt, m1,
                      mun);
+  return hipGetLastError();
+}
+
+hipError_t launch_coefficient_row_max(const double* c, int64_t ldc, int nt, int m1, double* kmax,
+                                      hipStream_t stream) {
+  hipLaunchKernelGGL(coefficient_row_max_kernel, dim3((unsigned)m1), dim3(256), 0, stream, c, ldc, nt, kmax);
   return hipGetLastError();
 }
 

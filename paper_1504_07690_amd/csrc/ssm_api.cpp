@@ -106,6 +106,9 @@ ssm_status check_params(const ssm_params* p) {
     return fail(SSM_ERR_ARG, "unknown precision %d", p->precision);
   if (p->ckpt_every != 0 && p->ckpt_every < 4) return fail(SSM_ERR_ARG, "ckpt_every must be 0 or >= 4");
   if (p->plan_batch < 0 || p->plan_chunk < 0) return fail(SSM_ERR_ARG, "plan_batch and plan_chunk must be >= 0");
+  const int32_t* lt = p->lattice;
+  if ((lt[0] || lt[1] || lt[2]) && !(lt[0] > 0 && lt[1] > 0 && lt[2] > 0))
+    return fail(SSM_ERR_ARG, "lattice must be all 0 or all positive");
   if (p->plan_batch > 0 && p->plan_batch < p->nt && p->plan_batch % 8)
     return fail(SSM_ERR_ARG, "plan_batch below nt must be a multiple of 8 (got %d)", p->plan_batch);
   if (p->plan_chunk > 0 && p->plan_chunk <= p->degree && p->plan_chunk % kMinChunk)
@@ -126,6 +129,32 @@ ssm_status check_params(const ssm_params* p) {
     if (p->plan_batch || p->plan_chunk) return fail(SSM_ERR_ARG, "plan_batch and plan_chunk apply to SSM_SS_DGC");
   }
   return SSM_OK;
+}
+
+ssm_status check_lattice(const ssm_csr* a, const ssm_params* p) {
+  const int32_t* lt = p->lattice;
+  if (lt[0] && (int64_t)lt[0] * lt[1] * lt[2] != a->n)
+    return fail(SSM_ERR_ARG, "lattice %d x %d x %d does not have n = %lld points", lt[0], lt[1], lt[2],
+                (long long)a->n);
+  return SSM_OK;
+}
+
+// The recurrence's visiting order for a lattice: tiles of the largest power of two up to
+// 16 that divides each of nx and ny (plain row order without a lattice).
+ssm::RowOrder row_order(const ssm_params* p) {
+  ssm::RowOrder o;
+  if (!p->lattice[0]) return o;
+  auto tile = [](int n) {
+    int t = 16;
+    while (n % t) t /= 2;
+    return t;
+  };
+  o.nx = p->lattice[0];
+  o.ny = p->lattice[1];
+  o.nz = p->lattice[2];
+  o.tx = tile(o.nx);
+  o.ty = tile(o.ny);
+  return o;
 }
 
 double eff_tau(const ssm_params* p) { return p->tau > 0 ? p->tau : 1e-7; }
@@ -158,7 +187,7 @@ struct Plan {
   // RESS-DGC: chunk = new blocks per round, ring of chunk + 1 slots
   bool ress = false;
   size_t off_nu = 0, off_kc = 0, off_trw = 0, off_hscr = 0, off_pw = 0, off_pz = 0, off_x = 0, off_kmu = 0,
-         off_knu = 0, off_xmax = 0, off_floor = 0, off_mun = 0;
+         off_knu = 0, off_xmax = 0, off_floor = 0, off_mun = 0, off_kmax = 0;
 };
 
 // Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
@@ -172,20 +201,14 @@ int dgc_group(const ssm_csr* a, const ssm_params* p) {
 }
 
 // Split BF16: one past the last degree whose coefficients reach 2^-8 of the table's
-// largest coefficient (host, from the FP64 table); degrees below it take the three
-// products, the rest one.
-int three_product_degrees(const std::vector<double>& c, int m1, int64_t ldc, int nt) {
+// largest coefficient, from the largest |mu_l(t_i)| of each degree l; degrees below it take
+// the three products, the rest one.
+int three_product_degrees(const std::vector<double>& kmax) {
   double cmax = 0.0;
-  std::vector<double> kmax(m1, 0.0);
-  for (int k = 0; k < m1; ++k)
-    for (int i = 0; i < nt; ++i) {
-      const double v = std::fabs(c[(size_t)k * ldc + i]);
-      cmax = std::max(cmax, v);
-      kmax[k] = std::max(kmax[k], v);
-    }
+  for (double v : kmax) cmax = std::max(cmax, v);
   int k3 = 0;
-  for (int k = 0; k < m1; ++k)
-    if (kmax[k] >= std::ldexp(cmax, -8)) k3 = k + 1;
+  for (size_t k = 0; k < kmax.size(); ++k)
+    if (kmax[k] >= std::ldexp(cmax, -8)) k3 = (int)k + 1;
   return k3;
 }
 
@@ -226,6 +249,7 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
   pl.off_mun = take((size_t)p->nt * 8);
   pl.off_floor = take((size_t)p->nt * 8);
+  pl.off_kmax = take(split ? (size_t)(p->degree + 1) * 8 : 0);
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * pl.batch * 2 * nn * 8);
   pl.off_z = take((size_t)pl.batch * e * es);
   pl.off_y = take((size_t)pl.chunk * e * es);
@@ -344,9 +368,10 @@ ssm_status make_plan(const ssm_csr* a, const ssm_params* p, bool own_w, size_t b
     layout(pl, a, p, own_w);
     if (budget && pl.total > budget) continue;
     const int nchunks = (m1 + chunk - 1) / chunk;
-    // a ring that holds every block forms them in the first pass only
-    const double cost = (chunk == m1 ? 1 : passes) * (p->degree * spmm_bytes) +
-                        passes * (2.0 * nchunks - 1.0) * batch * e * es;
+    // (a ring that holds every block forms them in the first pass only, but the smaller
+    // batches of more passes fill the sweep's point tiles worse: the model keeps one
+    // recurrence per pass)
+    const double cost = passes * (p->degree * spmm_bytes) + passes * (2.0 * nchunks - 1.0) * batch * e * es;
     if (best_cost < 0 || cost < best_cost) {
       best_cost = cost;
       best = pl;
@@ -401,6 +426,7 @@ struct ssm_ctx {
   double* sfloor = nullptr; // rounding floor of Algorithm 4's truncation per point (null: none)
   double* mun = nullptr;    // SS-DGC: sqrt(sum_l mu_l(t_i)^2) per point
   double eta = 0.0;         // SS-DGC: scale of the rounding floor (0: no floor)
+  ssm::RowOrder order;      // the recurrence's visiting order of the rows
   std::vector<double> dos_host;
   bool have_dos = false;
   bool have_dgc = false;
@@ -433,6 +459,7 @@ ssm_status ssm_workspace_size(const ssm_csr* a, const ssm_params* p, size_t budg
   ssm_status s = check_csr(a);
   if (s != SSM_OK) return s;
   if ((s = check_params(p)) != SSM_OK) return s;
+  if ((s = check_lattice(a, p)) != SSM_OK) return s;
   if (!bytes) return fail(SSM_ERR_ARG, "bytes is NULL");
   Plan pl;
   if ((s = make_plan(a, p, true, budget, pl)) != SSM_OK) return s;
@@ -445,6 +472,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   ssm_status s = check_csr(a);
   if (s != SSM_OK) return s;
   if ((s = check_params(p)) != SSM_OK) return s;
+  if ((s = check_lattice(a, p)) != SSM_OK) return s;
   if (!t_host || !out) return fail(SSM_ERR_ARG, "t_host and out must be non-NULL");
   for (int i = 0; i < p->nt; ++i)
     if (!std::isfinite(t_host[i])) return fail(SSM_ERR_ARG, "t[%d] is not finite", i);
@@ -481,6 +509,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->ranks = (int32_t*)(c->ws + pl.off_ranks);
   c->norm = (double*)(c->ws + pl.off_norm);
   c->eta = eff_floor_scale(p);
+  c->order = row_order(p);
   if (c->eta > 0) {
     c->mun = (double*)(c->ws + pl.off_mun);
     c->sfloor = (double*)(c->ws + pl.off_floor);
@@ -531,13 +560,6 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
     if ((e = ssm::launch_split_coefficients(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, pl.ldk, p->nt,
                                             c->stream)) != hipSuccess)
       return bail(hip_fail(e, "coefficient split kernel"));
-    const int m1 = p->degree + 1;
-    std::vector<double> table((size_t)m1 * pl.ldc);
-    if ((e = hipMemcpyAsync(table.data(), c->c64, table.size() * sizeof(double), hipMemcpyDeviceToHost,
-                            c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-      return bail(hip_fail(e, "copy of the coefficient table"));
-    c->k3 = three_product_degrees(table, m1, pl.ldc, p->nt);
   }
   if (pl.ress &&
       (e = ssm::launch_square_coefficients(c->c64, pl.ldc, p->nt, p->degree / 2, c->nu, pl.ldc, c->stream)) !=
@@ -548,7 +570,18 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
                                         c->stream)) != hipSuccess)
       return bail(hip_fail(e, "W generator"));
   }
+  std::vector<double> kmax;
+  if (c->chi) {  // the largest coefficient of each degree
+    kmax.resize(p->degree + 1);
+    double* kmax_dev = (double*)(c->ws + pl.off_kmax);
+    if ((e = ssm::launch_coefficient_row_max(c->c64, pl.ldc, p->nt, p->degree + 1, kmax_dev, c->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(kmax.data(), kmax_dev, kmax.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "largest coefficient per degree"));
+  }
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(hip_fail(e, "ssm_create sync"));
+  if (c->chi) c->k3 = three_product_degrees(kmax);
   c->stats.passes = pl.passes;
   c->stats.chunk = pl.chunk;
   c->stats.batch = pl.batch;
@@ -630,11 +663,12 @@ ssm_status forward_pass(ssm_ctx* c, int pass, bool first, Timeline* tl, int64_t&
           double* dots = moments ? c->dpart + (size_t)(s_step % pl.dgc_group) * 2 * dgc_nblocks : nullptr;
           if (f64)
             err = ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
-                                            (const double*)x, (const double*)xp, nullptr, (double*)out, st, dots);
+                                            (const double*)x, (const double*)xp, nullptr, (double*)out, st, dots,
+                                            c->order);
           else
             err = ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
                                             (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr,
-                                            (float*)out, st, dots);
+                                            (float*)out, st, dots, c->order);
           ++spmm_launches;
           if (err == hipSuccess && moments &&
               (s_step % pl.dgc_group == pl.dgc_group - 1 || s_step == dgc_steps(m) - 1)) {
@@ -843,7 +877,7 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
       const double* xp = kk == 1 ? nullptr : slot(kk - 2);
       err = ssm::launch_cheb_step_f64(n, nvp, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values,
                                       kk == 1 ? alpha : 2.0 * alpha, kk == 1 ? beta : 2.0 * beta,
-                                      kk == 1 ? 0.0 : -1.0, x, xp, nullptr, slot(kk), st);
+                                      kk == 1 ? 0.0 : -1.0, x, xp, nullptr, slot(kk), st, nullptr, c->order);
       if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
       ++spmm_launches;
     }
@@ -1054,9 +1088,11 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
     const double a = xp ? 2 * alpha : alpha, b = xp ? 2 * beta : beta, cc = xp ? -1.0 : 0.0;
     if (f64)
       return ssm::launch_cheb_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, a, b, cc,
-                                       (const double*)x, (const double*)xp, nullptr, (double*)out, st);
+                                       (const double*)x, (const double*)xp, nullptr, (double*)out, st, nullptr,
+                                       c->order);
     return ssm::launch_cheb_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)a,
-                                     (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out, st);
+                                     (float)b, (float)cc, (const float*)x, (const float*)xp, nullptr, (float*)out, st,
+                                     nullptr, c->order);
   };
 
   hipEvent_t ev[2] = {};

@@ -18,16 +18,23 @@ hipError_t launch_square_coefficients(const double* mu, int64_t ldc, int nt, int
 // Philox4x32-10 + Box-Muller block (philox.hip).
 hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, void* w, hipStream_t stream);
 
+// Visiting order of the rows of a lattice, rows x + nx (y + ny z) (nx = 0: plain row
+// order): tiles of tx x ty points of the x-y plane (tx | nx, ty | ny), each through every z.
+struct RowOrder {
+  int nx = 0, ny = 0, nz = 0, tx = 0, ty = 0;
+};
+
 // One Chebyshev step (cheb_spmm.hip):
 //   out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null)
+// The rows are computed in `order` (the result does not depend on it).
 hipError_t launch_cheb_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const double* val, double a, double b, double c, const double* x,
                                 const double* xprev, const double* d, double* out, hipStream_t stream,
-                                double* dots = nullptr);
+                                double* dots = nullptr, const RowOrder& order = RowOrder{});
 hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                 const float* val, float a, float b, float c, const float* x,
                                 const float* xprev, const float* d, float* out, hipStream_t stream,
-                                double* dots = nullptr);
+                                double* dots = nullptr, const RowOrder& order = RowOrder{});
 // Chebyshev moments for Algorithm 2.  With dots (2 cheb_step_blocks doubles) a step also
 // writes workgroup partials of <out, x> and <x, x>.  launch_moments reduces `count`
 // consecutive steps s0.. (partials 2 cheb_step_blocks apart; step s forms Y_{s+1} from
@@ -141,6 +148,9 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
 // mun[i] = sqrt(sum_{l<m1} c[l*ldc + i]^2) (launch_coefficient_norms), then
 // floor[i] = eta * mun[i] * (*w_sumsq) * inv_sqrt_e (launch_rounding_floor), with
 // w_sumsq = ||W||_F^2 on the device and inv_sqrt_e = 1 / sqrt(N N_v).
+// kmax[l] = max_{i < nt} |c[l*ldc + i]| for l < m1
+hipError_t launch_coefficient_row_max(const double* c, int64_t ldc, int nt, int m1, double* kmax,
+                                      hipStream_t stream);
 hipError_t launch_coefficient_norms(const double* c, int64_t ldc, int nt, int m1, double* mun, hipStream_t stream);
 hipError_t launch_rounding_floor(const double* mun, int nt, double eta, const double* w_sumsq, double inv_sqrt_e,
                                  double* floor_out, hipStream_t stream);

@@ -53,20 +53,21 @@ METHOD = {"ss": 0, "ress": 1}
 
 
 def _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every=0, dgc=False, method="ss",
-            nv_hybrid=0, floor_scale=0.0, plan=None) -> A.ssm_params:
+            nv_hybrid=0, floor_scale=0.0, plan=None, lattice=None) -> A.ssm_params:
     batch, chunk = plan if plan is not None else (0, 0)
+    lat = (C.c_int32 * 3)(*(lattice if lattice is not None else (0, 0, 0)))
     return A.ssm_params(float(lo), float(hi), float(sigma), float(tau), float(rho), int(nv), int(degree),
                         int(nt), int(PRECISION[precision]), int(seed) & 0xFFFFFFFFFFFFFFFF, int(ckpt_every),
                         int(bool(dgc)), int(METHOD[method]), int(nv_hybrid), float(floor_scale), int(batch),
-                        int(chunk))
+                        int(chunk), lat)
 
 
 def workspace_size(csr: DeviceCSR, *, lo, hi, sigma, nv, degree, nt, precision="fp32", tau=1e-7, rho=1e-3,
                    seed=0, budget=0, ckpt_every=0, dgc=False, method="ss", nv_hybrid=0, floor_scale=0.0,
-                   plan=None) -> int:
+                   plan=None, lattice=None) -> int:
     out = C.c_size_t(0)
     p = _params(lo, hi, sigma, nv, degree, nt, precision, tau, rho, seed, ckpt_every, dgc, method, nv_hybrid,
-                floor_scale, plan)
+                floor_scale, plan, lattice)
     A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(p), C.c_size_t(budget), C.byref(out)),
             "ssm_workspace_size")
     return int(out.value)
@@ -79,7 +80,7 @@ class SSM:
 
     def __init__(self, csr: DeviceCSR, *, lo, hi, sigma, nv, degree, t, precision="fp32", tau=1e-7, rho=1e-3,
                  seed=0, w: torch.Tensor | None = None, budget=0, ckpt_every=0, dgc=False, method="ss",
-                 nv_hybrid=0, floor_scale=0.0, plan=None, device="cuda:0"):
+                 nv_hybrid=0, floor_scale=0.0, plan=None, lattice=None, device="cuda:0"):
         self.csr = csr
         self.t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         self.nt = int(self.t.size)
@@ -96,20 +97,29 @@ class SSM:
         self.method = method
         self.nv_hybrid = int(nv_hybrid)
         self.params = _params(lo, hi, sigma, nv, degree, self.nt, precision, tau, rho, seed, ckpt_every, dgc,
-                              method, nv_hybrid, floor_scale, plan)
+                              method, nv_hybrid, floor_scale, plan, lattice)
         size = C.c_size_t(0)
         A.check(A.lib.ssm_workspace_size(C.byref(csr.struct()), C.byref(self.params), C.c_size_t(budget),
                                          C.byref(size)), "ssm_workspace_size")
         if budget:
             size = C.c_size_t(budget)
         self.ws = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=device)
-        base = self.ws.data_ptr()
-        self._off = (-base) % 256
+        self._size = int(size.value)
+        self._off = (-self.ws.data_ptr()) % 256
         self._ctx = C.c_void_p(0)
+        self._create()
+
+    def _create(self):
         tp = self.t.ctypes.data_as(C.POINTER(C.c_double))
-        A.check(A.lib.ssm_create(C.byref(csr.struct()), C.byref(self.params), tp, _ptr(w),
-                                 C.c_void_p(base + self._off), C.c_size_t(int(size.value)), _stream(),
+        A.check(A.lib.ssm_create(C.byref(self.csr.struct()), C.byref(self.params), tp, _ptr(self.w_in),
+                                 C.c_void_p(self.ws.data_ptr() + self._off), C.c_size_t(self._size), _stream(),
                                  C.byref(self._ctx)), "ssm_create")
+
+    def reset(self):
+        """Destroy the context and create it again on the same workspace: the set-up of
+        ssm_create (the coefficients of Algorithm 1, W, the split tables) runs again."""
+        self.close()
+        self._create()
 
     def dos(self):
         """(dos, r1, r2): the DOS estimate at the sweep points (A's units) and kept counts."""

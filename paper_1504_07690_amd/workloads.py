@@ -239,6 +239,7 @@ class Workload:
     lo: float
     hi: float
     seed: int
+    lattice: tuple | None = None  # (nx, ny, nz) when row x + nx (y + ny z) is lattice point (x, y, z)
 
     @property
     def c0(self) -> float:
@@ -315,6 +316,10 @@ NAMES = {
 }
 
 
+LATTICES = {2: (64, 64, 64), 4: (64, 64, 64), 5: (128, 128, 128)}
+LATTICE_N = {k: v[0] * v[1] * v[2] for k, v in LATTICES.items()}
+
+
 def make_workload(cfg: int, a: CSR | None = None, **override) -> Workload:
     """Workload ``cfg`` with optional parameter overrides (nv, degree, nt,
     sigma_hat, seed)."""
@@ -322,7 +327,7 @@ def make_workload(cfg: int, a: CSR | None = None, **override) -> Workload:
     nv, m, nt, sh = _PARAMS[cfg]
     lo, hi = interval(a)
     kw = dict(name=NAMES[cfg], a=a, nv=nv, degree=m, nt=nt, sigma_hat=sh,
-              lo=lo, hi=hi, seed=W_SEED)
+              lo=lo, hi=hi, seed=W_SEED, lattice=LATTICES.get(cfg) if a.n == LATTICE_N.get(cfg) else None)
     kw.update(override)
     return Workload(**kw)
 

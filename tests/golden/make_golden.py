@@ -5,6 +5,9 @@ full-size workload, with the shared seeded inputs:
                                                   # M = 1000, N_t = 1000, sigma^ = 0.01)
     python tests/golden/make_golden.py 4          # the shifted SPD Anderson lattice
                                                   # (M = 1500, N_t = 1500, sigma^ = 1/150)
+    python tests/golden/make_golden.py 3          # the random-graph Laplacian (N = 2^20,
+                                                  # N_v = 128, M = 2000, N_t = 2000), 16 points
+                                                  # (hours on one host core)
 
 Calls only the oracle (and the input generators).  Run from the repository root.
 """
@@ -22,12 +25,13 @@ from oracle import ssm_oracle as O  # noqa: E402
 from paper_1504_07690_amd import workloads as WL  # noqa: E402
 
 
-OUT = {2: "anderson64_fp64_oracle.json", 4: "anderson64_spd_fp64_oracle.json"}
+OUT = {2: "anderson64_fp64_oracle.json", 4: "anderson64_spd_fp64_oracle.json", 3: "er_graph_2p20_fp64_oracle.json"}
+NPOINTS = {2: 10, 4: 10, 3: 16}
 
 
 def main(cfg=2, out=None):
     wl = WL.make_workload(cfg)
-    stride = wl.nt // 10
+    stride = wl.nt // NPOINTS[cfg]
     out = out or OUT[cfg]
     points = np.arange(stride // 2, wl.nt, stride)
     t0 = time.time()

@@ -342,3 +342,11 @@ def test_gram_noalloc_limit_checked_on_the_host(A):
     assert A.lib.ssm_gram_noalloc(1, 64, 6, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_gram_noalloc(1, 64, 8, 1, None, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_gram_noalloc(9, 64, 8, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_ARG
+
+
+@pytest.mark.parametrize("lattice,status", [((4, 4, 4), 0), ((4, 4, 5), 1), ((4, 0, 4), 1), ((0, 0, 0), 0),
+                                            ((-4, -4, -4), 1)])
+def test_lattice_validated(A, lattice, status):
+    out = C.c_size_t(0)
+    p = _params(A, lattice=(C.c_int32 * 3)(*lattice))
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, 64)), C.byref(p), 0, C.byref(out)) == status

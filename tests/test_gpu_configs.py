@@ -50,7 +50,7 @@ def _ctx(S, wl, precision, t, budget=0, ckpt_every=0):
     dt = torch.float64 if precision == "fp64" else torch.float32
     csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
     ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=t, precision=precision,
-                seed=wl.seed, budget=budget, ckpt_every=ckpt_every, device=DEV)
+                seed=wl.seed, budget=budget, ckpt_every=ckpt_every, lattice=wl.lattice, device=DEV)
     return csr, ctx
 
 
@@ -326,7 +326,7 @@ def test_stencil27_adjoint_two_level_checkpoints(S):
     bb = n * nv * 4
     csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
     kw = dict(lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, precision="fp32", seed=wl.seed)
-    ctx = S.SSM(csr, t=t, ckpt_every=s, plan=(len(t), ring), device=DEV, **kw)
+    ctx = S.SSM(csr, t=t, ckpt_every=s, plan=(len(t), ring), lattice=wl.lattice, device=DEV, **kw)
     st = ctx.stats()
     assert st["passes"] == 1 and st["chunk"] == ring, st
     dos, r1, r2 = ctx.dos()

@@ -38,7 +38,7 @@ def _ctx(S, wl, precision, budget=0):
     dt = torch.float64 if precision == "fp64" else torch.float32
     csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
     return S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
-                 precision=precision, seed=wl.seed, budget=budget, device=DEV)
+                 precision=precision, seed=wl.seed, budget=budget, lattice=wl.lattice, device=DEV)
 
 
 def _free():

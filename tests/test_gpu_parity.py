@@ -491,3 +491,27 @@ def test_end_to_end_large_nv(S, nx, nv, degree, nt):
     dos32, *_ = _run(S, wl, "fp32", w=wl.w().astype(np.float32))
     print(f"nv={nv}: fp32 L1 {_l1(dos32, ref['dos']):.2e}")
     assert _l1(dos32, ref["dos"]) <= 1e-3
+
+
+@pytest.mark.parametrize("which,precision", [("anderson16", "fp32"), ("anderson24", "fp64"), ("stencil12", "fp32"),
+                                             ("stencil20", "bf16x3")])
+def test_lattice_row_order_changes_nothing(S, which, precision):
+    """The recurrence's tiled visiting order of a lattice's rows (tiles of 16, 8 or 4
+    points of the x-y plane through every z): every block and the DOS bit for bit equal
+    to the plain row order's."""
+    nx = int(which[-2:])
+    rng = _rng(nx)
+    a = WL.anderson_3d(nx, rng.uniform(-2, 2, nx ** 3)) if which.startswith("anderson") else \
+        WL.stencil27_lognormal(nx, rng)
+    wl = WL.make_workload(2, a=a, nv=12 if precision == "fp64" else 20, degree=60, nt=24, sigma_hat=0.05)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    out = []
+    for lattice in (None, (nx, nx, nx)):
+        csr = S.DeviceCSR.from_csr(a, dtype=dt, device=DEV)
+        ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
+                    precision=precision, seed=wl.seed, lattice=lattice, device=DEV)
+        dos, r1, r2 = ctx.dos()
+        out.append((dos, ctx.views()["y"].clone()))
+        ctx.close()
+    assert torch.equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
