@@ -188,8 +188,23 @@ __global__ void __launch_bounds__(256) zbar_big_kernel(int64_t n, int nv, const 
 // A row of N_v values is held by L = N_v/4 lanes, 4 values each (16 bytes in FP32,
 // 32 in FP64); a wave holds R = 64/L whole rows, so the L partial dot products of an
 // entry are summed inside the wave with lane permutes.  Rows go to XCDs in contiguous
-// ranges, as in the forward recurrence.
+// ranges, as in the forward recurrence, and a lattice's rows are visited in the same tiled
+// order (TILED); when a row fills a whole wave (WAVE_ROW: N_v = 256 in FP32) its CSR
+// entries come through the scalar cache.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lattice_row(int64_t rho, const RowOrder& o) {
+  const int tile_rows = o.tx * o.ty;
+  const int64_t col_rows = (int64_t)tile_rows * o.nz;
+  const int tile = (int)(rho / col_rows);
+  const int64_t rem = rho - (int64_t)tile * col_rows;
+  const int z = (int)(rem / tile_rows);
+  const int in = (int)(rem - (int64_t)z * tile_rows);
+  const int yy = in / o.tx, xx = in - yy * o.tx;
+  const int tiles_x = o.nx / o.tx;
+  const int ty_i = tile / tiles_x, tx_i = tile - ty_i * tiles_x;
+  return (int64_t)(tx_i * o.tx + xx) + (int64_t)o.nx * ((int64_t)(ty_i * o.ty + yy) + (int64_t)o.ny * z);
+}
+
 __device__ __forceinline__ double row_sum(double s, int lane, int q, int L) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -199,7 +214,7 @@ __device__ __forceinline__ double row_sum(double s, int lane, int q, int L) {
   return s;  // the row's total, in its lane q == 0
 }
 
-template <typename T, typename V>
+template <typename T, typename V, bool TILED, bool WAVE_ROW>
 __global__ void __launch_bounds__(256) reverse_step_kernel(int64_t n, int L, int R, int64_t nblocks, int64_t per_xcd,
                                                            const int32_t* __restrict__ row_ptr,
                                                            const int32_t* __restrict__ col_idx,
@@ -207,15 +222,16 @@ __global__ void __launch_bounds__(256) reverse_step_kernel(int64_t n, int L, int
                                                            const V* __restrict__ x, const V* __restrict__ xprev,
                                                            const V* __restrict__ d, V* __restrict__ out,
                                                            const V* __restrict__ y, double coef,
-                                                           double* __restrict__ abar) {
+                                                           double* __restrict__ abar, RowOrder order) {
   const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (lblock >= nblocks) return;  // uniform over the workgroup
   const int lane = threadIdx.x & 63;
   const int g = lane / L;
   const int q = lane - g * L;
-  const int64_t r = (lblock * 4 + (threadIdx.x >> 6)) * R + g;
-  const bool active = g < R && r < n;
-  const int64_t rs = active ? r : 0;  // idle lanes read row 0 and write nothing
+  const int64_t rho = (lblock * 4 + (threadIdx.x >> 6)) * R + g;
+  const bool active = g < R && rho < n;
+  int64_t rs = active ? (TILED ? lattice_row(rho, order) : rho) : 0;  // idle lanes read row 0 and write nothing
+  if constexpr (WAVE_ROW) rs = __builtin_amdgcn_readfirstlane((int)rs);  // one row per wave
   const int p0 = row_ptr[rs];
   const int len = active ? row_ptr[rs + 1] - p0 : 0;
   const int64_t own = rs * L + q;
@@ -379,7 +395,7 @@ hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, vo
 template <typename T, typename V>
 hipError_t launch_reverse_t(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx, const T* val, T a,
                             T b, T c, const void* x, const void* xprev, const void* d, void* out, const void* y,
-                            double coef, double* abar, hipStream_t stream) {
+                            double coef, double* abar, const RowOrder& o, hipStream_t stream) {
   const int L = nv / 4;
   if (L < 1 || L > 64 || nv % 4) return hipErrorInvalidValue;
   const int R = 64 / L;
@@ -387,9 +403,19 @@ hipError_t launch_reverse_t(int64_t n, int nv, const int32_t* row_ptr, const int
   const int64_t nblocks = (n + rows_per_block - 1) / rows_per_block;
   const int64_t per_xcd = (nblocks + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((reverse_step_kernel<T, V>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, stream, n, L, R,
-                     nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d,
-                     (V*)out, (const V*)y, coef, abar);
+  const bool tiled = o.nx > 0;
+  if (tiled && !(o.tx > 0 && o.ty > 0 && o.nx % o.tx == 0 && o.ny % o.ty == 0 && (int64_t)o.nx * o.ny * o.nz == n))
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+#define SSM_REVERSE_LAUNCH(TL, WR)                                                                                \
+  hipLaunchKernelGGL((reverse_step_kernel<T, V, TL, WR>), grid, block, 0, stream, n, L, R, nblocks, per_xcd, row_ptr, \
+                     col_idx, val, a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, (const V*)y, coef,     \
+                     abar, o)
+  if (tiled && L == 64) SSM_REVERSE_LAUNCH(true, true);
+  else if (tiled) SSM_REVERSE_LAUNCH(true, false);
+  else if (L == 64) SSM_REVERSE_LAUNCH(false, true);
+  else SSM_REVERSE_LAUNCH(false, false);
+#undef SSM_REVERSE_LAUNCH
   return hipGetLastError();
 }
 
@@ -404,17 +430,17 @@ hipError_t launch_transpose_coefficients(const double* c, int64_t ldc, int nt, i
 hipError_t launch_reverse_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                    const double* val, double a, double b, double c, const double* x,
                                    const double* xprev, const double* d, double* out, const double* y, double coef,
-                                   double* abar, hipStream_t stream) {
+                                   double* abar, hipStream_t stream, const RowOrder& order) {
   return launch_reverse_t<double, f64x4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, y, coef, abar,
-                                         stream);
+                                         order, stream);
 }
 
 hipError_t launch_reverse_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                    const float* val, float a, float b, float c, const float* x, const float* xprev,
                                    const float* d, float* out, const float* y, double coef, double* abar,
-                                   hipStream_t stream) {
+                                   hipStream_t stream, const RowOrder& order) {
   return launch_reverse_t<float, f32x4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, y, coef, abar,
-                                        stream);
+                                        order, stream);
 }
 
 }  // namespace ssm

@@ -1246,12 +1246,12 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
               err = ssm::launch_reverse_step_f64(n, nv, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values,
                                                  2 * alpha, 2 * beta, -1.0, (const double*)x, (const double*)xp,
                                                  (const double*)ybk, (double*)lam_slot(k), (const double*)yk1, coef,
-                                                 grad_dev, st);
+                                                 grad_dev, st, c->order);
             else
               err = ssm::launch_reverse_step_f32(n, nv, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values,
                                                  (float)(2 * alpha), (float)(2 * beta), -1.0f, (const float*)x,
                                                  (const float*)xp, (const float*)ybk, (float*)lam_slot(k),
-                                                 (const float*)yk1, coef, grad_dev, st);
+                                                 (const float*)yk1, coef, grad_dev, st, c->order);
             if (err != hipSuccess) return hip_fail(err, "reverse recurrence step");
           }
           return SSM_OK;

@@ -55,11 +55,11 @@ hipError_t launch_zbar(int is_f32, int64_t n, int nv, int ntb, const void* w, vo
 hipError_t launch_reverse_step_f64(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                    const double* val, double a, double b, double c, const double* x,
                                    const double* xprev, const double* d, double* out, const double* y, double coef,
-                                   double* abar, hipStream_t stream);
+                                   double* abar, hipStream_t stream, const RowOrder& order = RowOrder{});
 hipError_t launch_reverse_step_f32(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_idx,
                                    const float* val, float a, float b, float c, const float* x, const float* xprev,
                                    const float* d, float* out, const float* y, double coef, double* abar,
-                                   hipStream_t stream);
+                                   hipStream_t stream, const RowOrder& order = RowOrder{});
 // chi[k*ldk + i] / clo: the BF16 split of c[k*ldc + i] (rows k < m1, points i < nt)
 hipError_t launch_split_rows(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo, int64_t ldk,
                              hipStream_t stream);
