@@ -317,3 +317,42 @@ def test_adjoint_lattice_row_order_changes_nothing(S, which, nv):
         ctx.close()
     assert np.all(np.isfinite(grads[0])) and np.abs(grads[0]).max() > 0
     assert np.array_equal(grads[0], grads[1])
+
+
+def test_adjoint_single_entry_central_differences(S, cfg1_case):
+    """The gradient along one stored entry (i, j), i != j, alone: a perturbation that breaks
+    A's symmetry, against central differences of the oracle, whose K_W is
+    (W^T Z + Z^T W)/2 of the perturbed matrix's own blocks (the map the adjoint
+    differentiates).  The entries are chosen where g_ij and g_ji differ most, so that a
+    transposed index in the gradient's sum would fail."""
+    wl, dos_bar = cfg1_case
+    ctx = _ctx(S, wl, "fp64", w=wl.w())
+    ctx.dos()
+    g = ctx.backward(dos_bar).cpu().numpy()
+    ctx.close()
+    a = wl.a
+    rows = np.repeat(np.arange(a.n), np.diff(a.row_ptr))
+    cols = a.col_idx
+    pos = {(int(r), int(c)): p for p, (r, c) in enumerate(zip(rows, cols))}
+    off = np.nonzero(rows != cols)[0]
+    mirror = np.array([pos[(int(cols[p]), int(rows[p]))] for p in off])
+    asym = np.abs(g[off] - g[mirror])
+    order = off[np.argsort(-asym)]
+    assert asym.max() > 1e-3 * np.abs(g).max()  # the two entries' gradients differ
+    h = 1e-6 * np.abs(a.values).max()
+    checked = 0
+    for p in order[:6]:
+        e = np.zeros(a.nnz)
+        e[p] = 1.0
+        lp, rp = _oracle_objective(wl, a.values + h * e, dos_bar)
+        lm, rm = _oracle_objective(wl, a.values - h * e, dos_bar)
+        if not (np.array_equal(rp["r1"], rm["r1"]) and np.array_equal(rp["r2"], rm["r2"])):
+            continue
+        fd = (lp - lm) / (2 * h)
+        print(f"entry ({rows[p]}, {cols[p]}): adjoint {g[p]:.12e}  central difference {fd:.12e}  "
+              f"mirror entry {g[pos[(int(cols[p]), int(rows[p]))]]:.6e}")
+        assert abs(g[p] - fd) <= 1e-5 * abs(fd)
+        checked += 1
+        if checked == 2:
+            break
+    assert checked >= 1
