@@ -493,17 +493,20 @@ def test_end_to_end_large_nv(S, nx, nv, degree, nt):
     assert _l1(dos32, ref["dos"]) <= 1e-3
 
 
-@pytest.mark.parametrize("which,precision", [("anderson16", "fp32"), ("anderson24", "fp64"), ("stencil12", "fp32"),
-                                             ("stencil20", "bf16x3")])
-def test_lattice_row_order_changes_nothing(S, which, precision):
-    """The recurrence's tiled visiting order of a lattice's rows (tiles of 16, 8 or 4
-    points of the x-y plane through every z): every block and the DOS bit for bit equal
-    to the plain row order's."""
+@pytest.mark.parametrize("which,precision,nv", [
+    ("anderson16", "fp32", 20), ("anderson24", "fp64", 12), ("stencil12", "fp32", 20), ("stencil20", "bf16x3", 20),
+    ("stencil12", "fp32", 256), ("stencil20", "bf16x3", 256), ("anderson16", "fp64", 128), ("stencil08", "fp32", 256),
+    ("stencil10", "fp32", 256)])
+def test_lattice_row_order_changes_nothing(S, which, precision, nv):
+    """The recurrence's tiled visiting order of a lattice's rows (tiles of 16, 8, 4 or 2
+    points of the x-y plane through every z), with the CSR entries through the scalar cache
+    where a row fills a wave (N_v = 256 in FP32, 128 in FP64): every block and the DOS bit
+    for bit equal to the plain row order's."""
     nx = int(which[-2:])
     rng = _rng(nx)
     a = WL.anderson_3d(nx, rng.uniform(-2, 2, nx ** 3)) if which.startswith("anderson") else \
         WL.stencil27_lognormal(nx, rng)
-    wl = WL.make_workload(2, a=a, nv=12 if precision == "fp64" else 20, degree=60, nt=24, sigma_hat=0.05)
+    wl = WL.make_workload(2, a=a, nv=nv, degree=60, nt=24, sigma_hat=0.05)
     dt = torch.float64 if precision == "fp64" else torch.float32
     out = []
     for lattice in (None, (nx, nx, nx)):
