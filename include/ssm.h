@@ -102,7 +102,8 @@ typedef struct ssm_params {
                               same recurrence (same W, M and sweep points); read it with ssm_dgc
                               (SSM_SS_DGC only) */
   int32_t method;          /* an ssm_method (0 = SSM_SS_DGC).  SSM_RESS_DGC needs an even M,
-                              SSM_FP64 (else SSM_ERR_UNSUPPORTED), ckpt_every = 0 and dgc = 0 */
+                              SSM_FP64 or SSM_FP32 (else SSM_ERR_UNSUPPORTED), ckpt_every = 0
+                              and dgc = 0 */
   int32_t nv_hybrid;       /* N~_v of Algorithm 7: 0, or a multiple of 4 with nv + nv_hybrid <= 256
                               (SSM_RESS_DGC only; 0 for SSM_SS_DGC).  The block W of ssm_create
                               then has nv + nv_hybrid columns: W, then W~ */
@@ -180,10 +181,13 @@ ssm_status ssm_dos(ssm_ctx* ctx, double* dos_host, int32_t* ranks_host);
  * K_W~ = W~^T g^{M/2} W~ (Theorem 4).  The recurrence runs on V = [W W~] to degree
  * M/2 + 1 only: for symmetric A~, T_s^2 = (T_{2s} + T_0)/2 and T_{s+1} T_s =
  * (T_{2s+1} + T_1)/2 turn the Gram matrices of consecutive blocks into every moment
- * X_l, l <= M (FP64 throughout).  Algorithm 4's truncation also drops eigenvalues of
- * K_W(t_i) below 1e-12 sum_{l<=M/2} |mu_l(t_i)| max|X_l[:nv, :nv]|, the rounding level of
- * K_W as a sum of moments (at sweep points outside the spectrum K_W and K_Z are both
- * rounding, and their pencil would otherwise report arbitrary values).  ranks_host as
+ * X_l, l <= M.  With SSM_FP64 everything is FP64; with SSM_FP32 the recurrence runs in
+ * FP32 (CSR values and W float) and the Gram products and all later steps in FP64.
+ * Algorithm 4's truncation also drops eigenvalues of K_W(t_i) below
+ * eta sum_{l<=M/2} |mu_l(t_i)| max|X_l[:nv, :nv]|, the rounding level of K_W as a sum of
+ * moments, eta = 1e-12 (SSM_FP64) or 2^-18 (SSM_FP32) (at sweep points outside the
+ * spectrum K_W and K_Z are both rounding, and their pencil would otherwise report
+ * arbitrary values).  ranks_host as
  * for Algorithm 5 (r1, r2 of the N_v x N_v pencil).  The bound check uses
  * ||T_{M/2+1}(A~)V||_F. */
 

@@ -85,14 +85,16 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // Diagonalise the symmetric n x n matrix in sh.A (row stride ld); accumulate the
-// rotations into V (if V != nullptr, V must hold the identity on entry).
+// rotations into V (if V != nullptr, V must hold the identity on entry).  V is kept
+// transposed: eigenvector j is row j of the array (V[j * ld + r] is its entry r), so that
+// a pair's rotation updates two contiguous rows.
 // Each round rotates the disjoint index pairs (p_j, q_j) at once: A <- R^T A R, R the
 // product of the pair rotations.  Entries of the 2 x 2 block of pairs (j, k) depend only
 // on that block, so one lane updates a block (rows by pair j, then columns by pair k, the
 // order of a row pass followed by a column pass) and writes it and its mirror (k, j),
 // keeping A exactly symmetric; the pivot pair of a diagonal block becomes exactly 0.  When
 // n is odd the index left without a partner forms a one-element pair (q = -1, no rotation).
-template <int TH>
+template <int TH, int U>
 __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
   double* A = sh.A;
   const int tid = threadIdx.x;
@@ -135,71 +137,125 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
         sh.sn[tid] = s;
       }
       __syncthreads();
-      // blocks (j, k), j <= k, numbered row by row
-      for (int idx = tid; idx < nblocks; idx += TH) {
-        // row j of the upper triangle starts at j P - j (j - 1) / 2 (P = npairs): the quadratic
-        // inverted in float (within one of the row for P <= 128), then corrected by one step
-        const int P2 = 2 * npairs + 1;
-        int j = (int)((P2 - sqrtf((float)(P2 * P2 - 8 * idx))) * 0.5f);
-        j = j < 0 ? 0 : (j >= npairs ? npairs - 1 : j);
-        if (j * npairs - j * (j - 1) / 2 > idx)
-          --j;
-        else if ((j + 1) * npairs - (j + 1) * j / 2 <= idx)
-          ++j;
-        const int k = j + (idx - (j * npairs - j * (j - 1) / 2));
-        const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
-        const double cj = sh.cs[j], sj = sh.sn[j], ck = sh.cs[k], sk = sh.sn[k];
-        if (qj < 0 || qk < 0) {  // a one-element pair: a row, a column or one entry
-          if (qj < 0 && qk < 0) continue;  // its diagonal entry does not change
-          // the single index x against the pair (y0, y1) rotated by (c, s)
-          const int x = qj < 0 ? pj : pk;
-          const int y0 = qj < 0 ? pk : pj, y1 = qj < 0 ? qk : qj;
-          const double c = qj < 0 ? ck : cj, s = qj < 0 ? sk : sj;
-          const double a0 = A[x * ld + y0], a1 = A[x * ld + y1];
-          const double n0 = c * a0 - s * a1, n1 = s * a0 + c * a1;
-          A[x * ld + y0] = n0;
-          A[x * ld + y1] = n1;
-          A[y0 * ld + x] = n0;
-          A[y1 * ld + x] = n1;
-          continue;
+      // blocks (j, k), j <= k, numbered row by row.  Each lane takes U blocks per pass and
+      // issues all their loads before any store (the blocks of a round are disjoint), so that
+      // U loads are in flight at once where A lives in global scratch.
+      for (int i0 = tid; i0 < nblocks; i0 += U * TH) {
+        int jj[U], kk[U];
+        double a[U], b[U], c0[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = i0 + u * TH;
+          jj[u] = -1;
+          if (idx >= nblocks) continue;
+          // row j of the upper triangle starts at j P - j (j - 1) / 2 (P = npairs): the quadratic
+          // inverted in float (within one of the row for P <= 128), then corrected by one step
+          const int P2 = 2 * npairs + 1;
+          int j = (int)((P2 - sqrtf((float)(P2 * P2 - 8 * idx))) * 0.5f);
+          j = j < 0 ? 0 : (j >= npairs ? npairs - 1 : j);
+          if (j * npairs - j * (j - 1) / 2 > idx)
+            --j;
+          else if ((j + 1) * npairs - (j + 1) * j / 2 <= idx)
+            ++j;
+          const int k = j + (idx - (j * npairs - j * (j - 1) / 2));
+          const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
+          if (qj < 0 || qk < 0) {  // a one-element pair: a row, a column or one entry
+            if (qj < 0 && qk < 0) continue;  // its diagonal entry does not change
+            // the single index x against the pair (y0, y1)
+            const int x = qj < 0 ? pj : pk;
+            const int y0 = qj < 0 ? pk : pj, y1 = qj < 0 ? qk : qj;
+            a[u] = A[x * ld + y0];
+            b[u] = A[x * ld + y1];
+          } else {
+            a[u] = A[pj * ld + pk];
+            b[u] = A[pj * ld + qk];
+            c0[u] = A[qj * ld + pk];
+            d[u] = A[qj * ld + qk];
+          }
+          jj[u] = j;
+          kk[u] = k;
         }
-        const double a = A[pj * ld + pk], b = A[pj * ld + qk], c0 = A[qj * ld + pk], d = A[qj * ld + qk];
-        // rows by pair j
-        const double ra = cj * a - sj * c0, rc = sj * a + cj * c0;
-        const double rb = cj * b - sj * d, rd = sj * b + cj * d;
-        // columns by pair k
-        const double na = ck * ra - sk * rb, nb = sk * ra + ck * rb;
-        const double nc = ck * rc - sk * rd, nd = sk * rc + ck * rd;
-        if (j == k) {  // the pivot pair becomes exactly 0
-          A[pj * ld + pj] = na;
-          A[qj * ld + qj] = nd;
-          A[pj * ld + qj] = 0.0;
-          A[qj * ld + pj] = 0.0;
-        } else {
-          A[pj * ld + pk] = na;
-          A[pj * ld + qk] = nb;
-          A[qj * ld + pk] = nc;
-          A[qj * ld + qk] = nd;
-          A[pk * ld + pj] = na;
-          A[qk * ld + pj] = nb;
-          A[pk * ld + qj] = nc;
-          A[qk * ld + qj] = nd;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = jj[u], k = kk[u];
+          if (j < 0) continue;
+          const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
+          const double cj = sh.cs[j], sj = sh.sn[j], ck = sh.cs[k], sk = sh.sn[k];
+          if (qj < 0 || qk < 0) {  // rotated by the pair's (c, s)
+            const int x = qj < 0 ? pj : pk;
+            const int y0 = qj < 0 ? pk : pj, y1 = qj < 0 ? qk : qj;
+            const double c = qj < 0 ? ck : cj, s = qj < 0 ? sk : sj;
+            const double n0 = c * a[u] - s * b[u], n1 = s * a[u] + c * b[u];
+            A[x * ld + y0] = n0;
+            A[x * ld + y1] = n1;
+            A[y0 * ld + x] = n0;
+            A[y1 * ld + x] = n1;
+            continue;
+          }
+          // rows by pair j
+          const double ra = cj * a[u] - sj * c0[u], rc = sj * a[u] + cj * c0[u];
+          const double rb = cj * b[u] - sj * d[u], rd = sj * b[u] + cj * d[u];
+          // columns by pair k
+          const double na = ck * ra - sk * rb, nb = sk * ra + ck * rb;
+          const double nc = ck * rc - sk * rd, nd = sk * rc + ck * rd;
+          if (j == k) {  // the pivot pair becomes exactly 0
+            A[pj * ld + pj] = na;
+            A[qj * ld + qj] = nd;
+            A[pj * ld + qj] = 0.0;
+            A[qj * ld + pj] = 0.0;
+          } else {
+            A[pj * ld + pk] = na;
+            A[pj * ld + qk] = nb;
+            A[qj * ld + pk] = nc;
+            A[qj * ld + qk] = nd;
+            A[pk * ld + pj] = na;
+            A[qk * ld + pj] = nb;
+            A[pk * ld + qj] = nc;
+            A[qk * ld + qj] = nd;
+          }
         }
       }
-      if (V) {  // V <- V R: columns of each pair
-        for (int idx = tid; idx < npairs * n; idx += TH) {
-          const int k = idx / n, row = idx - k * n;
-          const int p = sh.pp[k], q = sh.qq[k];
-          if (q < 0) continue;
-          const double c = sh.cs[k], s = sh.sn[k];
-          const double vp = V[row * ld + p], vq = V[row * ld + q];
-          V[row * ld + p] = c * vp - s * vq;
-          V[row * ld + q] = s * vp + c * vq;
+      if (V) {  // V <- V R: columns of each pair, U entries per lane and pass as above
+        for (int i0 = tid; i0 < npairs * n; i0 += U * TH) {
+          int rr[U], kk[U];
+          double vp[U], vq[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int idx = i0 + u * TH;
+            kk[u] = -1;
+            if (idx >= npairs * n) continue;
+            const int k = idx / n, row = idx - k * n;
+            const int p = sh.pp[k], q = sh.qq[k];
+            if (q < 0) continue;
+            vp[u] = V[p * ld + row];
+            vq[u] = V[q * ld + row];
+            kk[u] = k;
+            rr[u] = row;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = kk[u];
+            if (k < 0) continue;
+            const int p = sh.pp[k], q = sh.qq[k], row = rr[u];
+            const double c = sh.cs[k], s = sh.sn[k];
+            V[p * ld + row] = c * vp[u] - s * vq[u];
+            V[q * ld + row] = s * vp[u] + c * vq[u];
+          }
         }
       }
       __syncthreads();
     }
   }
+}
+
+// Jacobi with the batching that suits where the matrices of a point with N_v = nv live:
+// one entry per lane and pass when both are in LDS, four when either is in global scratch.
+template <int TH>
+__device__ void jacobi_for(const GeShared& sh, double* V, int m, int ld, int nv) {
+  if (geneig_lds_matrices(nv) == 2)
+    jacobi<TH, 1>(sh, V, m, ld);
+  else
+    jacobi<TH, 4>(sh, V, m, ld);
 }
 
 // With nvh > 0 (Algorithm 6 / 7 with N~_v = nvh columns of W~) the point also gets the
@@ -210,7 +266,7 @@ template <int TH>
 __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* __restrict__ k_w,
                                                                   const double* __restrict__ k_z, double g_max,
                                                                   double tau, double rho, double* __restrict__ dos,
-                                                                  int32_t* __restrict__ ranks, int ntb,
+                                                                  int32_t* __restrict__ ranks, int rank_stride,
                                                                   double* __restrict__ scratch, int nvh,
                                                                   const double* __restrict__ k_c,
                                                                   const double* __restrict__ trw,
@@ -236,7 +292,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
   __syncthreads();
 
   // 1. W^T Z = U S U^T
-  jacobi<TH>(sh, sh.V, n, ld);
+  jacobi_for<TH>(sh, sh.V, n, ld, n);
   for (int j = tid; j < n; j += TH) sh.s[j] = sh.A[j * ld + j];
   __syncthreads();
 
@@ -263,7 +319,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
       dos[i] = nvh ? trw[i] / nvh : 0.0;  // C~ is empty: only Tr K_W~ / N~_v remains
       if (ranks) {
         ranks[i] = 0;
-        ranks[ntb + i] = 0;
+        ranks[rank_stride + i] = 0;
       }
     }
     return;
@@ -275,7 +331,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
       const int a = idx / r1, b = idx - a * r1;
       const int kb = sh.kidx[b];
       double acc = 0.0;
-      for (int c = 0; c < n; ++c) acc += kci[(int64_t)a * n + c] * sh.V[c * ld + kb];
+      for (int c = 0; c < n; ++c) acc += kci[(int64_t)a * n + c] * sh.V[kb * ld + c];
       g[idx] = acc * sh.scale[b];
     }
   }
@@ -285,7 +341,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
     const int row = idx / r1, a = idx - row * r1;
     const int ka = sh.kidx[a];
     double acc = 0.0;
-    for (int c = 0; c < n; ++c) acc += kz[(int64_t)row * n + c] * sh.V[c * ld + ka];
+    for (int c = 0; c < n; ++c) acc += kz[(int64_t)row * n + c] * sh.V[ka * ld + c];
     tmat[idx] = acc * sh.scale[a];
   }
   __threadfence_block();
@@ -295,7 +351,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
     const int a = idx / r1, b = idx - a * r1;
     const int ka = sh.kidx[a];
     double acc = 0.0;
-    for (int c = 0; c < n; ++c) acc += sh.V[c * ld + ka] * tmat[(int64_t)c * r1 + b];
+    for (int c = 0; c < n; ++c) acc += sh.V[ka * ld + c] * tmat[(int64_t)c * r1 + b];
     sh.A[a * ld + b] = acc * sh.scale[a];
   }
   __syncthreads();
@@ -315,9 +371,9 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
     }
     __threadfence_block();
     __syncthreads();
-    jacobi<TH>(sh, sh.V, r1, ld);
+    jacobi_for<TH>(sh, sh.V, r1, ld, n);
   } else {
-    jacobi<TH>(sh, nullptr, r1, ld);
+    jacobi_for<TH>(sh, nullptr, r1, ld, n);
   }
 
   // 4. range filter and trace (fixed order); kidx now flags the eigenvectors kept
@@ -337,7 +393,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
     sh.s[0] = tr;
     if (ranks) {
       ranks[i] = r1;
-      ranks[ntb + i] = r2;
+      ranks[rank_stride + i] = r2;
     }
   }
   __syncthreads();
@@ -348,7 +404,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
       const int a = idx / r1, j = idx - a * r1;
       if (!sh.kidx[j]) continue;
       double h = 0.0;
-      for (int b = 0; b < r1; ++b) h += g[(int64_t)a * r1 + b] * sh.V[b * ld + j];
+      for (int b = 0; b < r1; ++b) h += g[(int64_t)a * r1 + b] * sh.V[j * ld + b];
       part += h * h;
     }
     const double hs = block_sum<TH>(part, sh.red);
@@ -404,9 +460,9 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
     sh.V[r * ld + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi<TH>(sh, sh.V, n, ld);
+  jacobi_for<TH>(sh, sh.V, n, ld, n);
   for (int j = tid; j < n; j += TH) sh.s[j] = sh.A[j * ld + j];
-  for (int idx = tid; idx < n * n; idx += TH) ug[idx] = sh.V[(idx / n) * ld + idx % n];
+  for (int idx = tid; idx < n * n; idx += TH) ug[idx] = sh.V[(idx % n) * ld + idx / n];
   __syncthreads();
   // 2. truncation (as in the forward kernel)
   if (tid == 0) {
@@ -435,7 +491,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
   for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += kz[(int64_t)r * n + q] * sh.V[q * ld + c];
+    for (int q = 0; q < n; ++q) acc += kz[(int64_t)r * n + q] * sh.V[c * ld + q];
     tg[idx] = acc;
   }
   __threadfence_block();
@@ -443,7 +499,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
   for (int idx = tid; idx < n * n; idx += TH) {
     const int r = idx / n, c = idx - r * n;
     double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += sh.V[q * ld + r] * tg[(int64_t)q * n + c];
+    for (int q = 0; q < n; ++q) acc += sh.V[r * ld + q] * tg[(int64_t)q * n + c];
     sh.A[r * ld + c] = acc;
   }
   __syncthreads();
@@ -461,7 +517,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
     sh.V[a * ld + b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi<TH>(sh, sh.V, r1, ld);
+  jacobi_for<TH>(sh, sh.V, r1, ld, n);
   // 5. P (U coordinates, n x n) = sum over in-range xi of x x^T, embedded -> global tg
   const double hi = (1.0 + rho) * g_max;
   for (int idx = tid; idx < n * n; idx += TH) tg[idx] = 0.0;
@@ -472,7 +528,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
     double acc = 0.0;
     for (int j = 0; j < r1; ++j) {
       const double xi = sh.A[j * ld + j];
-      if (xi >= 0.0 && xi <= hi) acc += sh.V[a * ld + j] * sh.V[b * ld + j];
+      if (xi >= 0.0 && xi <= hi) acc += sh.V[j * ld + a] * sh.V[j * ld + b];
     }
     tg[(int64_t)sh.kidx[a] * n + sh.kidx[b]] = acc;
   }
@@ -563,13 +619,13 @@ hipError_t launch_backward_t(int nv, int ntb, const double* k_w, const double* k
 template <int TH>
 hipError_t launch_trace_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                           double rho, double* dos, int32_t* ranks, double* scratch, int nvh, const double* k_c,
-                          const double* trw, double* hscr, const double* s_floor, size_t lds,
+                          const double* trw, double* hscr, const double* s_floor, int rank_stride, size_t lds,
                           hipStream_t stream) {
   hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel<TH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_trace_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho, dos,
-                     ranks, ntb, scratch, nvh, k_c, trw, hscr, s_floor);
+                     ranks, rank_stride, scratch, nvh, k_c, trw, hscr, s_floor);
   return hipGetLastError();
 }
 
@@ -594,20 +650,21 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                                double rho, double* dos, int32_t* ranks, double* scratch, hipStream_t stream,
                                int nvh, const double* k_c, const double* trw, double* hscr,
-                               const double* s_floor) {
+                               const double* s_floor, int rank_stride) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
+  if (rank_stride <= 0) rank_stride = ntb;
   const size_t lds = geneig_lds_bytes(nv);
   switch (geneig_threads(nv)) {
     case 256:
       return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
-                                 s_floor, lds, stream);
+                                 s_floor, rank_stride, lds, stream);
     case 512:
       return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
-                                 s_floor, lds, stream);
+                                 s_floor, rank_stride, lds, stream);
     default:
       return launch_trace_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw,
-                                            hscr, s_floor, lds, stream);
+                                            hscr, s_floor, rank_stride, lds, stream);
   }
 }
 

@@ -122,8 +122,8 @@ ssm_status check_params(const ssm_params* p) {
       return fail(SSM_ERR_ARG, "nv_hybrid must be 0 or a positive multiple of 4 (got %d)", p->nv_hybrid);
     if (p->nv + p->nv_hybrid > kMaxNv)
       return fail(SSM_ERR_UNSUPPORTED, "nv + nv_hybrid > %d is not implemented in this build", kMaxNv);
-    if (p->precision != SSM_FP64)
-      return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC runs in FP64 only in this build (precision SSM_FP64)");
+    if (p->precision != SSM_FP64 && p->precision != SSM_FP32)
+      return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC runs in FP64 or FP32 in this build");
     if (p->ckpt_every) return fail(SSM_ERR_UNSUPPORTED, "RESS-DGC has no adjoint in this build (ckpt_every must be 0)");
     if (p->dgc) return fail(SSM_ERR_UNSUPPORTED, "the DGC by-product is built for SSM_SS_DGC only");
     if (p->plan_batch || p->plan_chunk) return fail(SSM_ERR_ARG, "plan_batch and plan_chunk apply to SSM_SS_DGC");
@@ -269,6 +269,7 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
 void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   const int nvp = p->nv + p->nv_hybrid;
   const size_t e = (size_t)a->n * nvp;
+  const size_t es = elem_bytes(p->precision);
   const size_t nn = (size_t)p->nv * p->nv;
   const size_t nnp = (size_t)nvp * nvp;
   const int m1 = p->degree + 1;
@@ -282,7 +283,7 @@ void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_t = take(p->nt * 8);
   pl.off_c64 = take((size_t)m1 * pl.ldc * 8);
   pl.off_nu = take((size_t)m1 * pl.ldc * 8);
-  pl.off_w = take(own_w ? e * 8 : 0);
+  pl.off_w = take(own_w ? e * es : 0);
   pl.off_kw = take((size_t)p->nt * nn * 8);
   pl.off_kz = take((size_t)p->nt * nn * 8);
   pl.off_kc = take((size_t)p->nt * p->nv_hybrid * p->nv * 8);
@@ -300,7 +301,7 @@ void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_xmax = take((size_t)S * 8);
   pl.off_floor = take((size_t)p->nt * 8);
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * std::max(pl.chunk, 1) * 2 * nnp * 8);
-  pl.off_y = take((size_t)(pl.chunk + 1) * e * 8);
+  pl.off_y = take((size_t)(pl.chunk + 1) * e * es);
   pl.total = o;
 }
 
@@ -390,6 +391,9 @@ struct ssm_ctx {
   ssm_csr a{};
   ssm_params p{};
   hipStream_t stream = nullptr;
+  // Algorithm 4 of a group of sweep points runs on this stream while the caller's stream
+  // goes on with the next group's Gram matrices (or the next batch's passes)
+  hipStream_t side = nullptr;
   Plan pl;
   char* ws = nullptr;
   double* t = nullptr;
@@ -492,7 +496,8 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->ws = (char*)workspace;
   c->t = (double*)(c->ws + pl.off_t);
   c->c64 = (double*)(c->ws + pl.off_c64);
-  c->c32 = p->precision == SSM_FP64 ? nullptr : (float*)(c->ws + pl.off_c32);
+  // the FP32 copy of the table feeds the SS-DGC sweeps only (RESS-DGC sums moments in FP64)
+  c->c32 = (p->precision == SSM_FP64 || pl.ress) ? nullptr : (float*)(c->ws + pl.off_c32);
   if (p->precision == SSM_FP32_BF16X3) {
     c->chi = (__bf16*)(c->ws + pl.off_chi);
     c->clo = (__bf16*)(c->ws + pl.off_clo);
@@ -536,10 +541,13 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->dos_host.assign(p->nt, 0.0);
 
   auto bail = [&](ssm_status st) {
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return st;
   };
   hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess)
+    return bail(hip_fail(e, "side stream"));
   if ((e = hipMemcpyAsync(c->t, t_host, sizeof(double) * p->nt, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "copy of sweep points"));
   if (pl.ldc != p->nt) {  // padding columns of the coefficient table are read by the sweep: make them 0
@@ -595,6 +603,7 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
 ssm_status ssm_destroy(ssm_ctx* c) {
   if (!c) return fail(SSM_ERR_ARG, "ctx is NULL");
   for (auto ev : c->events) (void)hipEventDestroy(ev);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
   return SSM_OK;
 }
@@ -736,7 +745,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 
   // events: [0] start, then (begin, end) pairs per timed launch group
   const int nchunks = (m + 1 + pl.chunk - 1) / pl.chunk;
-  const size_t need = 2 + (size_t)pl.passes * (2 * nchunks + 2) * 2 + 4;
+  const size_t need = 4 + (size_t)pl.passes * (2 * nchunks + 16) * 2;
   while (c->events.size() < need) {
     hipEvent_t ev;
     SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
@@ -750,6 +759,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   c->z_valid = false;
 
   auto y_slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % pl.chunk) * e * es; };
+  const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
   for (int pass = 0; pass < pl.passes; ++pass) {
     const int p0 = pass * pl.batch;
     const int nb = std::min(pl.batch, p.nt - p0);
@@ -762,23 +772,43 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
         err = ssm::launch_rounding_floor(c->mun, p.nt, c->eta, c->norm + 0, 1.0 / std::sqrt((double)e), c->sfloor, st);
       if (err != hipSuccess) return hip_fail(err, "norm kernel");
     }
-    Span gs{mark(), mark(), 2};
-    SSM_HIP(hipEventRecord(c->events[gs.b], st), "hipEventRecord");
-    hipError_t err = ssm::launch_gram(!f64, n, nv, nb, c->w, c->z, c->kw + (int64_t)p0 * nv * nv,
-                                      c->kz + (int64_t)p0 * nv * nv, pl.nseg, c->gpart, st);
-    if (err != hipSuccess) return hip_fail(err, "Gram kernel");
-    SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
-    tl.spans.push_back(gs);
+    // Gram matrices of the batch in groups of points; Algorithm 4 of each group follows on the
+    // side stream, beside the next group's Gram (or the next batch's passes): the Gram keeps
+    // the matrix cores busy, Algorithm 4 the LDS and the vector units
+    const int groups = nb >= 512 ? 4 : nb >= 128 ? 2 : 1;
+    for (int gi = 0; gi < groups; ++gi) {
+      const int q0 = p0 + (int)((int64_t)nb * gi / groups), q1 = p0 + (int)((int64_t)nb * (gi + 1) / groups);
+      const int ng = q1 - q0;
+      // segments for the group's size, within the plan's partial-sum buffer
+      const int nseg = std::max(1, std::min(gram_segments(n, ng), (int)((int64_t)pl.nseg * pl.batch / ng)));
+      Span gs{mark(), mark(), 2};
+      SSM_HIP(hipEventRecord(c->events[gs.b], st), "hipEventRecord");
+      hipError_t err = ssm::launch_gram(!f64, n, nv, ng, c->w, (const char*)c->z + (size_t)(q0 - p0) * e * es,
+                                        c->kw + (int64_t)q0 * nv * nv, c->kz + (int64_t)q0 * nv * nv, nseg, c->gpart,
+                                        st);
+      if (err != hipSuccess) return hip_fail(err, "Gram kernel");
+      SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
+      tl.spans.push_back(gs);
+      SSM_HIP(hipStreamWaitEvent(c->side, c->events[gs.en], 0), "hipStreamWaitEvent");
+      Span as{mark(), mark(), 3};
+      SSM_HIP(hipEventRecord(c->events[as.b], c->side), "hipEventRecord");
+      err = ssm::launch_geneig_trace(nv, ng, c->kw + (int64_t)q0 * nv * nv, c->kz + (int64_t)q0 * nv * nv, g_max,
+                                     p.tau, p.range_slack, c->dos + q0, c->ranks + q0,
+                                     c->escr + (int64_t)q0 * ssm::geneig_scratch_doubles(nv), c->side, 0, nullptr,
+                                     nullptr, nullptr, c->sfloor ? c->sfloor + q0 : nullptr, p.nt);
+      if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
+      SSM_HIP(hipEventRecord(c->events[as.en], c->side), "hipEventRecord");
+      tl.spans.push_back(as);
+    }
     c->last_batch_start = p0;
   }
-  const double g_max = 1.0 / ((double)n * std::sqrt(2.0 * M_PI) * p.sigma);
-  Span es_{mark(), mark(), 3};
-  SSM_HIP(hipEventRecord(c->events[es_.b], st), "hipEventRecord");
-  hipError_t err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks,
-                                            c->escr, st, 0, nullptr, nullptr, nullptr, c->sfloor);
-  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
-  SSM_HIP(hipEventRecord(c->events[es_.en], st), "hipEventRecord");
-  tl.spans.push_back(es_);
+  // the caller's stream waits for the last group of Algorithm 4
+  const size_t ev_join = mark();
+  SSM_HIP(hipEventRecord(c->events[ev_join], c->side), "hipEventRecord");
+  SSM_HIP(hipStreamWaitEvent(st, c->events[ev_join], 0), "hipStreamWaitEvent");
+  const size_t ev_end = mark();
+  SSM_HIP(hipEventRecord(c->events[ev_end], st), "hipEventRecord");
+  hipError_t err;
   if (pl.dgc_group) {
     err = ssm::launch_dgc(c->c64, pl.ldc, p.nt, m + 1, nv, c->dsums, c->dgc, c->dgc + p.nt, st);
     if (err != hipSuccess) return hip_fail(err, "Algorithm 2 kernel");
@@ -801,7 +831,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     *dst += ms;
   }
   float tot = 0.f;
-  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[es_.en]), "hipEventElapsedTime");
+  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[ev_end]), "hipEventElapsedTime");
   S.ms_total = tot;
   S.spmm_launches = spmm_launches;
   S.sweep_launches = sweep_launches;
@@ -833,6 +863,11 @@ namespace {
 // g^{M/2}(t_i I - A) W is rounding noise, K_Z's independent rounding gives the pencil
 // arbitrary eigenvalues, in range included.
 constexpr double kRessFloor = 1e-12;
+// With an FP32 recurrence the moments carry the blocks' rounding, which grows with the
+// degree and is doubled by the product identity: the floor is 2^-18 of the same sum, about
+// 32 units of FP32 rounding (a host model of the FP32 moments on the 32 x 32 workload gave
+// DOS L1 errors against FP64 of 1.4e-2, 2.2e-4 and 7e-6 with 1e-12, 2^-22 and 2^-18).
+constexpr double kRessFloorF32 = 0x1p-18;
 
 ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   const ssm_params& p = c->p;
@@ -846,6 +881,8 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   const int R = pl.chunk + 1;       // ring slots
   const double alpha = 2.0 / (p.hi - p.lo);
   const double beta = -(p.hi + p.lo) / (p.hi - p.lo);
+  const bool f64 = p.precision == SSM_FP64;
+  const size_t es = elem_bytes(p.precision);
   hipStream_t st = c->stream;
   const int rounds = (S + pl.chunk - 1) / pl.chunk;
   const size_t need = 4 * (size_t)rounds + 8;
@@ -861,9 +898,9 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   auto rec = [&](size_t ev) { return hipEventRecord(c->events[ev], st); };
   const size_t ev_start = mark();
   SSM_HIP(rec(ev_start), "hipEventRecord");
-  auto slot = [&](int k) -> double* { return (double*)c->y + (size_t)(k % R) * e; };
+  auto slot = [&](int k) -> char* { return (char*)c->y + (size_t)(k % R) * e * es; };
   int64_t spmm_launches = 0;
-  hipError_t err = hipMemcpyAsync(slot(0), c->w, e * 8, hipMemcpyDeviceToDevice, st);
+  hipError_t err = hipMemcpyAsync(slot(0), c->w, e * es, hipMemcpyDeviceToDevice, st);
   if (err != hipSuccess) return hip_fail(err, "copy of W");
   int k = 0;       // last block formed
   int s_done = 0;  // next pair to form
@@ -873,11 +910,17 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     Span rs{mark(), 0, 0};
     SSM_HIP(rec(rs.b), "hipEventRecord");
     for (int kk = k + 1; kk <= k_last; ++kk) {
-      const double* x = slot(kk - 1);
-      const double* xp = kk == 1 ? nullptr : slot(kk - 2);
-      err = ssm::launch_cheb_step_f64(n, nvp, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values,
-                                      kk == 1 ? alpha : 2.0 * alpha, kk == 1 ? beta : 2.0 * beta,
-                                      kk == 1 ? 0.0 : -1.0, x, xp, nullptr, slot(kk), st, nullptr, c->order);
+      const char* x = slot(kk - 1);
+      const char* xp = kk == 1 ? nullptr : slot(kk - 2);
+      const double sa = kk == 1 ? alpha : 2.0 * alpha, sb = kk == 1 ? beta : 2.0 * beta, sc = kk == 1 ? 0.0 : -1.0;
+      if (f64)
+        err = ssm::launch_cheb_step_f64(n, nvp, c->a.row_ptr, c->a.col_idx, (const double*)c->a.values, sa, sb, sc,
+                                        (const double*)x, (const double*)xp, nullptr, (double*)slot(kk), st, nullptr,
+                                        c->order);
+      else
+        err = ssm::launch_cheb_step_f32(n, nvp, c->a.row_ptr, c->a.col_idx, (const float*)c->a.values, (float)sa,
+                                        (float)sb, (float)sc, (const float*)x, (const float*)xp, nullptr,
+                                        (float*)slot(kk), st, nullptr, c->order);
       if (err != hipSuccess) return hip_fail(err, "Chebyshev step");
       ++spmm_launches;
     }
@@ -890,9 +933,9 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     for (int a = s_done; a < k_last;) {
       const int sa = a % R;
       const int len = sa == R - 1 ? 1 : std::min(k_last - a, R - 1 - sa);
-      const double* lo_blk = (const double*)c->y + (size_t)sa * e;
-      const double* hi_blk = sa == R - 1 ? (const double*)c->y : lo_blk + e;
-      err = ssm::launch_gram_pairs(0, n, nvp, len, hi_blk, lo_blk, e, c->pw + (int64_t)a * nnp,
+      const char* lo_blk = (const char*)c->y + (size_t)sa * e * es;
+      const char* hi_blk = sa == R - 1 ? (const char*)c->y : lo_blk + e * es;
+      err = ssm::launch_gram_pairs(!f64, n, nvp, len, hi_blk, lo_blk, e, c->pw + (int64_t)a * nnp,
                                    c->pz + (int64_t)a * nnp, pl.nseg, c->gpart, st);
       if (err != hipSuccess) return hip_fail(err, "pair Gram kernel");
       a += len;
@@ -903,8 +946,8 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     s_done = k_last;
   }
   // bound check inputs: ||V||_F^2 and ||T_{M/2+1}(A~) V||_F^2
-  err = ssm::launch_sumsq(c->w, e, 0, c->norm + 8, c->norm + 0, st);
-  if (err == hipSuccess) err = ssm::launch_sumsq(slot(S), e, 0, c->norm + 8, c->norm + 1, st);
+  err = ssm::launch_sumsq(c->w, e, !f64, c->norm + 8, c->norm + 0, st);
+  if (err == hipSuccess) err = ssm::launch_sumsq(slot(S), e, !f64, c->norm + 8, c->norm + 1, st);
   if (err != hipSuccess) return hip_fail(err, "norm kernel");
   // moments and the per-point sums (FP64 sweep GEMM over X, blocks of N_v'^2 entries)
   Span ms{mark(), 0, 1};
@@ -916,7 +959,8 @@ ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     err = ssm::launch_sweep_f64(nnp, m1, p.nt, c->nu, pl.ldc, pl.ldc, c->xm, c->knu, 0, st);
   if (err == hipSuccess) err = ssm::launch_ress_extract(p.nt, nv, nvh, c->kmu, c->knu, c->kw, c->kz, c->kc, c->trw, st);
   if (err == hipSuccess)
-    err = ssm::launch_ress_floor(nv, nvp, m / 2, c->xm, c->c64, pl.ldc, p.nt, kRessFloor, c->xmax, c->sfloor, st);
+    err = ssm::launch_ress_floor(nv, nvp, m / 2, c->xm, c->c64, pl.ldc, p.nt, f64 ? kRessFloor : kRessFloorF32,
+                                 c->xmax, c->sfloor, st);
   if (err != hipSuccess) return hip_fail(err, "moment kernels");
   ms.en = mark();
   SSM_HIP(rec(ms.en), "hipEventRecord");

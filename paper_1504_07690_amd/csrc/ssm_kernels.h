@@ -123,11 +123,12 @@ __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
 // nvh > 0 adds the hybrid correction of Algorithm 6 from k_c (ntb x nvh x nv), trw (ntb)
 // with hscr (ntb * nvh * nv doubles) as scratch.
 // s_floor (ntb doubles, may be null): Algorithm 4 step 2 also drops s_j < s_floor[i].
+// Point i writes r1 to ranks[i] and r2 to ranks[rank_stride + i] (rank_stride 0: ntb).
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max,
                                double tau, double rho, double* dos, int32_t* ranks, double* scratch,
                                hipStream_t stream, int nvh = 0, const double* k_c = nullptr,
                                const double* trw = nullptr, double* hscr = nullptr,
-                               const double* s_floor = nullptr);
+                               const double* s_floor = nullptr, int rank_stride = 0);
 // RESS-DGC (ress.hip): X_l, l < m1, of the N_v' = nvp block from the pair Gram matrices,
 // and the per-point split of K_mu, K_nu (nvp x nvp each) into K_W, K_Z (nv x nv), K_C
 // (nvh x nv) and Tr K_W~.

@@ -99,7 +99,8 @@ def test_dgc_moments_workspace(A, precision, vec):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(method=2), 1), (dict(nv_hybrid=4), 1), (dict(method=1, degree=51), 1),
-    (dict(method=1, degree=50, precision=1), 7), (dict(method=1, degree=50, precision=0, nv_hybrid=6), 1),
+    (dict(method=1, degree=50, precision=2), 7), (dict(method=1, degree=50, precision=3), 7),
+    (dict(method=1, degree=50, precision=0, nv_hybrid=6), 1),
     (dict(method=1, degree=50, precision=0, nv_hybrid=-4), 1),
     (dict(method=1, degree=50, precision=0, nv=128, nv_hybrid=132), 7),
     (dict(method=1, degree=50, precision=0, ckpt_every=8), 7), (dict(method=1, degree=50, precision=0, dgc=1), 7),
@@ -126,6 +127,11 @@ def test_ress_workspace_plan(A):
     tiny = C.c_size_t(0)
     assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 2 * e, C.byref(tiny)) == \
         A.SSM_ERR_WORKSPACE
+    # an FP32 recurrence: the same ring of 4-byte blocks
+    p32 = _params(A, nv=nv, degree=m, nt=nt, precision=1, method=1, nv_hybrid=nvh)
+    full32 = C.c_size_t(0)
+    assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p32), 0, C.byref(full32)) == 0
+    assert full.value - full32.value >= ring // 2
 
 
 def test_workspace_budget_forces_more_passes_or_chunks(A):

@@ -30,11 +30,12 @@ def S():
     return ssm
 
 
-def _ctx(S, wl, v, nv, nvh, budget=0, t=None):
-    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=DEV)
-    wd = torch.tensor(v, dtype=torch.float64, device=DEV)
+def _ctx(S, wl, v, nv, nvh, budget=0, t=None, precision="fp64"):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
+    wd = torch.tensor(v, dtype=dt, device=DEV)
     ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=wl.degree, t=wl.t if t is None else t,
-                precision="fp64", seed=wl.seed, w=wd, budget=budget, method="ress", nv_hybrid=nvh, device=DEV)
+                precision=precision, seed=wl.seed, w=wd, budget=budget, method="ress", nv_hybrid=nvh, device=DEV)
     return csr, wd, ctx
 
 
@@ -144,7 +145,7 @@ def test_ress_errors(S, cfg1):
     wl = cfg1
     csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
     with pytest.raises(A.SSMError) as ei:
-        S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=8, degree=20, t=wl.t, precision="fp32",
+        S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=8, degree=20, t=wl.t, precision="bf16x3",
               method="ress", device=DEV)
     assert ei.value.status == A.SSM_ERR_UNSUPPORTED
     v = WL.gaussian_block(wl.a.n, 8, seed=1)
@@ -182,3 +183,51 @@ def test_ress_hybrid_under_sampled_regime(S, cfg1):
     e_s = np.abs(ss - ref).sum() / np.abs(ref).sum()
     print(f"L1 vs exact DOS: RESS-DGC 20+20 {e_h:.3e}, SS-DGC 40 {e_s:.3e}; SS-DGC r1 max {r1.max()}")
     assert e_h < e_s
+
+
+def _l1(x, r):
+    return float(np.abs(x - r).sum() / np.abs(r).sum())
+
+
+@pytest.mark.parametrize("nv,nvh", [(40, 0), (20, 20), (12, 8)])
+def test_ress_fp32_recurrence(S, cfg1, nv, nvh):
+    """RESS-DGC with an FP32 recurrence and pair Gram matrices of FP32 blocks (products and
+    sums in FP64), against the oracle's FP64 Algorithm 7 on the same (FP32-rounded) V:
+    relative L1 within 1e-3, the gate of the reduced-precision paths.  Its floor of
+    Algorithm 4's truncation is 2^-18 of the sum of moments (the FP32 moments' rounding)."""
+    wl = cfg1
+    v = WL.gaussian_block(wl.a.n, nv + nvh, seed=5).astype(np.float32).astype(np.float64)
+    ref = O.ress_dgc(wl.a, v[:, :nv], v[:, nv:] if nvh else None, wl.t, wl.degree, wl.sigma, wl.lo, wl.hi)
+    csr, wd, ctx = _ctx(S, wl, v, nv, nvh, precision="fp32")
+    dos, r1, r2 = ctx.dos()
+    x = ctx.views()["moments"].cpu().numpy()
+    ctx.close()
+    xr = _moments(wl.a, v, wl.degree, wl.lo, wl.hi)
+    xerr = np.abs(x - xr).max() / np.abs(xr[0]).max()
+    print(f"RESS-DGC FP32 N_v={nv} N~_v={nvh}: DOS L1 vs the FP64 oracle {_l1(dos, ref['dos']):.2e}, "
+          f"max error {np.abs(dos - ref['dos']).max() / ref['dos'].max():.2e} of the maximum; moments "
+          f"{xerr:.2e} of max|X_0|")
+    assert _l1(dos, ref["dos"]) <= 1e-3
+    assert xerr <= 1e-5
+
+
+def test_ress_fp32_rank_resolved(S):
+    """N_v = 120 above the numerical rank of the 32 x 32 workload's filter (M = 1000,
+    sigma^ = 0.01, 64 points over the whole interval): the FP64 and FP32 RESS-DGC paths
+    against the oracle's Algorithm 7 and against the exact DOS of the degree-M/2 filter."""
+    a = WL.make_matrix(1)
+    wl = WL.make_workload(1, a=a, nv=120, degree=1000, nt=64, sigma_hat=0.01)
+    v = WL.gaussian_block(a.n, 120, seed=7).astype(np.float32).astype(np.float64)
+    ref = O.ress_dgc(a, v, None, wl.t, wl.degree, wl.sigma, wl.lo, wl.hi)
+    exact = O.exact_dos(np.linalg.eigvalsh(a.to_dense()), wl.t, wl.sigma)
+    out = {}
+    for precision in ("fp64", "fp32"):
+        csr, wd, ctx = _ctx(S, wl, v, 120, 0, precision=precision)
+        out[precision] = ctx.dos()
+        ctx.close()
+    for precision, (dos, r1, r2) in out.items():
+        print(f"RESS-DGC {precision} N_v=120: L1 vs oracle {_l1(dos, ref['dos']):.2e}, vs exact "
+              f"{_l1(dos, exact):.2e} (oracle vs exact {_l1(ref['dos'], exact):.2e}); r1 {r1.min()}..{r1.max()}")
+    _check(out["fp64"][0], ref["dos"], "RESS-DGC FP64 N_v=120")
+    assert _l1(out["fp32"][0], ref["dos"]) <= 1e-3
+    assert _l1(ref["dos"], exact) <= 1e-3
