@@ -10,8 +10,10 @@ the context's workspace (the coefficients of Algorithm 1, W, the split tables) a
 ssm_dos.  The adjoint (ssm_backward) of the
 measured path is timed once after the steps, and so is one ssm_dos that also forms the
 DGC estimate of Algorithm 2 from the same recurrence, and RESS-DGC (Algorithm 7, FP64)
-with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6), the random-graph
-workload's whole DOS and the 27-point workload's recurrence rate.  The oracle's baseline
+with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6; also with an FP32
+recurrence), the random-graph
+workload's whole DOS (SS-DGC, and RESS-DGC with an FP32 recurrence), the 27-point workload's
+recurrence rate and its whole DOS by RESS-DGC (FP32 recurrence).  The oracle's baseline
 runs first, on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
@@ -333,12 +335,13 @@ def main():
             "ssm_dos_max_rel_change": float(np.abs(dosd - dos).max() / dos.max()),
             "dgc_vs_ssm_l1_resolved": float(np.abs(dgc_out["dos"][keep] - dosd[keep]).sum() / np.abs(dosd[keep]).sum())}
     if not args.no_ress:
-        # Algorithm 7 (FP64) on the same workload: N_v = 80 alone, and 40 + 40 with the
-        # hybrid correction of Algorithm 6 (the paper's split when N_v is short of the rank)
+        # Algorithm 7 on the same workload: N_v = 80 alone, and 40 + 40 with the hybrid
+        # correction of Algorithm 6 (the paper's split when N_v is short of the rank); the
+        # recurrence in FP64, and in FP32 for the split
         keep = dos > 1e-2 * dos.max()
-        for nvr, nvh in ((80, 0), (40, 40)):
-            csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64, device=dev)
-            ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nvr, degree=m, t=wl.t, precision="fp64",
+        for rprec, nvr, nvh in (("fp64", 80, 0), ("fp64", 40, 40), ("fp32", 40, 40)):
+            csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float64 if rprec == "fp64" else torch.float32, device=dev)
+            ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nvr, degree=m, t=wl.t, precision=rprec,
                         seed=wl.seed, method="ress", nv_hybrid=nvh, budget=budget_left(), lattice=wl.lattice,
                         device=dev)
             ctx.dos()
@@ -357,8 +360,8 @@ def main():
             if "dos" in dgc_out:
                 entry["l1_vs_dgc_resolved"] = float(np.abs(dres[keep] - dgc_out["dos"][keep]).sum()
                                                     / np.abs(dgc_out["dos"][keep]).sum())
-            comparisons[f"ress_dgc_fp64_nv{nvr}_hybrid{nvh}"] = entry
-            log(f"RESS-DGC N_v={nvr} N~_v={nvh}: {msr:.1f} ms/DOS  phases {entry['phases_ms']}")
+            comparisons[f"ress_dgc_{rprec}_nv{nvr}_hybrid{nvh}"] = entry
+            log(f"RESS-DGC {rprec} N_v={nvr} N~_v={nvh}: {msr:.1f} ms/DOS  phases {entry['phases_ms']}")
     out["comparisons"] = comparisons
     if adjoint:
         out["adjoint"] = adjoint
@@ -372,7 +375,8 @@ def main():
 def large_workloads(S, WL, torch, dev, budget_left):
     """The random-graph workload's whole DOS (split-BF16 sweep, sweep-point batches as
     planned in the free memory; its DOS against the stored oracle values when present), and
-    the 27-point workload's recurrence rate (N_v = 256, a run of 400 steps on 8 points)."""
+    by RESS-DGC with an FP32 recurrence; the 27-point workload's recurrence rate (N_v = 256,
+    a run of 400 steps on 8 points) and its whole DOS by RESS-DGC (FP32 recurrence)."""
     res = {}
     wl = WL.make_workload(3)
     csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
@@ -403,6 +407,25 @@ def large_workloads(S, WL, torch, dev, budget_left):
         entry["dos_l1_vs_oracle_points"] = float(np.abs(dos[pts] - ref).sum() / np.abs(ref).sum())
     res["random_graph_dos"] = entry
     log(f"random graph: {s_dos:.2f} s per DOS, plan {entry['plan']}, {us:.0f} us per step")
+    # the same workload by RESS-DGC (Algorithm 7, FP32 recurrence to degree M/2 + 1): no Z,
+    # so no replays of the recurrence
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision="fp32",
+                seed=wl.seed, method="ress", budget=budget_left(12), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.reset()
+    dres, _, _ = ctx.dos()
+    s_res = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    torch.cuda.empty_cache()
+    res["random_graph_ress_dgc_fp32"] = {
+        "s_per_dos": s_res, "ring_slots": st["chunk"], "steps": st["spmm_launches"],
+        "phases_ms": {"recurrence": st["ms_recurrence"], "pair_gram": st["ms_gram"],
+                      "moments_and_sums": st["ms_sweep"], "geneig": st["ms_geneig"]}}
+    log(f"random graph, RESS-DGC FP32: {s_res:.2f} s per DOS")
 
     wl = WL.make_workload(5, degree=400)
     t = wl.t[wl.nt // 16::wl.nt // 8]
@@ -422,6 +445,27 @@ def large_workloads(S, WL, torch, dev, budget_left):
                                    "GBps_compulsory": comp / (us * 1e-6) / 1e9,
                                    "frac_hbm": comp / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
     log(f"27-point recurrence: {us:.0f} us per step, {res['stencil27_recurrence']['GBps_compulsory']:.0f} GB/s")
+    # its whole DOS (M = 4000, N_t = 4000) by RESS-DGC with an FP32 recurrence: SS-DGC would
+    # need about 36 sweep-point batches, each replaying the 4000 steps
+    wl = WL.make_workload(5)
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t, precision="fp32",
+                seed=wl.seed, method="ress", budget=budget_left(12), lattice=wl.lattice, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.reset()
+    ctx.dos()
+    s_res = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    torch.cuda.empty_cache()
+    res["stencil27_ress_dgc_fp32"] = {
+        "workload": wl.name, "nv": wl.nv, "degree": wl.degree, "nt": wl.nt, "s_per_dos": s_res,
+        "ring_slots": st["chunk"], "steps": st["spmm_launches"],
+        "phases_ms": {"recurrence": st["ms_recurrence"], "pair_gram": st["ms_gram"],
+                      "moments_and_sums": st["ms_sweep"], "geneig": st["ms_geneig"]}}
+    log(f"27-point workload, RESS-DGC FP32: {s_res:.1f} s per DOS")
     return res
 
 

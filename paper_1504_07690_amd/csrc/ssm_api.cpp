@@ -391,9 +391,6 @@ struct ssm_ctx {
   ssm_csr a{};
   ssm_params p{};
   hipStream_t stream = nullptr;
-  // Algorithm 4 of a group of sweep points runs on this stream while the caller's stream
-  // goes on with the next group's Gram matrices (or the next batch's passes)
-  hipStream_t side = nullptr;
   Plan pl;
   char* ws = nullptr;
   double* t = nullptr;
@@ -541,13 +538,10 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   c->dos_host.assign(p->nt, 0.0);
 
   auto bail = [&](ssm_status st) {
-    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return st;
   };
   hipError_t e;
-  if ((e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess)
-    return bail(hip_fail(e, "side stream"));
   if ((e = hipMemcpyAsync(c->t, t_host, sizeof(double) * p->nt, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return bail(hip_fail(e, "copy of sweep points"));
   if (pl.ldc != p->nt) {  // padding columns of the coefficient table are read by the sweep: make them 0
@@ -565,8 +559,8 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
                     hipSuccess)
     return bail(hip_fail(e, "coefficient norm kernel"));
   if (c->chi) {
-    if ((e = ssm::launch_split_coefficients(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, pl.ldk, p->nt,
-                                            c->stream)) != hipSuccess)
+    if ((e = ssm::launch_split_blocks(c->c64, pl.ldc, p->nt, p->degree + 1, c->chi, c->clo, (int)(pl.ldk / 16), p->nt,
+                                      c->stream)) != hipSuccess)
       return bail(hip_fail(e, "coefficient split kernel"));
   }
   if (pl.ress &&
@@ -603,7 +597,6 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
 ssm_status ssm_destroy(ssm_ctx* c) {
   if (!c) return fail(SSM_ERR_ARG, "ctx is NULL");
   for (auto ev : c->events) (void)hipEventDestroy(ev);
-  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
   return SSM_OK;
 }
@@ -708,12 +701,14 @@ ssm_status forward_pass(ssm_ctx* c, int pass, bool first, Timeline* tl, int64_t&
     if (f64)
       err = ssm::launch_sweep_f64(e, kc, nb, c->c64 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
                                   (const double*)y_slot(k_first), (double*)c->z, ch > 0, st);
-    else if (p.precision == SSM_FP32_BF16X3)
-      err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + (int64_t)p0 * pl.ldk + k_first,
-                                     c->clo + (int64_t)p0 * pl.ldk + k_first, pl.ldk, p.nt - p0,
-                                     (int64_t)(p.nt - p0) * pl.ldk - k_first, (const float*)y_slot(k_first),
-                                     (float*)c->z, ch > 0, c->k3 - k_first, nb, st);
-    else if (p.precision == SSM_FP32)
+    else if (p.precision == SSM_FP32_BF16X3) {
+      // the split tables are in 16-degree blocks of nt rows; chunk starts are multiples of 16
+      if (k_first % 16) return fail(SSM_ERR_STATE, "ring chunk starts at degree %d, not a multiple of 16", k_first);
+      const int64_t off = ((int64_t)(k_first / 16) * p.nt + p0) * 16;
+      err = ssm::launch_sweep_bf16x3(e, kc, nb, c->chi + off, c->clo + off, 16, p.nt - p0,
+                                     (int64_t)p.nt * pl.ldk - off, (const float*)y_slot(k_first), (float*)c->z,
+                                     ch > 0, c->k3 - k_first, nb, st, (int64_t)16 * p.nt);
+    } else if (p.precision == SSM_FP32)
       err = ssm::launch_sweep_f32(e, kc, nb, c->c32 + (int64_t)k_first * pl.ldc + p0, pl.ldc, pl.ldc - p0,
                                   (const float*)y_slot(k_first), (float*)c->z, ch > 0, st);
     else
@@ -745,7 +740,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
 
   // events: [0] start, then (begin, end) pairs per timed launch group
   const int nchunks = (m + 1 + pl.chunk - 1) / pl.chunk;
-  const size_t need = 4 + (size_t)pl.passes * (2 * nchunks + 16) * 2;
+  const size_t need = 2 + (size_t)pl.passes * (2 * nchunks + 2) * 2 + 4;
   while (c->events.size() < need) {
     hipEvent_t ev;
     SSM_HIP(hipEventCreate(&ev), "hipEventCreate");
@@ -772,43 +767,22 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
         err = ssm::launch_rounding_floor(c->mun, p.nt, c->eta, c->norm + 0, 1.0 / std::sqrt((double)e), c->sfloor, st);
       if (err != hipSuccess) return hip_fail(err, "norm kernel");
     }
-    // Gram matrices of the batch in groups of points; Algorithm 4 of each group follows on the
-    // side stream, beside the next group's Gram (or the next batch's passes): the Gram keeps
-    // the matrix cores busy, Algorithm 4 the LDS and the vector units
-    const int groups = nb >= 512 ? 4 : nb >= 128 ? 2 : 1;
-    for (int gi = 0; gi < groups; ++gi) {
-      const int q0 = p0 + (int)((int64_t)nb * gi / groups), q1 = p0 + (int)((int64_t)nb * (gi + 1) / groups);
-      const int ng = q1 - q0;
-      // segments for the group's size, within the plan's partial-sum buffer
-      const int nseg = std::max(1, std::min(gram_segments(n, ng), (int)((int64_t)pl.nseg * pl.batch / ng)));
-      Span gs{mark(), mark(), 2};
-      SSM_HIP(hipEventRecord(c->events[gs.b], st), "hipEventRecord");
-      hipError_t err = ssm::launch_gram(!f64, n, nv, ng, c->w, (const char*)c->z + (size_t)(q0 - p0) * e * es,
-                                        c->kw + (int64_t)q0 * nv * nv, c->kz + (int64_t)q0 * nv * nv, nseg, c->gpart,
-                                        st);
-      if (err != hipSuccess) return hip_fail(err, "Gram kernel");
-      SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
-      tl.spans.push_back(gs);
-      SSM_HIP(hipStreamWaitEvent(c->side, c->events[gs.en], 0), "hipStreamWaitEvent");
-      Span as{mark(), mark(), 3};
-      SSM_HIP(hipEventRecord(c->events[as.b], c->side), "hipEventRecord");
-      err = ssm::launch_geneig_trace(nv, ng, c->kw + (int64_t)q0 * nv * nv, c->kz + (int64_t)q0 * nv * nv, g_max,
-                                     p.tau, p.range_slack, c->dos + q0, c->ranks + q0,
-                                     c->escr + (int64_t)q0 * ssm::geneig_scratch_doubles(nv), c->side, 0, nullptr,
-                                     nullptr, nullptr, c->sfloor ? c->sfloor + q0 : nullptr, p.nt);
-      if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
-      SSM_HIP(hipEventRecord(c->events[as.en], c->side), "hipEventRecord");
-      tl.spans.push_back(as);
-    }
+    Span gs{mark(), mark(), 2};
+    SSM_HIP(hipEventRecord(c->events[gs.b], st), "hipEventRecord");
+    hipError_t err = ssm::launch_gram(!f64, n, nv, nb, c->w, c->z, c->kw + (int64_t)p0 * nv * nv,
+                                      c->kz + (int64_t)p0 * nv * nv, pl.nseg, c->gpart, st);
+    if (err != hipSuccess) return hip_fail(err, "Gram kernel");
+    SSM_HIP(hipEventRecord(c->events[gs.en], st), "hipEventRecord");
+    tl.spans.push_back(gs);
     c->last_batch_start = p0;
   }
-  // the caller's stream waits for the last group of Algorithm 4
-  const size_t ev_join = mark();
-  SSM_HIP(hipEventRecord(c->events[ev_join], c->side), "hipEventRecord");
-  SSM_HIP(hipStreamWaitEvent(st, c->events[ev_join], 0), "hipStreamWaitEvent");
-  const size_t ev_end = mark();
-  SSM_HIP(hipEventRecord(c->events[ev_end], st), "hipEventRecord");
-  hipError_t err;
+  Span es_{mark(), mark(), 3};
+  SSM_HIP(hipEventRecord(c->events[es_.b], st), "hipEventRecord");
+  hipError_t err = ssm::launch_geneig_trace(nv, p.nt, c->kw, c->kz, g_max, p.tau, p.range_slack, c->dos, c->ranks,
+                                            c->escr, st, 0, nullptr, nullptr, nullptr, c->sfloor);
+  if (err != hipSuccess) return hip_fail(err, "Algorithm 4 kernel");
+  SSM_HIP(hipEventRecord(c->events[es_.en], st), "hipEventRecord");
+  tl.spans.push_back(es_);
   if (pl.dgc_group) {
     err = ssm::launch_dgc(c->c64, pl.ldc, p.nt, m + 1, nv, c->dsums, c->dgc, c->dgc + p.nt, st);
     if (err != hipSuccess) return hip_fail(err, "Algorithm 2 kernel");
@@ -831,7 +805,7 @@ ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
     *dst += ms;
   }
   float tot = 0.f;
-  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[ev_end]), "hipEventElapsedTime");
+  SSM_HIP(hipEventElapsedTime(&tot, c->events[ev_start], c->events[es_.en]), "hipEventElapsedTime");
   S.ms_total = tot;
   S.spmm_launches = spmm_launches;
   S.sweep_launches = sweep_launches;

@@ -85,16 +85,21 @@ hipError_t launch_sweep_bf16(int64_t e, int kc, int ntb, const float* c, int64_t
 // arows = rows of chi/clo readable from the pointers, a_elems = bf16 values readable from
 // each pointer (at least (arows - 1) ldk + kc rounded up to 8: rows are read in 8-value
 // pieces; reads past it return zeros).  e % 4 == 0, z 16-byte aligned.
+// bstride != 16: the tables are in 16-degree blocks (launch_split_blocks): degree k of row
+// i at (k / 16) bstride + 16 i + k % 16, with ldk = 16 and bstride >= 16 arows.
 // k3: three products on the first k3 contraction indices of the launch (rounded up to
 // whole 32-wide k-steps), Chi^T Yhi alone on the rest; k3 >= kc: three everywhere.
 // m3: 256-row output tiles starting at or past row m3 take the single product
 // throughout (m3 >= ntb: no such tile).
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
                                int64_t arows, int64_t a_elems, const float* y, float* z, int accumulate, int k3,
-                               int m3, hipStream_t stream);
+                               int m3, hipStream_t stream, int64_t bstride = 16);
 size_t sweep_bf16x3_lds_bytes();
 hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo,
                                      int64_t ldk, int ntp, hipStream_t stream);
+// chi/clo in 16-degree blocks: degree k of point i at ((k / 16) ntp + i) 16 + k % 16, k < 16 nblk
+hipError_t launch_split_blocks(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo, int nblk,
+                               int ntp, hipStream_t stream);
 
 // Gram (gram.hip).  scratch: gram_scratch_slots(nseg) * ntb * 2 * nv * nv doubles.
 int gram_scratch_slots(int nseg);

@@ -395,8 +395,9 @@ __device__ __forceinline__ int x3_brow(int r) { return r ^ ((r >> 1) & 1); }
 template <bool ROW8>
 __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, int ntb,
                                                            const __bf16* __restrict__ chi,
-                                                           const __bf16* __restrict__ clo, int64_t ldk,
-                                                           int64_t arows, int64_t a_elems, const float* __restrict__ y,
+                                                           const __bf16* __restrict__ clo, int64_t rstride,
+                                                           int64_t bstride, int64_t arows, int64_t a_elems,
+                                                           const float* __restrict__ y,
                                                            float* __restrict__ z, int accumulate, int mt,
                                                            int nt_tiles, int k3, int m3) {
   extern __shared__ __attribute__((aligned(16))) unsigned char x3_lds[];
@@ -435,13 +436,16 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   int boffj[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) boffj[j] = (int)boff + (ROW8 ? (int)(j * e * 4) : 0);
+  // A lane loads 8 degrees (piece a_c of a row's 32): degrees 16 b .. 16 b + 15 of row i
+  // sit at b bstride + i rstride (rows: rstride = ldk, bstride = 16; 16-degree blocks:
+  // rstride = 16, bstride = 16 x rows)
   uint32_t aoff[2];
-  const int a_k = (tid & 3) * 8;
+  const int a_c = tid & 3;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int piece = tid + 512 * h;
     const int64_t i = (i0 + (piece >> 2) < arows) ? i0 + (piece >> 2) : arows - 1;
-    aoff[h] = (uint32_t)((i * ldk + a_k) * 2);
+    aoff[h] = (uint32_t)(((a_c >> 1) * bstride + i * rstride + (a_c & 1) * 8) * 2);
   }
   const int64_t abytes = a_elems * 2;  // the tables' extent from chi / clo
   auto rsrc = [](const void* p, int64_t bytes) {
@@ -451,12 +455,13 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
   auto load_t = [&](Staging& S, int u, auto three) {
     constexpr bool THREE = decltype(three)::value;
     const int k0 = X3_BK * u;
-    const auto rh = rsrc(chi + k0, abytes - (int64_t)k0 * 2);
+    const int64_t ub = (int64_t)(k0 / 16) * bstride;  // the unit's first 16-degree block
+    const auto rh = rsrc(chi + ub, abytes - ub * 2);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
       S.ra_hi[h] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)aoff[h], 0, 0));
     if constexpr (THREE) {
-      const auto rl = rsrc(clo + k0, abytes - (int64_t)k0 * 2);
+      const auto rl = rsrc(clo + ub, abytes - ub * 2);
 #pragma unroll
       for (int h = 0; h < 2; ++h)
         S.ra_lo[h] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)aoff[h], 0, 0));
@@ -493,7 +498,7 @@ __global__ void __launch_bounds__(512) sweep_bf16x3_kernel(int64_t e, int kc, in
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          if (X3_BK * u + a_k + j >= kc) S.ra_hi[h][j] = S.ra_lo[h][j] = 0;
+          if (X3_BK * u + 8 * a_c + j >= kc) S.ra_hi[h][j] = S.ra_lo[h][j] = 0;
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -684,6 +689,29 @@ __global__ void __launch_bounds__(256) split_coefficients_kernel(const double* _
   clo[gid] = lo;
 }
 
+// The same split in 16-degree blocks: degree k of point i at ((k / 16) ntp + i) 16 + k % 16
+// (blocks of ntp rows of 16, k < 16 nblk), so that the sweep's 256-point x 32-degree unit
+// of a table is two runs of 256 x 32 bytes instead of 256 half-lines a row apart.
+__global__ void __launch_bounds__(256) split_blocks_kernel(const double* __restrict__ c, int64_t ldc, int nt, int m1,
+                                                           __bf16* __restrict__ chi, __bf16* __restrict__ clo,
+                                                           int nblk, int ntp) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nblk * ntp * 16) return;
+  const int kk = (int)(gid & 15);
+  const int64_t row = gid >> 4;  // (k / 16) ntp + i
+  const int b = (int)(row / ntp);
+  const int i = (int)(row - (int64_t)b * ntp);
+  const int k = 16 * b + kk;
+  __bf16 hi = (__bf16)0.f, lo = (__bf16)0.f;
+  if (i < nt && k < m1) {
+    const double v = c[(int64_t)k * ldc + i];
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (double)hi);
+  }
+  chi[gid] = hi;
+  clo[gid] = lo;
+}
+
 template <typename T, typename K>
 hipError_t launch_tiles(K kernel, int bm, int bn, int64_t e, int kc, int ntb, const T* c, int64_t ldc,
                         int64_t acols, const T* y, T* z, int accumulate, hipStream_t stream) {
@@ -713,7 +741,7 @@ size_t sweep_bf16x3_lds_bytes() { return (size_t)2 * 4 * X3_TILE * sizeof(__bf16
 
 hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, const __bf16* clo, int64_t ldk,
                                int64_t arows, int64_t a_elems, const float* y, float* z, int accumulate, int k3,
-                               int m3, hipStream_t stream) {
+                               int m3, hipStream_t stream, int64_t bstride) {
   const size_t lds = sweep_bf16x3_lds_bytes();
   const bool row8 = e * 4 * 7 + 1024 < ((int64_t)1 << 31);
   const void* kfn = row8 ? (const void*)sweep_bf16x3_kernel<true> : (const void*)sweep_bf16x3_kernel<false>;
@@ -725,14 +753,19 @@ hipError_t launch_sweep_bf16x3(int64_t e, int kc, int ntb, const __bf16* chi, co
   const int64_t blocks = (int64_t)mt * nt_pad;
   if (blocks > 0x7FFFFFFF || ntiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   // e % 4 == 0: 16-byte stores of Z rows; the tables' byte offsets are 32-bit resource offsets
-  if (e < 4 || e % 4 || ((uintptr_t)z % 16) || arows < ntb || a_elems < (arows - 1) * ldk + (kc + 7) / 8 * 8 || a_elems * 2 > 0x7FFFFFFF)
+  // bstride = 16: rows of ldk degrees; else blocks of 16 degrees, bstride apart, holding
+  // rows of 16 (ldk = 16)
+  if (bstride != 16 && (ldk != 16 || bstride < 16 * arows || bstride % 8)) return hipErrorInvalidValue;
+  const int64_t plast = (kc + 7) / 8 - 1;  // the last 8-degree piece a row reads
+  const int64_t need = (plast / 2) * bstride + (arows - 1) * ldk + (plast % 2) * 8 + 8;
+  if (e < 4 || e % 4 || ((uintptr_t)z % 16) || arows < ntb || a_elems < need || a_elems * 2 > 0x7FFFFFFF)
     return hipErrorInvalidValue;
   if (row8)
     hipLaunchKernelGGL(sweep_bf16x3_kernel<true>, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo,
-                       ldk, arows, a_elems, y, z, accumulate, mt, (int)ntiles, k3, m3);
+                       ldk, bstride, arows, a_elems, y, z, accumulate, mt, (int)ntiles, k3, m3);
   else
     hipLaunchKernelGGL(sweep_bf16x3_kernel<false>, dim3((unsigned)blocks), dim3(512), lds, stream, e, kc, ntb, chi, clo,
-                       ldk, arows, a_elems, y, z, accumulate, mt, (int)ntiles, k3, m3);
+                       ldk, bstride, arows, a_elems, y, z, accumulate, mt, (int)ntiles, k3, m3);
   return hipGetLastError();
 }
 
@@ -741,6 +774,14 @@ hipError_t launch_split_coefficients(const double* c, int64_t ldc, int nt, int m
   const int64_t total = (int64_t)ntp * ldk;
   hipLaunchKernelGGL(split_coefficients_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, c, ldc,
                      nt, m1, chi, clo, ldk, ntp);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_blocks(const double* c, int64_t ldc, int nt, int m1, __bf16* chi, __bf16* clo, int nblk,
+                               int ntp, hipStream_t stream) {
+  const int64_t total = (int64_t)nblk * ntp * 16;
+  hipLaunchKernelGGL(split_blocks_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, c, ldc, nt,
+                     m1, chi, clo, nblk, ntp);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ from paper_1504_07690_amd import workloads as WL
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 GOLDEN4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "anderson64_spd_fp64_oracle.json")
+GOLDEN3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "er_graph_2p20_fp64_oracle.json")
 
 
 @pytest.fixture(scope="module")
@@ -228,6 +229,69 @@ def test_large_workload_sampled_stages(S, cfg, precision):
     del ctx, csr
     _free()
 
+
+
+def test_random_graph_dos_against_stored_oracle(S):
+    """The random-graph workload's whole DOS (N = 2^20, N_v = 128, M = 2000, N_t = 2000,
+    split-BF16 sweep, sweep-point batches as planned in the free memory) against the
+    oracle's FP64 SS-DGC at 16 strided points on the same W: relative L1 within 1e-3 (the
+    kept ranks are printed beside the oracle's)."""
+    if not os.path.exists(GOLDEN3):
+        pytest.skip("stored oracle values of the random-graph workload are not present")
+    with open(GOLDEN3) as fh:
+        g = json.load(fh)
+    wl = WL.make_workload(3)
+    assert wl.a.n == g["n"] and wl.a.nnz == g["nnz"] and abs(wl.lo - g["lo"]) < 1e-12
+    csr, ctx = _ctx(S, wl, "bf16x3", wl.t, budget=_budget())
+    dos, r1, r2 = ctx.dos()
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    _free()
+    pts, ref = np.array(g["points"]), np.array(g["dos"])
+    l1 = np.abs(dos[pts] - ref).sum() / np.abs(ref).sum()
+    print(f"{wl.name} bf16x3: plan {st['passes']} pass(es), ring {st['chunk']}, {st['ms_total'] / 1e3:.1f} s; "
+          f"L1 vs the stored oracle values at {len(pts)} points {l1:.2e}; r1 {r1[pts].tolist()} "
+          f"(oracle {g['r1']})")
+    assert l1 <= 1e-3
+
+
+def test_random_graph_ress_dgc_full_size(S):
+    """RESS-DGC (Algorithm 7) on the random-graph workload at full size (N = 2^20, N_v = 128,
+    M = 2000, N_t = 2000: 1001 recurrence steps, no Z), with an FP32 and an FP64 recurrence:
+    the moments X_0..X_2 of the device's block against the oracle's W^T T_l(A~) W on the same
+    W, the DOS within 0 <= phi <= N_v (1 + rho) g_max, and the FP32 path's DOS within 1e-3
+    relative L1 of the FP64 path's."""
+    wl = WL.make_workload(3)
+    g_max = O.range_bound(wl.sigma, wl.a.n)
+    out = {}
+    for precision in ("fp64", "fp32"):
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=DEV)
+        ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
+                    precision=precision, seed=wl.seed, method="ress", budget=_budget(), device=DEV)
+        dos, r1, r2 = ctx.dos()
+        st = ctx.stats()
+        v = ctx.views()
+        x = v["moments"][:3].cpu().numpy()
+        w = v["w"].double().cpu().numpy()
+        ctx.close()
+        del ctx, csr, v
+        _free()
+        print(f"{wl.name} RESS-DGC {precision}: {st['ms_total'] / 1e3:.2f} s (recurrence {st['ms_recurrence']:.0f}, "
+              f"pair Gram {st['ms_gram']:.0f}, moments {st['ms_sweep']:.0f}, Alg. 4 {st['ms_geneig']:.0f} ms), "
+              f"ring {st['chunk']}, r1 {r1.min()}..{r1.max()}")
+        ref = np.zeros_like(x)
+        for l, v_c in O.chebyshev_blocks(wl.a, w, 2, wl.lo, wl.hi):
+            ref[l] = w.T @ v_c
+        err = np.abs(x - ref).max() / np.abs(ref[0]).max()
+        print(f"  moments X_0..X_2: max error {err:.2e} of max|X_0|")
+        assert err <= (1e-11 if precision == "fp64" else 1e-5)
+        assert np.all(np.isfinite(dos)) and dos.min() >= 0.0 and dos.max() <= wl.nv * (1 + 1e-3) * g_max
+        out[precision] = dos
+    l1 = np.abs(out["fp32"] - out["fp64"]).sum() / np.abs(out["fp64"]).sum()
+    print(f"  FP32 against FP64 recurrence: DOS L1 {l1:.2e}")
+    assert l1 <= 1e-3
 
 
 @pytest.fixture(scope="module")

@@ -518,3 +518,40 @@ def test_lattice_row_order_changes_nothing(S, which, precision, nv):
         ctx.close()
     assert torch.equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("plan", [None, (304, 48), (104, 0), (104, 32)])
+def test_split_sweep_context_tables(S, plan):
+    """The context's split-BF16 sweep reads its coefficient tables in 16-degree blocks of all
+    N_t rows: rows of Z against the oracle's sweep (Algorithm 5 steps 6-8) of the device's
+    own blocks, on a ragged case (N_t = 300 points over two 256-point tiles, M + 1 = 101
+    degrees, N N_v not a multiple of 256), with every block resident, with a ring of 48
+    blocks (launches starting at degrees 48 and 96 that add into Z), and with batches of 104
+    points (launches starting at rows 104 and 208), alone and with a ring of 32."""
+    from test_gpu_configs import _assert_z_rows
+    a = WL.anderson_3d(13, _rng(31).uniform(-2, 2, 13 ** 3))
+    wl = WL.make_workload(2, a=a, nv=20, degree=100, nt=300, sigma_hat=0.03)
+    n, nv, m = wl.a.n, wl.nv, wl.degree
+    rows = np.sort(_rng(32).choice(n, 7, replace=False))
+    rows_t = torch.as_tensor(rows, device=DEV)
+    mu = O.dgc_coefficients(wl.t, m, wl.sigma, n, wl.lo, wl.hi)
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=DEV)
+    kw = dict(lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=m, t=wl.t, precision="bf16x3", seed=wl.seed,
+              device=DEV)
+    ctx = S.SSM(csr, **kw)  # every block resident: the device's Y_0..Y_M
+    ctx.dos()
+    yr = ctx.views()["y"][:, rows_t, :].double().cpu().numpy()
+    ctx.close()
+    ctx = S.SSM(csr, plan=plan, **kw)
+    ctx.dos()
+    st = ctx.stats()
+    v = ctx.views()
+    p0, nb = v["first_point_of_last_batch"], v["batch"]
+    nb = min(nb, wl.nt - p0)
+    z = v["z"][:nb, rows_t, :].double().cpu().numpy()
+    ctx.close()
+    print(f"plan {plan}: {st['passes']} passes, chunk {st['chunk']}, {st['sweep_launches']} sweep launches, "
+          f"k3 {st['split_k3']}; rows of Z of points {p0}..{p0 + nb - 1}")
+    if plan is not None:
+        assert st["passes"] > 1 or st["chunk"] < m + 1
+    _assert_z_rows(z, mu[:, p0:p0 + nb], yr, "bf16x3", st["split_k3"])
