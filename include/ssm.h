@@ -144,6 +144,14 @@ typedef struct ssm_stats {
   int32_t batch;           /* N_t^b: sweep points per batch */
   int32_t gram_segments;   /* row segments of the Gram partial sums */
   int32_t split_k3;        /* SSM_FP32_BF16X3: degrees below this take three products (else 0) */
+  int32_t box_stencil;     /* 1 if the recurrence takes the box-stencil kernel: a lattice whose
+                              rows' entries all lie in the 3 x 3 x 3 box of their point (periodic
+                              wrap, every side >= 3), rows of whole 1 KB multiples (N_v' times the
+                              element size) and x-y tiles of a multiple of 8 points; it gathers
+                              each line of a neighbourhood once for 8 points of a row of the
+                              lattice and sums each point's terms in box order (the CSR order
+                              away from the wrap), so blocks may differ from the CSR kernel's in
+                              rounding only */
 } ssm_stats;
 
 /* Message of the last failed call on this thread ("" if none). */

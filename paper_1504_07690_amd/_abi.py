@@ -40,7 +40,8 @@ class ssm_stats(C.Structure):
     _fields_ = [("ms_total", C.c_double), ("ms_recurrence", C.c_double), ("ms_sweep", C.c_double),
                 ("ms_gram", C.c_double), ("ms_geneig", C.c_double), ("spmm_launches", C.c_int64),
                 ("sweep_launches", C.c_int64), ("passes", C.c_int32), ("chunk", C.c_int32),
-                ("batch", C.c_int32), ("gram_segments", C.c_int32), ("split_k3", C.c_int32)]
+                ("batch", C.c_int32), ("gram_segments", C.c_int32), ("split_k3", C.c_int32),
+                ("box_stencil", C.c_int32)]
 
 
 class ssm_backward_stats(C.Structure):

@@ -230,6 +230,141 @@ __global__ void __launch_bounds__(256) dgc_kernel(const double* __restrict__ c, 
   out[i] = acc;
 }
 
+// Box stencils.  Offset of lattice coordinate u2 from u1 on a periodic side of length m
+// (m >= 3): -1, 0, 1, or 2 when u2 is farther away.
+__device__ __forceinline__ int wrap_diff(int u1, int u2, int m) {
+  int d = u2 - u1;
+  if (d == m - 1) d = -1;
+  if (d == 1 - m) d = 1;
+  return (d >= -1 && d <= 1) ? d : 2;
+}
+
+// slot 9 (dz + 1) + 3 (dy + 1) + dx + 1 of entry (row, col) in the box of row's point, or -1
+__device__ __forceinline__ int box_slot(int64_t row, int64_t col, int nx, int ny, int nz) {
+  const int x1 = (int)(row % nx), y1 = (int)((row / nx) % ny), z1 = (int)(row / ((int64_t)nx * ny));
+  const int x2 = (int)(col % nx), y2 = (int)((col / nx) % ny), z2 = (int)(col / ((int64_t)nx * ny));
+  const int dx = wrap_diff(x1, x2, nx), dy = wrap_diff(y1, y2, ny), dz = wrap_diff(z1, z2, nz);
+  if (dx == 2 || dy == 2 || dz == 2) return -1;
+  return 9 * (dz + 1) + 3 * (dy + 1) + dx + 1;
+}
+
+__global__ void __launch_bounds__(256) box_check_kernel(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col_idx, int nx, int ny, int nz,
+                                                        int* __restrict__ bad) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  uint32_t seen = 0;
+  for (int p = row_ptr[row]; p < row_ptr[row + 1]; ++p) {
+    const int sl = box_slot(row, col_idx[p], nx, ny, nz);
+    if (sl < 0 || (seen >> sl) & 1u) {
+      *bad = 1;
+      return;
+    }
+    seen |= 1u << sl;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) box_values_kernel(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col_idx,
+                                                         const T* __restrict__ val, int nx, int ny, int nz,
+                                                         T* __restrict__ box) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  T v[27];
+#pragma unroll
+  for (int s = 0; s < 27; ++s) v[s] = (T)0;
+  for (int p = row_ptr[row]; p < row_ptr[row + 1]; ++p) {
+    const int sl = box_slot(row, col_idx[p], nx, ny, nz);
+#pragma unroll
+    for (int s = 0; s < 27; ++s)
+      if (s == sl) v[s] = val[p];
+  }
+#pragma unroll
+  for (int s = 0; s < 27; ++s) box[row * 27 + s] = v[s];
+}
+
+// One step on a box stencil.  A wave computes kBoxRows consecutive points x0 .. x0 + R - 1
+// of a tile row (one 64-lane slice of their N_v values): for each of the 9 lines (dy, dz)
+// of their neighbourhood it gathers the R + 2 rows x0 - 1 .. x0 + R once and adds each
+// point's three terms in the order dx = -1, 0, 1, so a point's terms are summed in box
+// order (the CSR order of a row away from the lattice's wrap).  R + 2 gathers per line
+// instead of 3 R; the values come through the scalar cache (the rows are wave-uniform).
+template <typename T, typename V, bool KEEP>
+__global__ void __launch_bounds__(CS_THREADS) box_step_kernel(int64_t n, int nvv, int64_t nwaves, int64_t nblocks,
+                                                       int64_t per_xcd, const T* __restrict__ box, T a, T b,
+                                                       T c, const V* __restrict__ x,
+                                                       const V* __restrict__ xprev, const V* __restrict__ d,
+                                                       V* __restrict__ out, RowOrder o) {
+  constexpr int R = kBoxRows;
+  const int64_t lblock = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lblock >= nblocks) return;
+  const int64_t wid = lblock * (CS_THREADS / 64) + (threadIdx.x >> 6);
+  if (wid >= nwaves) return;  // uniform over the wave; the kernel has no barrier
+  const int lane = threadIdx.x & 63;
+  const int wpr = nvv / 64;  // waves per row
+  const int64_t g = wid / wpr;
+  const int q = (int)(wid - g * wpr) * 64 + lane;
+  const int r0 = __builtin_amdgcn_readfirstlane((int)tiled_row(g * R, o));
+  const int nx = o.nx, ny = o.ny, nz = o.nz;
+  const int x0 = r0 % nx, y = (r0 / nx) % ny, z = r0 / (nx * ny);
+  V acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = (V)(T)0;
+  const T* bx = box + (int64_t)r0 * 27;
+  const int xl = x0 == 0 ? nx - 1 : x0 - 1;      // left neighbour of the first point
+  const int xr = x0 + R == nx ? 0 : x0 + R;      // right neighbour of the last
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = z + dz < 0 ? nz - 1 : (z + dz == nz ? 0 : z + dz);
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = y + dy < 0 ? ny - 1 : (y + dy == ny ? 0 : y + dy);
+      const int64_t line = (int64_t)nx * (yy + (int64_t)ny * zz);
+      V gq[R + 2];
+      gq[0] = x[(line + xl) * nvv + q];
+#pragma unroll
+      for (int i = 0; i < R; ++i) gq[i + 1] = x[(line + x0 + i) * nvv + q];
+      gq[R + 1] = x[(line + xr) * nvv + q];
+      const int so = 9 * (dz + 1) + 3 * (dy + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r] += bx[27 * r + so] * gq[r];
+        acc[r] += bx[27 * r + so + 1] * gq[r + 1];
+        acc[r] += bx[27 * r + so + 2] * gq[r + 2];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t gid = (int64_t)(r0 + r) * nvv + q;
+    V res = a * acc[r] + b * x[gid];
+    if (xprev) res += c * __builtin_nontemporal_load(&xprev[gid]);
+    if (d) res += __builtin_nontemporal_load(&d[gid]);
+    if constexpr (KEEP)
+      out[gid] = res;
+    else
+      __builtin_nontemporal_store(res, &out[gid]);
+  }
+}
+
+template <typename T, typename V>
+hipError_t launch_box(bool keep, int64_t n, int nvv, const T* box, T a, T b, T c, const T* x, const T* xprev,
+                      const T* d, T* out, const RowOrder& o, hipStream_t stream) {
+  const int64_t nwaves = n / kBoxRows * (nvv / 64);
+  const int64_t nblocks = (nwaves + CS_THREADS / 64 - 1) / (CS_THREADS / 64);
+  const int64_t per_xcd = (nblocks + 7) / 8;
+  if (per_xcd * 8 > 0x7FFFFFFF || n > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(per_xcd * 8)), block(CS_THREADS);
+  if (keep)
+    hipLaunchKernelGGL((box_step_kernel<T, V, true>), grid, block, 0, stream, n, nvv, nwaves, nblocks, per_xcd, box, a,
+                       b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, o);
+  else
+    hipLaunchKernelGGL((box_step_kernel<T, V, false>), grid, block, 0, stream, n, nvv, nwaves, nblocks, per_xcd, box,
+                       a, b, c, (const V*)x, (const V*)xprev, (const V*)d, (V*)out, o);
+  return hipGetLastError();
+}
+
 template <typename T, typename V, bool TILED, bool WR>
 hipError_t launch_v(dim3 grid, bool keep, int64_t n, int nvv, int64_t nblocks, int64_t per_xcd, const int32_t* row_ptr,
                     const int32_t* col_idx, const T* val, T a, T b, T c, const T* x, const T* xprev, const T* d, T* out,
@@ -266,6 +401,8 @@ hipError_t launch(int64_t n, int nv, const int32_t* row_ptr, const int32_t* col_
   if (o.nx > 0) {
     if (!(o.tx > 0 && o.ty > 0 && o.nx % o.tx == 0 && o.ny % o.ty == 0 && (int64_t)o.nx * o.ny * o.nz == n))
       return hipErrorInvalidValue;
+    if (o.box && !dots && nvv % 64 == 0 && o.tx % kBoxRows == 0 && o.nx >= 3 && o.ny >= 3 && o.nz >= 3)
+      return launch_box<T, V>(keep, n, nvv, (const T*)o.box, a, b, c, x, xprev, d, out, o, stream);
     if (nvv % 64 == 0)
       return launch_v<T, V, true, true>(grid, keep, n, nvv, nblocks, per_xcd, row_ptr, col_idx, val, a, b, c, x, xprev,
                                         d, out, dots, o, stream);
@@ -293,6 +430,27 @@ hipError_t launch_cheb_step_f32(int64_t n, int nv, const int32_t* row_ptr, const
                                 const float* xprev, const float* d, float* out, hipStream_t stream,
                                 double* dots, const RowOrder& order) {
   return launch<float, f32x4, 4>(n, nv, row_ptr, col_idx, val, a, b, c, x, xprev, d, out, dots, order, stream);
+}
+
+hipError_t launch_box_check(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz,
+                            int* bad, hipStream_t stream) {
+  if (nx < 3 || ny < 3 || nz < 3 || (int64_t)nx * ny * nz != n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(box_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n, row_ptr, col_idx,
+                     nx, ny, nz, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_values(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* val, int is_f32,
+                             int nx, int ny, int nz, void* box, hipStream_t stream) {
+  if (nx < 3 || ny < 3 || nz < 3 || (int64_t)nx * ny * nz != n) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (is_f32)
+    hipLaunchKernelGGL(box_values_kernel<float>, grid, block, 0, stream, n, row_ptr, col_idx, (const float*)val, nx, ny,
+                       nz, (float*)box);
+  else
+    hipLaunchKernelGGL(box_values_kernel<double>, grid, block, 0, stream, n, row_ptr, col_idx, (const double*)val, nx,
+                       ny, nz, (double*)box);
+  return hipGetLastError();
 }
 
 int64_t cheb_step_blocks(int64_t n, int nv, int is_f32) {

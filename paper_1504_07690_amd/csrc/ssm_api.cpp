@@ -157,6 +157,19 @@ ssm::RowOrder row_order(const ssm_params* p) {
   return o;
 }
 
+// Bytes of A's values in box order that a context keeps when its lattice rows fill whole
+// waves (N_v' values of a row take a multiple of 1 KB) and its tiles hold whole groups of
+// kBoxRows points: the recurrence may then take the box kernel (if A's pattern passes the
+// box check at ssm_create).  0 otherwise.
+size_t box_bytes(const ssm_csr* a, const ssm_params* p) {
+  if (!p->lattice[0]) return 0;
+  const ssm::RowOrder o = row_order(p);
+  const size_t es = elem_bytes(p->precision);
+  const int nvp = p->nv + (p->method == SSM_RESS_DGC ? p->nv_hybrid : 0);
+  if (o.nx < 3 || o.ny < 3 || o.nz < 3 || o.tx % ssm::kBoxRows || (nvp * es) % 1024) return 0;
+  return (size_t)a->n * 27 * es;
+}
+
 double eff_tau(const ssm_params* p) { return p->tau > 0 ? p->tau : 1e-7; }
 double eff_rho(const ssm_params* p) { return p->range_slack >= 0 ? p->range_slack : 1e-3; }
 
@@ -188,6 +201,7 @@ struct Plan {
   bool ress = false;
   size_t off_nu = 0, off_kc = 0, off_trw = 0, off_hscr = 0, off_pw = 0, off_pz = 0, off_x = 0, off_kmu = 0,
          off_knu = 0, off_xmax = 0, off_floor = 0, off_mun = 0, off_kmax = 0;
+  size_t off_box = 0, box_bytes = 0;  // A's values in box order (lattice box stencils)
 };
 
 // Algorithm 2 by-product: recurrence steps s = 0..M/2 take inner products; their
@@ -261,6 +275,8 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
                                    : 0);
   pl.off_dsums = take(pl.dgc_group ? (size_t)2 * dgc_steps(p->degree) * 8 : 0);
   pl.off_dgc = take(pl.dgc_group ? (size_t)(p->nt + p->degree + 1) * 8 : 0);
+  pl.box_bytes = box_bytes(a, p);
+  pl.off_box = take(pl.box_bytes);
   pl.total = o;
 }
 
@@ -302,6 +318,8 @@ void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_floor = take((size_t)p->nt * 8);
   pl.off_gpart = take((size_t)ssm::gram_scratch_slots(pl.nseg) * std::max(pl.chunk, 1) * 2 * nnp * 8);
   pl.off_y = take((size_t)(pl.chunk + 1) * e * es);
+  pl.box_bytes = box_bytes(a, p);
+  pl.off_box = take(pl.box_bytes);
   pl.total = o;
 }
 
@@ -428,6 +446,7 @@ struct ssm_ctx {
   double* mun = nullptr;    // SS-DGC: sqrt(sum_l mu_l(t_i)^2) per point
   double eta = 0.0;         // SS-DGC: scale of the rounding floor (0: no floor)
   ssm::RowOrder order;      // the recurrence's visiting order of the rows
+  void* box = nullptr;      // A's values in box order (box stencils on the lattice), refreshed per call
   std::vector<double> dos_host;
   bool have_dos = false;
   bool have_dgc = false;
@@ -572,6 +591,15 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
                                         c->stream)) != hipSuccess)
       return bail(hip_fail(e, "W generator"));
   }
+  int box_bad = 1;
+  if (pl.box_bytes) {  // is every row's pattern inside the 3 x 3 x 3 box of its point?
+    int* flag = (int*)(c->ws + pl.off_box);
+    if ((e = hipMemsetAsync(flag, 0, sizeof(int), c->stream)) != hipSuccess ||
+        (e = ssm::launch_box_check(a->n, a->row_ptr, a->col_idx, p->lattice[0], p->lattice[1], p->lattice[2], flag,
+                                   c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(&box_bad, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return bail(hip_fail(e, "box stencil check"));
+  }
   std::vector<double> kmax;
   if (c->chi) {  // the largest coefficient of each degree
     kmax.resize(p->degree + 1);
@@ -584,6 +612,11 @@ ssm_status ssm_create(const ssm_csr* a, const ssm_params* p, const double* t_hos
   }
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(hip_fail(e, "ssm_create sync"));
   if (c->chi) c->k3 = three_product_degrees(kmax);
+  if (pl.box_bytes && !box_bad) {
+    c->box = c->ws + pl.off_box;
+    c->order.box = c->box;
+    c->stats.box_stencil = 1;
+  }
   c->stats.passes = pl.passes;
   c->stats.chunk = pl.chunk;
   c->stats.batch = pl.batch;
@@ -603,6 +636,15 @@ ssm_status ssm_destroy(ssm_ctx* c) {
 
 namespace {
 ssm_status ress_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host);
+
+// A's values in box order, from the CSR as it is now (the values may change between calls)
+ssm_status refresh_box(ssm_ctx* c) {
+  if (!c->box) return SSM_OK;
+  const int32_t* lt = c->p.lattice;
+  hipError_t e = ssm::launch_box_values(c->a.n, c->a.row_ptr, c->a.col_idx, c->a.values, c->p.precision != SSM_FP64,
+                                        lt[0], lt[1], lt[2], c->box, c->stream);
+  return e == hipSuccess ? SSM_OK : hip_fail(e, "box values");
+}
 }
 
 namespace {
@@ -727,6 +769,8 @@ ssm_status forward_pass(ssm_ctx* c, int pass, bool first, Timeline* tl, int64_t&
 
 ssm_status ssm_dos(ssm_ctx* c, double* dos_host, int32_t* ranks_host) {
   if (!c || !dos_host) return fail(SSM_ERR_ARG, "ctx and dos_host must be non-NULL");
+  ssm_status bs = refresh_box(c);
+  if (bs != SSM_OK) return bs;
   if (c->pl.ress) return ress_dos(c, dos_host, ranks_host);
   const ssm_params& p = c->p;
   const Plan& pl = c->pl;
@@ -1077,6 +1121,8 @@ ssm_status ssm_backward(ssm_ctx* c, const double* dos_bar_host, double* grad_dev
   if (!c->have_dos) return fail(SSM_ERR_STATE, "ssm_backward needs a preceding ssm_dos");
   for (int i = 0; i < p.nt; ++i)
     if (!std::isfinite(dos_bar_host[i])) return fail(SSM_ERR_ARG, "dos_bar[%d] is not finite", i);
+  ssm_status bs = refresh_box(c);  // blocks formed again here take A's values as they are now
+  if (bs != SSM_OK) return bs;
   const BackwardLayout L = backward_layout(c);
   if (ws_bytes < L.total || ((uintptr_t)workspace % kAlign))
     return fail(SSM_ERR_WORKSPACE, "backward needs %zu bytes (256-byte aligned), got %zu", L.total, ws_bytes);

@@ -22,7 +22,21 @@ hipError_t launch_gaussian_block(uint64_t seed, int64_t n, int nv, int dtype, vo
 // order): tiles of tx x ty points of the x-y plane (tx | nx, ty | ny), each through every z.
 struct RowOrder {
   int nx = 0, ny = 0, nz = 0, tx = 0, ty = 0;
+  // A's values in box order (launch_box_values), when every entry of a row lies in the
+  // 3 x 3 x 3 box of its lattice point: the step then gathers each line of a neighbourhood
+  // once for several rows (launch_cheb_step, no dots, rows of whole waves)
+  const void* box = nullptr;
 };
+// Box stencils on a periodic nx x ny x nz lattice (each side >= 3): *bad = 1 if a row of the
+// CSR has an entry outside the 3 x 3 x 3 box of its point or two entries in one box slot
+// (bad is written only then); launch_box_values writes box[27 row + s], s = 9 (dz + 1) +
+// 3 (dy + 1) + dx + 1, the value of the row's entry at that offset (0 where it has none).
+hipError_t launch_box_check(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, int nx, int ny, int nz,
+                            int* bad, hipStream_t stream);
+hipError_t launch_box_values(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const void* val, int is_f32,
+                             int nx, int ny, int nz, void* box, hipStream_t stream);
+// rows of a step computed together by the box kernel (tx must be a multiple of it)
+constexpr int kBoxRows = 8;
 
 // One Chebyshev step (cheb_spmm.hip):
 //   out = a * (A x) + b * x + c * xprev + d   (xprev, d may be null)

@@ -356,3 +356,26 @@ def test_lattice_validated(A, lattice, status):
     out = C.c_size_t(0)
     p = _params(A, lattice=(C.c_int32 * 3)(*lattice))
     assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, 64)), C.byref(p), 0, C.byref(out)) == status
+
+
+@pytest.mark.parametrize("nv,precision,lattice,grows", [
+    (256, 1, (16, 16, 16), True), (128, 0, (16, 16, 16), True), (80, 1, (16, 16, 16), False),
+    (256, 1, (12, 12, 12), False), (256, 1, None, False), (256, 0, (8, 8, 8), True)])
+def test_box_stencil_workspace(A, nv, precision, lattice, grows):
+    """A lattice context whose rows fill whole waves (N_v times the element size a multiple
+    of 1 KB) and whose x-y tiles hold multiples of 8 points keeps A's values in box order:
+    27 values per row more workspace; other contexts do not."""
+    n = 4096 if lattice is None else lattice[0] * lattice[1] * lattice[2]
+    sizes = []
+    for lt in (None, lattice):
+        p = _params(A, nv=nv, degree=20, nt=8, precision=precision)
+        if lt is not None:
+            p.lattice = (C.c_int32 * 3)(*lt)
+        out = C.c_size_t(0)
+        assert A.lib.ssm_workspace_size(C.byref(_dummy_csr(A, n)), C.byref(p), 0, C.byref(out)) == 0
+        sizes.append(out.value)
+    es = 8 if precision == 0 else 4
+    if grows:
+        assert sizes[1] - sizes[0] >= n * 27 * es and sizes[1] - sizes[0] < n * 27 * es + 512
+    else:
+        assert sizes[1] == sizes[0]

@@ -501,7 +501,10 @@ def test_lattice_row_order_changes_nothing(S, which, precision, nv):
     """The recurrence's tiled visiting order of a lattice's rows (tiles of 16, 8, 4 or 2
     points of the x-y plane through every z), with the CSR entries through the scalar cache
     where a row fills a wave (N_v = 256 in FP32, 128 in FP64): every block and the DOS bit
-    for bit equal to the plain row order's."""
+    for bit equal to the plain row order's.  Where the tiles hold multiples of 8 points and
+    rows fill waves, the lattice context takes the box-stencil kernel, which sums a point's
+    terms in box order: there the blocks agree to the rounding of that order (FP32 1e-5,
+    FP64 1e-13 of the block's largest entry, over 60 steps) and the DOS to 1e-5 (1e-12)."""
     nx = int(which[-2:])
     rng = _rng(nx)
     a = WL.anderson_3d(nx, rng.uniform(-2, 2, nx ** 3)) if which.startswith("anderson") else \
@@ -514,10 +517,55 @@ def test_lattice_row_order_changes_nothing(S, which, precision, nv):
         ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
                     precision=precision, seed=wl.seed, lattice=lattice, device=DEV)
         dos, r1, r2 = ctx.dos()
-        out.append((dos, ctx.views()["y"].clone()))
+        out.append((dos, ctx.views()["y"].clone(), ctx.stats()["box_stencil"]))
         ctx.close()
-    assert torch.equal(out[0][1], out[1][1])
-    assert np.array_equal(out[0][0], out[1][0])
+    box = out[1][2]
+    assert out[0][2] == 0
+    assert box == (nv * (8 if precision == "fp64" else 4) % 1024 == 0 and nx % 8 == 0), box
+    if not box:
+        assert torch.equal(out[0][1], out[1][1])
+        assert np.array_equal(out[0][0], out[1][0])
+        return
+    y0, y1 = out[0][1].double(), out[1][1].double()
+    tol_y, tol_d = (1e-13, 1e-12) if precision == "fp64" else (1e-5, 1e-5)
+    dy = ((y1 - y0).abs().amax(dim=(1, 2)) / y0.abs().amax(dim=(1, 2))).max().item()
+    dd = np.abs(out[1][0] - out[0][0]).max() / np.abs(out[0][0]).max()
+    print(f"{which} {precision} N_v={nv}: box kernel, blocks {dy:.2e}, DOS {dd:.2e} of the largest")
+    assert dy <= tol_y and dd <= tol_d
+
+
+@pytest.mark.parametrize("which,precision,nv", [("stencil16", "fp32", 256), ("anderson16", "fp64", 128),
+                                                ("stencil08", "fp64", 256)])
+def test_box_stencil_recurrence_against_oracle(S, which, precision, nv):
+    """The box-stencil kernel of the recurrence (8 points of a lattice row per wave, every
+    neighbourhood line gathered once, wrapped rows included) against the oracle's
+    recurrence (Algorithm 5 steps 9-10): every block of 30 steps on the same W within the
+    chebyshev test's bounds (FP32 2e-5, FP64 1e-12 of max|W| per step)."""
+    nx = int(which[-2:])
+    rng = _rng(nx + 1)
+    a = WL.anderson_3d(nx, rng.uniform(-2, 2, nx ** 3)) if which.startswith("anderson") else \
+        WL.stencil27_lognormal(nx, rng)
+    degree = 30
+    wl = WL.make_workload(2, a=a, nv=nv, degree=degree, nt=8, sigma_hat=0.05)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    w = wl.w()
+    if precision == "fp32":
+        w = w.astype(np.float32).astype(np.float64)
+    csr = S.DeviceCSR.from_csr(a, dtype=dt, device=DEV)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=nv, degree=degree, t=wl.t, precision=precision,
+                w=torch.tensor(w, dtype=dt, device=DEV), lattice=(nx, nx, nx), device=DEV)
+    assert ctx.stats()["box_stencil"] == 1
+    ctx.dos()
+    got = ctx.views()["y"].double().cpu().numpy()
+    ctx.close()
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    scale = np.abs(w).max()
+    worst = 0.0
+    for l, v in O.chebyshev_blocks(a, w, degree, wl.lo, wl.hi):
+        err = np.abs(got[l] - v).max()
+        worst = max(worst, err / (scale * max(1, l)))
+        assert err <= tol * scale * max(1, l), l
+    print(f"{which} {precision} N_v={nv}: worst block error {worst:.2e} of max|W| per step")
 
 
 @pytest.mark.parametrize("plan", [None, (304, 48), (104, 0), (104, 32)])
