@@ -137,27 +137,44 @@ __device__ void jacobi(const GeShared& sh, double* V, int n, int ld) {
         sh.sn[tid] = s;
       }
       __syncthreads();
-      // blocks (j, k), j <= k, numbered row by row.  Each lane takes U blocks per pass and
-      // issues all their loads before any store (the blocks of a round are disjoint), so that
-      // U loads are in flight at once where A lives in global scratch.
-      for (int i0 = tid; i0 < nblocks; i0 += U * TH) {
+      // blocks (j, k), j <= k.  Each lane takes U blocks per pass and issues all their loads
+      // before any store (the blocks of a round are disjoint), so that U loads are in flight
+      // at once where A lives in global scratch.  In LDS (U = 1) the blocks are numbered row
+      // by row of the triangle.  In global scratch a wave takes an 8 x 8 tile of blocks (j in
+      // 8 consecutive pairs, k in 8 others): the entries it writes, and their mirrors, then
+      // fall in 8 runs of 8 consecutive columns instead of 64 separate rows.
+      const int T8 = (npairs + 7) / 8;
+      const int nwork = U == 1 ? nblocks : T8 * (T8 + 1) / 2 * 64;
+      // row j of a triangle of side P starts at j P - j (j - 1) / 2: the quadratic inverted in
+      // float (within one of the row for P <= 128), then corrected by one step
+      auto tri = [](int idx, int P, int& j, int& k) {
+        const int P2 = 2 * P + 1;
+        j = (int)((P2 - sqrtf((float)(P2 * P2 - 8 * idx))) * 0.5f);
+        j = j < 0 ? 0 : (j >= P ? P - 1 : j);
+        if (j * P - j * (j - 1) / 2 > idx)
+          --j;
+        else if ((j + 1) * P - (j + 1) * j / 2 <= idx)
+          ++j;
+        k = j + (idx - (j * P - j * (j - 1) / 2));
+      };
+      for (int i0 = tid; i0 < nwork; i0 += U * TH) {
         int jj[U], kk[U];
         double a[U], b[U], c0[U], d[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int idx = i0 + u * TH;
           jj[u] = -1;
-          if (idx >= nblocks) continue;
-          // row j of the upper triangle starts at j P - j (j - 1) / 2 (P = npairs): the quadratic
-          // inverted in float (within one of the row for P <= 128), then corrected by one step
-          const int P2 = 2 * npairs + 1;
-          int j = (int)((P2 - sqrtf((float)(P2 * P2 - 8 * idx))) * 0.5f);
-          j = j < 0 ? 0 : (j >= npairs ? npairs - 1 : j);
-          if (j * npairs - j * (j - 1) / 2 > idx)
-            --j;
-          else if ((j + 1) * npairs - (j + 1) * j / 2 <= idx)
-            ++j;
-          const int k = j + (idx - (j * npairs - j * (j - 1) / 2));
+          if (idx >= nwork) continue;
+          int j, k;
+          if (U == 1) {
+            tri(idx, npairs, j, k);
+          } else {  // TH is a multiple of 64: a wave's lanes share one tile
+            int tj, tk;
+            tri(idx >> 6, T8, tj, tk);
+            j = 8 * tj + ((idx & 63) >> 3);
+            k = 8 * tk + (idx & 7);
+            if (j >= npairs || k >= npairs || j > k) continue;
+          }
           const int pj = sh.pp[j], qj = sh.qq[j], pk = sh.pp[k], qk = sh.qq[k];
           if (qj < 0 || qk < 0) {  // a one-element pair: a row, a column or one entry
             if (qj < 0 && qk < 0) continue;  // its diagonal entry does not change
