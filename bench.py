@@ -441,6 +441,7 @@ def large_workloads(S, WL, torch, dev, budget_left):
     comp, _ = spmm_bytes_models(wl.a.n, wl.a.nnz, wl.nv, 4)
     us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
     res["stencil27_recurrence"] = {"workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv,
+                                   "kernel": "box_step_kernel" if st["box_stencil"] else "cheb_step_kernel",
                                    "steps": st["spmm_launches"], "us_per_step": us,
                                    "GBps_compulsory": comp / (us * 1e-6) / 1e9,
                                    "frac_hbm": comp / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
