@@ -13,8 +13,9 @@ DGC estimate of Algorithm 2 from the same recurrence, and RESS-DGC (Algorithm 7,
 with N_v = 80 and with 40 + 40 vectors (hybrid correction of Algorithm 6; also with an FP32
 recurrence), the random-graph
 workload's whole DOS (SS-DGC, and RESS-DGC with an FP32 recurrence), the 27-point workload's
-recurrence rate and its whole DOS by RESS-DGC (FP32 recurrence).  The oracle's baseline
-runs first, on the host cores.
+recurrence rate and its whole DOS by RESS-DGC (FP32 recurrence), the 32 x 32 workload (device
+paths against the oracle's whole run on one host thread), and the copy and GEMM rates torch's
+own kernels reach on the GPU.  The oracle's baseline runs first, on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|bf16|fp64]
                     [--no-fp64] [--no-bf16] [--no-cpu-baseline] [--no-adjoint] [--no-dgc] [--no-ress]
@@ -153,6 +154,78 @@ def spmm_bytes_models(n, nnz, nv, es):
     return compulsory, gather
 
 
+def machine_rates(torch, dev):
+    """What the GPU reaches on plain library work, beside the vendor peaks: a device-to-device
+    copy of 4 GiB (bytes read + written per second) and square GEMMs in BF16 and FP64 (torch's
+    BLAS), each the best of 5 launches."""
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+    src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    t_copy = best(lambda: dst.copy_(src))
+    del src, dst
+    out = {"copy_GBps": 2 * (4 << 30) / t_copy / 1e9}
+    for name, dt, nn in (("bf16_gemm_TFLOPs", torch.bfloat16, 8192), ("fp64_gemm_TFLOPs", torch.float64, 8192)):
+        a = torch.randn(nn, nn, dtype=dt, device=dev)
+        b = torch.randn(nn, nn, dtype=dt, device=dev)
+        t = best(lambda: torch.matmul(a, b))
+        out[name] = 2 * nn ** 3 / t / 1e12
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_small():
+    """The oracle's whole SS-DGC on the 32 x 32 random Laplacian (N = 1024, N_v = 40, M = 200,
+    N_t = 200) on one host thread, the paper's setting: seconds and the estimate."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ssm_oracle as O
+    from paper_1504_07690_amd import workloads as WL
+    wl = WL.make_workload(1)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ref = O.ss_dgc(wl.a, wl.w(), wl.t, wl.degree, wl.sigma, wl.lo, wl.hi)
+        return time.perf_counter() - t0, ref["dos"]
+
+
+def small_workload(S, WL, torch, dev, oracle_small):
+    """The 32 x 32 random Laplacian (N = 1024, N_v = 40, M = 200, N_t = 200): the device's FP64 and
+    split-BF16 paths, against the oracle's run of the baseline leg (one host thread) on the
+    same W when it was taken."""
+    wl = WL.make_workload(1)
+    w = wl.w()
+    entry = {"workload": wl.name, "n": wl.a.n, "nv": wl.nv, "degree": wl.degree, "nt": wl.nt}
+    ref = None
+    if oracle_small is not None:
+        entry["oracle_s_one_thread"], ref = oracle_small
+    for precision in ("fp64", "bf16x3"):
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        csr = S.DeviceCSR.from_csr(wl.a, dtype=dt, device=dev)
+        ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=wl.t,
+                    precision=precision, w=torch.tensor(w, dtype=dt, device=dev), device=dev)
+        ctx.dos()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dos, _, _ = ctx.dos()
+        t_dev = time.perf_counter() - t0
+        ctx.close()
+        entry[f"{precision}_ms_per_dos"] = t_dev * 1e3
+        if ref is not None:
+            entry[f"{precision}_dos_l1_vs_oracle"] = float(np.abs(dos - ref).sum() / np.abs(ref).sum())
+    return entry
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,11 +251,15 @@ def main():
 
     # the oracle's baseline first: its process pool forks before anything touches the GPU
     baseline = None
+    oracle_small = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample on the host cores ...")
         t0 = time.time()
         baseline = cpu_baseline(2)
         log(f"oracle baseline: {baseline['value']:.4g} s per DOS extrapolated ({time.time() - t0:.1f} s)")
+        if not args.no_large:
+            oracle_small = cpu_baseline_small()
+            baseline["small_workload_s_one_thread"] = oracle_small[0]
 
     import torch
 
@@ -367,6 +444,10 @@ def main():
         out["adjoint"] = adjoint
     if not args.no_large:
         out["large"] = large_workloads(S, WL, torch, dev, budget_left)
+    if not args.no_large:
+        out["small"] = small_workload(S, WL, torch, dev, oracle_small)
+        out["machine"] = machine_rates(torch, dev)
+        log(f"32^2 workload: {out['small']}; machine: {out['machine']}")
     if baseline is not None:
         out["cpu_baseline"] = baseline
     print(json.dumps(out), flush=True)
