@@ -125,8 +125,17 @@ typedef struct ssm_params {
   int32_t lattice[3];      /* 0, 0, 0, or (nx, ny, nz) with nx ny nz = N when row x + nx (y + ny z)
                               is point (x, y, z) of a lattice (a stencil matrix): the recurrence then
                               computes the rows tile by tile of the x-y plane, each tile through
-                              every z, so that the rows a stencil gathers stay in the L2.  The
-                              results do not depend on it (a visiting order only) */
+                              every z, so that the rows a stencil gathers stay in the L2 (a
+                              visiting order only: the blocks do not depend on it).  Where the
+                              rows fill whole 1 KB multiples (N_v' times the element size), the
+                              tiles hold multiples of 8 points and every side is at least 3, the
+                              workspace also holds A's values in box order (27 N values) and, if
+                              ssm_create finds every row's entries inside the 3 x 3 x 3 box of its
+                              point (periodic wrap), the recurrence takes the box-stencil kernel
+                              (ssm_stats.box_stencil): blocks then differ from the CSR kernel's
+                              in the rounding order of rows next to the wrap only.  The values
+                              in box order are refreshed from the CSR at each ssm_dos and
+                              ssm_backward */
 } ssm_params;
 
 /* Per-phase device times (milliseconds, HIP events on the context's stream)
