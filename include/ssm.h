@@ -417,16 +417,25 @@ ssm_status ssm_gram(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const
 ssm_status ssm_gram_noalloc(int32_t precision, int64_t n, int32_t nv, int32_t ntb, const void* w, const void* z,
                             double* k_w, double* k_z, int32_t nseg, void* stream);
 
-/* Algorithm 4 and the trace, for ntb points: for point i, eig(k_w[i]) = U S U^T,
- * keep s_j >= tau max_j s_j (nothing if max s <= 0), B = S~^-1/2 U~^T k_z[i]
- * U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi in [0, (1 + rho) g_max];
- * ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).  Cyclic Jacobi in
- * FP64.  scratch: ntb*nv*nv doubles for nv <= 96, ntb*(nv*nv + nv*(nv+1)) for
- * 96 < nv <= 128 (the eigenvector matrix then lives in it instead of LDS) and
- * ntb*(nv*nv + 2*nv*(nv+1)) above (both Jacobi matrices). */
+/* Algorithm 4 and the trace, for ntb points: for point i, eig(k_w[i]) = U S U^T
+ * (k_w[i] taken as its symmetric part), keep s_j >= tau max_j s_j (nothing if
+ * max s <= 0), B = S~^-1/2 U~^T k_z[i] U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi
+ * in [0, (1 + rho) g_max]; ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).
+ * All in FP64: cyclic Jacobi for nv <= 128; above, a Householder reduction to
+ * tridiagonal form, implicit QL for eig(k_w[i]) and bisection for eig(B) (a point
+ * whose QL iterations run past their limit is redone by Jacobi).  k_w, k_z: ntb
+ * row-major nv x nv FP64 matrices on the device; dos_dev: ntb doubles, ranks_dev:
+ * 2 ntb int32 (may be NULL).  scratch: ssm_geneig_trace_scratch_doubles(nv, ntb)
+ * doubles of device memory, owned by the caller, contents ignored on entry.
+ * SSM_ERR_ARG on NULL pointers, nv or ntb < 1 or bad g_max/tau/rho;
+ * SSM_ERR_UNSUPPORTED for nv > 256. */
 ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max,
                             double tau, double rho, double* dos_dev, int32_t* ranks_dev, double* scratch,
                             void* stream);
+/* Scratch of ssm_geneig_trace in doubles: ntb nv^2 for nv <= 96, ntb (nv^2 + nv(nv+1))
+ * for 96 < nv <= 128, min(ntb, 2048) (6 nv^2 + 8 nv + 8) above (the tridiagonal
+ * path runs 2048 points at a time).  -1 for nv outside [1, 256] or ntb < 1. */
+int64_t ssm_geneig_trace_scratch_doubles(int32_t nv, int32_t ntb);
 
 #ifdef __cplusplus
 }

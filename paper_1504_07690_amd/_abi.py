@@ -94,6 +94,7 @@ _SIGS = {
     "ssm_gram_noalloc": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int32, _P]),
     "ssm_geneig_trace": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P,
                                    _P, _P]),
+    "ssm_geneig_trace_scratch_doubles": (C.c_int64, [C.c_int32, C.c_int32]),
 }
 
 for _name, (_res, _args) in _SIGS.items():

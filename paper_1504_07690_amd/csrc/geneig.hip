@@ -275,6 +275,8 @@ __device__ void jacobi_for(const GeShared& sh, double* V, int m, int ld, int nv)
     jacobi<TH, 4>(sh, V, m, ld);
 }
 
+// Point i's scratch starts at scratch + i scr_stride.  With `only` set, point i is
+// skipped unless only[i scr_stride] is nonzero (the points the tridiagonal path gave up).
 // With nvh > 0 (Algorithm 6 / 7 with N~_v = nvh columns of W~) the point also gets the
 // hybrid correction (Tr K_W~ - ||K_C C~||_F^2) / N~_v, C~ = U~ S~^-1/2 Q~ with Q~ the
 // eigenvectors of step 3 that pass step 4: G = K_C U~ S~^-1/2 (N~_v x r1, in hscr) is
@@ -288,16 +290,19 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
                                                                   const double* __restrict__ k_c,
                                                                   const double* __restrict__ trw,
                                                                   double* __restrict__ hscr,
-                                                                  const double* __restrict__ s_floor) {
+                                                                  const double* __restrict__ s_floor,
+                                                                  int64_t scr_stride,
+                                                                  const double* __restrict__ only) {
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t nn = (int64_t)n * n;
+  if (only && only[i * scr_stride] == 0.0) return;  // a point the tridiagonal path finished
   const double* kw = k_w + i * nn;
   const double* kz = k_z + i * nn;
-  double* tmat = scratch + i * (int64_t)geneig_scratch_doubles(nv);
+  double* tmat = scratch + i * scr_stride;
   GeShared sh;
   ge_layout(sh, lds, n, tmat + nn, TH);
 
@@ -607,6 +612,723 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// N_v above GE_TRI_NV, trace only (no hybrid correction): the two symmetric
+// eigenproblems go through a tridiagonal matrix instead of Jacobi sweeps, whose
+// cost there is the traffic of rotating two N_v x N_v matrices in global scratch
+// once per round.
+//   a. Householder reduction Q^T K Q = T (T tridiagonal: d on the diagonal, e[i]
+//      coupling i and i + 1), the reflectors kept in the rows of the reduced matrix;
+//   b. for K_W: Q by backward accumulation of the reflectors, stored transposed, then
+//      implicit QL with Wilkinson shifts on T; each QL iteration's plane rotations
+//      are applied to the rows of Z = Q (one lane per row, the rows of Q^T read
+//      contiguously across lanes), so Z ends as the eigenvectors, row j of the
+//      transposed array being eigenvector j (the layout of the Jacobi path);
+//   c. for B: eigenvalues only, by bisection on the Sturm counts of T, one lane per
+//      eigenvalue index.
+// Scratch per point (geneig_scratch_doubles, all row stride n): Q and then the n x r1
+// product at 0, the matrix being reduced at n^2, Z^T at n^2 + n (n + 1).
+// ---------------------------------------------------------------------------
+constexpr int GT_TH = 256;           // one lane per matrix row or column (n <= 256)
+constexpr int GT_MAX_QL = 30;        // QL iterations allowed per eigenvalue, on average
+constexpr double GT_EPS = 0x1p-52;   // deflation and bisection tolerance unit
+constexpr int GT_U = 8;              // loads a lane issues before it uses the first
+
+struct TriShared {
+  double d[GE_MAX_NV];
+  double e[GE_MAX_NV];
+  double tau[GE_MAX_NV];
+  double v[2][GE_MAX_NV];  // this step's reflector and the next one's
+  double w[2][GE_MAX_NV];  // this step's w and the next step's p
+  double cs[GE_MAX_NV];
+  double sn[GE_MAX_NV];
+  double s[GE_MAX_NV];
+  double scale[GE_MAX_NV];
+  double red[GT_TH / 64];
+  int kidx[GE_MAX_NV];
+  int misc[4];
+};
+
+// Sum over the workgroup: a butterfly in each wave (lane 0's value taken), then the
+// waves' sums in a fixed order; every lane returns the same value.
+__device__ __forceinline__ double gt_sum(double v, double* red) {
+  static_assert(GT_TH == 256, "four waves");
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = __shfl(v, 0);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// The reflector of x (m entries, global): H = I - tau v v^T with v_0 = 1 maps x to
+// beta e_1 (tau = 0, beta = x_0 when x_1.. are all 0).  v goes to vout; returns tau, beta
+// in *beta.  Every lane must call it.
+__device__ __forceinline__ double gt_reflector(const double* x, int m, double* vout, double* beta, TriShared& sh) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int j = 1 + tid; j < m; j += GT_TH) part += x[j] * x[j];
+  const double sigma2 = gt_sum(part, sh.red);
+  const double alpha = x[0];
+  double tau = 0.0, b = alpha, scl = 0.0;
+  if (sigma2 > 0.0) {
+    const double nrm = sqrt(alpha * alpha + sigma2);
+    b = alpha >= 0.0 ? -nrm : nrm;
+    tau = (b - alpha) / b;
+    scl = 1.0 / (alpha - b);
+  }
+  for (int j = tid; j < m; j += GT_TH) vout[j] = j == 0 ? 1.0 : x[j] * scl;
+  *beta = b;
+  return tau;
+}
+
+// Householder reduction of the symmetric n x n matrix A (global, row stride ld, both
+// triangles held) to T = (d, e).  Step k: x = A[k][k+1..] (= the column below the
+// diagonal), H = I - tau v v^T with v_0 = 1 maps x to beta e_1, and the trailing block
+// A22 <- H A22 H = A22 - v w^T - w v^T with p = tau A22 v, w = p - (tau/2)(p.v) v.
+// Each step after the first reads A22 once: its first row is updated first, the next
+// reflector is taken from it, and the pass that updates the rest of A22 also forms the
+// next p (the column of A22 below that row is never read again, so it is left as is).
+// v is left in A[k][k+1..], tau in sh.tau[k] (0: H = I).
+__device__ __forceinline__ void tri_reduce(double* A, int n, int ld, TriShared& sh) {
+  const int tid = threadIdx.x;
+  if (n >= 3) {  // step 0's reflector and p
+    double beta;
+    const double tau = gt_reflector(A + 1, n - 1, sh.v[0], &beta, sh);
+    if (tid == 0) {
+      sh.d[0] = A[0];
+      sh.e[0] = beta;
+      sh.tau[0] = tau;
+    }
+    __syncthreads();
+    const int m = n - 1;
+    const double* a22 = A + ld + 1;
+    for (int c = tid; c < m; c += GT_TH) {
+      double acc = 0.0;
+      int r = 0;
+#pragma unroll 1
+      for (; r + GT_U <= m; r += GT_U) {
+        double a[GT_U];
+#pragma unroll
+        for (int u = 0; u < GT_U; ++u) a[u] = a22[(int64_t)(r + u) * ld + c];
+#pragma unroll
+        for (int u = 0; u < GT_U; ++u) acc += a[u] * sh.v[0][r + u];
+      }
+      for (; r < m; ++r) acc += a22[(int64_t)r * ld + c] * sh.v[0][r];
+      sh.w[0][c] = tau * acc;
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k + 2 < n; ++k) {
+    const int b = k & 1;  // buffers of this step; the next step's are b ^ 1
+    const int m = n - k - 1;
+    const double tau = sh.tau[k];
+    double* vk = sh.v[b];
+    double* wk = sh.w[b];
+    double* a22 = A + (int64_t)(k + 1) * ld + k + 1;
+    if (tau != 0.0) {  // w = p - (tau/2)(p.v) v
+      double part = 0.0;
+      for (int j = tid; j < m; j += GT_TH) part += wk[j] * vk[j];
+      const double h = 0.5 * tau * gt_sum(part, sh.red);
+      for (int j = tid; j < m; j += GT_TH) wk[j] -= h * vk[j];
+      __syncthreads();
+      for (int c = tid; c < m; c += GT_TH) a22[c] -= vk[0] * wk[c] + wk[0] * vk[c];  // row k + 1
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (k + 3 < n) {  // next reflector from row k + 1, then the rest of A22 with p'
+      double beta;
+      const double tau1 = gt_reflector(a22 + 1, m - 1, sh.v[b ^ 1], &beta, sh);
+      if (tid == 0) {
+        sh.d[k + 1] = a22[0];
+        sh.e[k + 1] = beta;
+        sh.tau[k + 1] = tau1;
+      }
+      __syncthreads();
+      const double* vn = sh.v[b ^ 1];
+      for (int c = 1 + tid; c < m; c += GT_TH) {
+        // with tau = 0 (H = I) the column's v_c, w_c are 0 and p was 0, so A22 stays as it is
+        const double vc = tau != 0.0 ? vk[c] : 0.0, wc = tau != 0.0 ? wk[c] : 0.0;
+        double* col = a22 + c;
+        double acc = 0.0;
+        int r = 1;
+#pragma unroll 1
+        for (; r + GT_U <= m; r += GT_U) {
+          double a[GT_U];
+#pragma unroll
+          for (int u = 0; u < GT_U; ++u) a[u] = col[(int64_t)(r + u) * ld];
+#pragma unroll
+          for (int u = 0; u < GT_U; ++u) {
+            const double x = a[u] - (vk[r + u] * wc + wk[r + u] * vc);
+            col[(int64_t)(r + u) * ld] = x;
+            acc += x * vn[r + u - 1];
+          }
+        }
+        for (; r < m; ++r) {
+          const double x = col[(int64_t)r * ld] - (vk[r] * wc + wk[r] * vc);
+          col[(int64_t)r * ld] = x;
+          acc += x * vn[r - 1];
+        }
+        sh.w[b ^ 1][c - 1] = tau1 * acc;
+      }
+    } else if (tau != 0.0) {  // last step: the 2 x 2 block's second row
+      for (int c = tid; c < m; c += GT_TH) a22[ld + c] -= vk[1] * wk[c] + wk[1] * vk[c];
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int j = tid; j < m; j += GT_TH) A[(int64_t)k * ld + k + 1 + j] = vk[j];  // row k is no longer read
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (tid == 0) {
+    if (n >= 2) {
+      sh.d[n - 2] = A[(int64_t)(n - 2) * ld + n - 2];
+      sh.e[n - 2] = A[(int64_t)(n - 1) * ld + n - 2];
+      sh.tau[n - 2] = 0.0;
+    }
+    sh.d[n - 1] = A[(int64_t)(n - 1) * ld + n - 1];
+    sh.e[n - 1] = 0.0;
+    sh.tau[n - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Eigenvalue j (ascending) of T = (sh.d, sh.e), n x n, by bisection: the count of
+// eigenvalues below x is the number of negative pivots of the LDL^T factorisation of
+// T - x I (Sturm), pivots of magnitude <= pivmin replaced by -pivmin.  The search runs
+// from the Gershgorin interval until its width is <= 2 eps ||T|| (the midpoint is
+// returned).  sh.w[0] must hold e_i^2, and e2max their maximum.
+__device__ __forceinline__ double tri_bisect(int j, int n, const TriShared& sh, double glo, double ghi, double e2max) {
+  const double tn = fmax(fabs(glo), fabs(ghi));
+  const double tol = fmax(2.0 * GT_EPS * tn, 1e-300);
+  const double pivmin = 0x1p-1022 * fmax(1.0, e2max);
+  double a = glo - tol, b = ghi + tol;
+  for (int it = 0; it < 128 && b - a > tol; ++it) {
+    const double x = 0.5 * (a + b);
+    double q = sh.d[0] - x;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+      q = (sh.d[i] - x) - sh.w[0][i - 1] / q;
+      if (fabs(q) <= pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    if (cnt > j)
+      b = x;
+    else
+      a = x;
+  }
+  return 0.5 * (a + b);
+}
+
+// Per-point scratch of the tridiagonal path (row stride n throughout): the matrix being
+// reduced (its reflectors, later B) at 0, Z^T at n^2, the QL record (later the n x r1
+// product) at 2 n^2, then d, e, tau, the eigenvalues of K_W and the point's status.
+struct TriPoint {
+  double* a;
+  double* zt;
+  double* rec;
+  double* d;
+  double* e;
+  double* tau;
+  double* eig;
+  double* status;  // [0]: 0 when QL finished, 1 when it stopped (the Jacobi kernel redoes the point);
+                   // [1]: QL iterations recorded; [2]: rotations recorded
+  int* hdr;        // per recorded iteration: m, i0 (its rotations are i = m-1 down to i0)
+  __device__ TriPoint(double* base, int n) {
+    const int64_t nn = (int64_t)n * n;
+    a = base;
+    zt = base + nn;
+    rec = base + 2 * nn;
+    d = base + 6 * nn;
+    e = d + n;
+    tau = e + n;
+    eig = tau + n;
+    status = eig + n;
+    hdr = (int*)(status + 8);
+  }
+};
+constexpr int GT_REC_NN = 4;   // rotation record capacity, in doubles per n^2
+constexpr int GT_REC_IT = 4;   // recorded iterations allowed, per n (about 2 n are taken)
+
+// a. The symmetric part of K_W reduced to tridiagonal form.
+__global__ void __launch_bounds__(GT_TH) geneig_tri_reduce_kernel(int nv, const double* __restrict__ k_w,
+                                                                  double* __restrict__ scratch, int64_t stride) {
+  __shared__ TriShared sh;
+  const int n = nv;
+  const int tid = threadIdx.x;
+  const double* kw = k_w + blockIdx.x * (int64_t)n * n;
+  TriPoint pt(scratch + blockIdx.x * stride, n);
+  for (int idx = tid; idx < n * n; idx += GT_TH) {
+    const int r = idx / n, c = idx - r * n;
+    pt.a[idx] = 0.5 * (kw[idx] + kw[(int64_t)c * n + r]);
+  }
+  __threadfence_block();
+  __syncthreads();
+  tri_reduce(pt.a, n, n, sh);
+  for (int j = tid; j < n; j += GT_TH) {
+    pt.d[j] = sh.d[j];
+    pt.e[j] = sh.e[j];
+    pt.tau[j] = sh.tau[j];
+  }
+}
+
+// 1/sqrt(x) for normal x > 0: the hardware estimate and two Newton steps
+// y <- y (3 - x y^2) / 2 (each at least doubles the correct bits).
+__device__ __forceinline__ double gt_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// b. Implicit QL with Wilkinson shifts on T, by one lane: it finds the next unreduced
+// block [l, m] (|e_m| <= eps (|d_m| + |d_m+1|) splits it), takes one shifted iteration on
+// it and records the iteration's rotations (c_i, s_i), i = m-1 down to i0, in the
+// stream pt.rec, with (m, i0) in pt.hdr.  The rotations are to be applied, in record
+// order, to the columns (i, i+1) of Z: z_i+1 <- s z_i + c z_i+1, z_i <- c z_i - s z_i+1.
+// Status 1 when the iterations exceed GT_MAX_QL n, or the record its capacity.
+__global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __restrict__ scratch, int64_t stride) {
+  __shared__ double d[GE_MAX_NV], e[GE_MAX_NV];
+  const int n = nv;
+  TriPoint pt(scratch + blockIdx.x * stride, n);
+  for (int j = threadIdx.x; j < n; j += 64) {
+    d[j] = pt.d[j];
+    e[j] = pt.e[j];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int64_t cap = (int64_t)GT_REC_NN * n * n;
+  double* rec = pt.rec;
+  int64_t pos = 0;
+  int l = 0, iters = 0, nrec = 0;
+  bool ok = true;
+  for (;;) {
+    int mm = -1;
+    while (l < n) {
+      int m = l;
+      for (; m < n - 1; ++m)
+        if (fabs(e[m]) <= GT_EPS * (fabs(d[m]) + fabs(d[m + 1]))) break;
+      if (m == l) {
+        ++l;
+        continue;
+      }
+      mm = m;
+      break;
+    }
+    if (mm < 0) break;
+    if (++iters > GT_MAX_QL * n || nrec >= GT_REC_IT * n || pos + 2 * (mm - l) > cap) {
+      ok = false;
+      break;
+    }
+    // shift: the eigenvalue of the leading 2 x 2 block nearer d_l
+    double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+    double r = sqrt(g * g + 1.0);
+    g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+    double s = 1.0, c = 1.0, p = 0.0;
+    int i = mm - 1;
+    double ei = e[i], di = d[i], di1 = d[i + 1];  // entries the step reads, loaded one step ahead
+    for (; i >= l; --i) {
+      const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? d[i - 1] : 0.0;
+      const double f = s * ei, b = c * ei;
+      const double ss = f * f + g * g;
+      if (ss == 0.0) {  // the block splits at i + 1: drop the shift and redo the block
+        e[i + 1] = 0.0;
+        d[i + 1] = di1 - p;
+        e[mm] = 0.0;
+        break;
+      }
+      const double inv = gt_rsqrt(ss);
+      r = ss * inv;
+      e[i + 1] = r;
+      s = f * inv;
+      c = g * inv;
+      g = di1 - p;
+      r = (di - g) * s + 2.0 * c * b;
+      p = s * r;
+      d[i + 1] = g + p;
+      g = c * r - b;
+      rec[pos] = c;
+      rec[pos + 1] = s;
+      pos += 2;
+      ei = en;
+      di1 = di;
+      di = dn;
+    }
+    if (i + 1 < mm) {
+      pt.hdr[2 * nrec] = mm;
+      pt.hdr[2 * nrec + 1] = i + 1;
+      ++nrec;
+    }
+    if (i < l) {
+      d[l] -= p;
+      e[l] = g;
+      e[mm] = 0.0;
+    }
+  }
+  for (int j = 0; j < n; ++j) pt.eig[j] = d[j];
+  pt.status[1] = nrec;
+  pt.status[2] = (double)(pos / 2);
+  pt.status[0] = ok ? 0.0 : 1.0;
+}
+
+// c. Rows of U = Q Y, 64 per workgroup, one per lane of wave 0 (in LDS as L[j][lane], so
+// the wave's accesses are contiguous): row r starts as e_r, takes x <- x H_k for
+// k = 0..n-3 (x - tau (x.v) v^T), then the recorded rotations, and is written to
+// Z^T[.][r].  Wave 1 feeds wave 0 through two LDS slots per kind: the reflectors one per
+// step, the rotation record in blocks of GT_BLK (an iteration may span blocks; wave 0
+// carries its state across).  Its loads are issued GT_VD (GT_RD) steps before their
+// data is due, in rotating register sets, so a step waits for none of them; each step
+// ends at a barrier.  The workgroups of one point's row chunks run on one XCD (blockIdx
+// modulo 8 picks the XCD), so the record streams from that XCD's L2 after the first.
+constexpr int GT_BLK = 512;  // rotations per staged block
+constexpr int GT_VD = 3;     // reflector loads in flight
+constexpr int GT_RD = 2;     // rotation block loads in flight
+
+__host__ __device__ constexpr size_t tri_vectors_lds_doubles(int n) {
+  return (size_t)n * 64 + 2 * GE_MAX_NV + 2 * 2 * GT_BLK + GE_MAX_NV + GT_REC_IT * GE_MAX_NV;
+}
+__host__ __device__ inline int tri_vectors_groups(int np, int nv) { return (np + 7) / 8 * 8 * ((nv + 63) / 64); }
+
+__global__ void __launch_bounds__(128) geneig_tri_vectors_kernel(int nv, int np, double* __restrict__ scratch,
+                                                                 int64_t stride) {
+  extern __shared__ double lds[];
+  const int n = nv;
+  double* L = lds;
+  double* vslot = L + n * 64;                  // 2 reflectors
+  double* rslot = vslot + 2 * GE_MAX_NV;       // 2 blocks of rotations
+  double* taus = rslot + 2 * 2 * GT_BLK;
+  int* hdr = (int*)(taus + GE_MAX_NV);         // 2 GT_REC_IT GE_MAX_NV ints
+  const int nch = (n + 63) / 64;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int point = (slot / nch) * 8 + xcd, ch = slot % nch;
+  if (point >= np) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  TriPoint pt(scratch + point * stride, n);
+  if (pt.status[0] != 0.0) return;
+  const int nit = (int)pt.status[1];
+  const int64_t nrot = (int64_t)pt.status[2];
+  const int nrefl = n - 2;
+  const int r = ch * 64 + lane;
+  constexpr int VQ = GE_MAX_NV / 64, RQ = 2 * GT_BLK / 64;
+
+  // Loads are unconditional, at a clamped address inside the point's data; the entries
+  // past the end are zeroed when the set is written to LDS.  So the compiler can count the
+  // loads in flight and wait for the oldest set only.
+  auto load_v = [&](int k, double (&x)[VQ]) {  // reflector k, lane-strided
+    const int kk = k < nrefl ? k : nrefl - 1;
+    const double* v = pt.a + (int64_t)kk * n + kk + 1;
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) {
+      const int idx = lane + 64 * q;
+      x[q] = v[idx < n - kk - 1 ? idx : 0];
+    }
+  };
+  auto put_v = [&](int k, const double (&x)[VQ]) {
+    const int m = k < nrefl ? n - k - 1 : 0;
+    double* dst = vslot + (k & 1) * GE_MAX_NV;
+#pragma unroll
+    for (int q = 0; q < VQ; ++q) dst[lane + 64 * q] = lane + 64 * q < m ? x[q] : 0.0;
+  };
+  const int64_t last = 2 * nrot - 1;  // the record's last entry (-1: none)
+  auto load_r = [&](int64_t blk, double (&x)[RQ]) {
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int64_t idx = blk * 2 * GT_BLK + lane + 64 * q;
+      x[q] = pt.rec[idx <= last ? idx : (last > 0 ? last : 0)];
+    }
+  };
+  auto put_r = [&](int64_t blk, const double (&x)[RQ]) {
+    double* dst = rslot + (blk & 1) * 2 * GT_BLK;
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) dst[lane + 64 * q] = blk * 2 * GT_BLK + lane + 64 * q <= last ? x[q] : 0.0;
+  };
+
+  // wave 0's step k of the reflector phase: x <- x H_k
+  auto reflect = [&](int k) {
+    const int m = n - k - 1;
+    const double tau = taus[k];
+    const double* v = vslot + (k & 1) * GE_MAX_NV;
+    if (tau == 0.0) return;
+    double* x = L + (k + 1) * 64 + lane;
+    double acc[4] = {};
+    int t = 0;
+    for (; t + GT_U <= m; t += GT_U) {
+      double xv[GT_U];
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u) xv[u] = x[(t + u) * 64];
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u) acc[u & 3] += xv[u] * v[t + u];
+    }
+    for (; t < m; ++t) acc[0] += x[t * 64] * v[t];
+    const double y = tau * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    for (t = 0; t + GT_U <= m; t += GT_U) {  // reads of a batch before its writes
+      double xv[GT_U], vv[GT_U];
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u) {
+        xv[u] = x[(t + u) * 64];
+        vv[u] = v[t + u];
+      }
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u) x[(t + u) * 64] = xv[u] - y * vv[u];
+    }
+    for (; t < m; ++t) x[t * 64] -= y * v[t];
+  };
+
+  // the two waves run separate loops with the same barriers: 1 + nrefl + 1 + nblk
+  const int64_t nblk = (nrot + GT_BLK - 1) / GT_BLK;
+  if (wave == 1) {
+    double vs[GT_VD][VQ];  // reflectors in flight, v_j in set j % GT_VD
+    for (int j = lane; j < n; j += 64) taus[j] = pt.tau[j];
+    for (int j = lane; j < 2 * nit; j += 64) hdr[j] = pt.hdr[j];
+    load_v(0, vs[0]);
+    put_v(0, vs[0]);
+#pragma unroll
+    for (int j = 1; j <= GT_VD; ++j) load_v(j, vs[j % GT_VD]);
+    __syncthreads();
+    // step k: v_{k+1} (loaded GT_VD steps ago) to LDS, v_{k+1+GT_VD} into the same set
+    for (int k0 = 0; k0 < nrefl; k0 += GT_VD) {
+#pragma unroll
+      for (int u = 0; u < GT_VD; ++u) {
+        const int k = k0 + u;
+        if (k < nrefl) {
+          put_v(k + 1, vs[(u + 1) % GT_VD]);
+          load_v(k + 1 + GT_VD, vs[(u + 1) % GT_VD]);
+          __syncthreads();
+        }
+      }
+    }
+    double rs[GT_RD][RQ];  // rotation blocks in flight, block j in set j % GT_RD
+    load_r(0, rs[0]);
+    put_r(0, rs[0]);
+#pragma unroll
+    for (int j = 1; j <= GT_RD; ++j) load_r(j, rs[j % GT_RD]);
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nblk; b0 += GT_RD) {
+#pragma unroll
+      for (int u = 0; u < GT_RD; ++u) {
+        const int64_t blk = b0 + u;
+        if (blk < nblk) {
+          put_r(blk + 1, rs[(u + 1) % GT_RD]);
+          load_r(blk + 1 + GT_RD, rs[(u + 1) % GT_RD]);
+          __syncthreads();
+        }
+      }
+    }
+  } else {
+    for (int j = 0; j < n; ++j) L[j * 64 + lane] = j == r ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = 0; k < nrefl; ++k) {
+      reflect(k);
+      __syncthreads();
+    }
+    __syncthreads();
+    int it = 0, t = 0, mm = 0, i0 = 0, cnt = 0;  // the iteration and rotation reached
+    double hold = 0.0;
+    if (nit > 0) {
+      mm = hdr[0];
+      i0 = hdr[1];
+      cnt = mm - i0;
+    }
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+      const double* rb = rslot + (blk & 1) * 2 * GT_BLK;
+      int64_t p = blk * GT_BLK;
+      const int64_t pend = p + GT_BLK < nrot ? p + GT_BLK : nrot;
+      while (p < pend) {
+        if (t == 0) hold = L[mm * 64 + lane];
+        const int nh = (int)(cnt - t < pend - p ? cnt - t : pend - p);
+        const double* rc = rb + 2 * (p - blk * GT_BLK);
+        const int top = mm - 1 - t;  // rotation j of this run is i = top - j
+        int j = 0;
+        // every LDS read of a batch is issued before its first write: the compiler cannot
+        // tell the rows written from the rotations read, so it would not move them
+        for (; j + GT_U <= nh; j += GT_U) {
+          double z[GT_U], c[GT_U], sn[GT_U];
+#pragma unroll
+          for (int u = 0; u < GT_U; ++u) {
+            z[u] = L[(top - j - u) * 64 + lane];
+            c[u] = rc[2 * (j + u)];
+            sn[u] = rc[2 * (j + u) + 1];
+          }
+#pragma unroll
+          for (int u = 0; u < GT_U; ++u) {
+            L[(top - j - u + 1) * 64 + lane] = sn[u] * z[u] + c[u] * hold;
+            hold = c[u] * z[u] - sn[u] * hold;
+          }
+        }
+        for (; j < nh; ++j) {
+          const double z = L[(top - j) * 64 + lane];
+          const double c = rc[2 * j], sn = rc[2 * j + 1];
+          L[(top - j + 1) * 64 + lane] = sn * z + c * hold;
+          hold = c * z - sn * hold;
+        }
+        t += nh;
+        p += nh;
+        if (t == cnt) {
+          L[i0 * 64 + lane] = hold;
+          t = 0;
+          if (++it < nit) {
+            mm = hdr[2 * it];
+            i0 = hdr[2 * it + 1];
+            cnt = mm - i0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (r < n)
+    for (int j = wave; j < n; j += 2) pt.zt[(int64_t)j * n + r] = L[j * 64 + lane];
+}
+
+// d. Algorithm 4 steps 2-4 from U, S: truncation, B, its eigenvalues (reduction, then
+// bisection) and the trace.
+__global__ void __launch_bounds__(GT_TH) geneig_tri_trace_kernel(int nv, const double* __restrict__ k_z,
+                                                                 double g_max, double tau, double rho,
+                                                                 double* __restrict__ dos,
+                                                                 int32_t* __restrict__ ranks, int rank_stride,
+                                                                 double* __restrict__ scratch, int64_t stride,
+                                                                 const double* __restrict__ s_floor) {
+  __shared__ TriShared sh;
+  const int n = nv, ld = nv;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* kz = k_z + i * (int64_t)n * n;
+  TriPoint pt(scratch + i * stride, n);
+  if (*pt.status != 0.0) return;  // the Jacobi kernel writes this point
+  double* A = pt.a;
+  const double* zt = pt.zt;
+  double* q = pt.rec;  // the n x r1 product
+
+  // 2. truncation
+  if (tid == 0) {
+    double smax = -INFINITY;
+    for (int j = 0; j < n; ++j) smax = fmax(smax, pt.eig[j]);
+    int r1 = 0;
+    if (smax > 0.0) {
+      const double thr = s_floor ? fmax(tau * smax, s_floor[i]) : tau * smax;
+      for (int j = 0; j < n; ++j) {
+        const double sj = pt.eig[j];
+        if (sj >= thr) {
+          sh.kidx[r1] = j;
+          sh.scale[r1] = 1.0 / sqrt(sj);
+          ++r1;
+        }
+      }
+    }
+    sh.misc[0] = r1;
+  }
+  __syncthreads();
+  const int r1 = sh.misc[0];
+  if (r1 == 0) {
+    if (tid == 0) {
+      dos[i] = 0.0;
+      if (ranks) {
+        ranks[i] = 0;
+        ranks[rank_stride + i] = 0;
+      }
+    }
+    return;
+  }
+
+  // 3a. T = K_Z^T U~ S~^-1/2 (n x r1, row stride r1, in the record's place): lane `row`
+  // reads column `row` of K_Z, contiguous across lanes, against GT_U eigenvectors at a
+  // time staged in LDS as ub[c][t] (read by all lanes at once).  (K_Z^T in place of K_Z
+  // changes B into B^T, which the symmetrisation below takes to the same matrix.)
+  __shared__ double ub[GE_MAX_NV * GT_U];
+  auto stage_u = [&](int a0) {
+    __syncthreads();  // the previous group is no longer read
+    for (int idx = tid; idx < GT_U * n; idx += GT_TH) {
+      const int t = idx / n, c = idx - t * n;
+      ub[c * GT_U + t] = a0 + t < r1 ? zt[(int64_t)sh.kidx[a0 + t] * ld + c] : 0.0;
+    }
+    __syncthreads();
+  };
+  for (int a0 = 0; a0 < r1; a0 += GT_U) {
+    stage_u(a0);
+    if (tid < n) {
+      const int row = tid;
+      double acc[GT_U] = {};
+#pragma unroll 2
+      for (int c = 0; c < n; ++c) {
+        const double kv = kz[(int64_t)c * n + row];
+#pragma unroll
+        for (int t = 0; t < GT_U; ++t) acc[t] += kv * ub[c * GT_U + t];
+      }
+#pragma unroll
+      for (int t = 0; t < GT_U; ++t)
+        if (a0 + t < r1) q[(int64_t)row * r1 + a0 + t] = acc[t] * sh.scale[a0 + t];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // 3b. B = S~^-1/2 U~^T T -> A (r1 x r1, row stride ld): lane b down column b of T
+  for (int a0 = 0; a0 < r1; a0 += GT_U) {
+    stage_u(a0);
+    if (tid < r1) {
+      const int b = tid;
+      double acc[GT_U] = {};
+#pragma unroll 2
+      for (int c = 0; c < n; ++c) {
+        const double tv = q[(int64_t)c * r1 + b];
+#pragma unroll
+        for (int t = 0; t < GT_U; ++t) acc[t] += ub[c * GT_U + t] * tv;
+      }
+#pragma unroll
+      for (int t = 0; t < GT_U; ++t)
+        if (a0 + t < r1) A[(int64_t)(a0 + t) * ld + b] = acc[t] * sh.scale[a0 + t];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int idx = tid; idx < r1 * r1; idx += GT_TH) {
+    const int a = idx / r1, b = idx - a * r1;
+    if (a < b) {
+      const double m = 0.5 * (A[(int64_t)a * ld + b] + A[(int64_t)b * ld + a]);
+      A[(int64_t)a * ld + b] = m;
+      A[(int64_t)b * ld + a] = m;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+
+  // eig(B): reduction, then bisection
+  tri_reduce(A, r1, ld, sh);
+  double glo = INFINITY, ghi = -INFINITY, e2max = 0.0;  // every lane: Gershgorin interval
+  for (int j = 0; j < r1; ++j) {
+    const double rad = (j > 0 ? fabs(sh.e[j - 1]) : 0.0) + (j + 1 < r1 ? fabs(sh.e[j]) : 0.0);
+    glo = fmin(glo, sh.d[j] - rad);
+    ghi = fmax(ghi, sh.d[j] + rad);
+  }
+  for (int j = 0; j + 1 < r1; ++j) e2max = fmax(e2max, sh.e[j] * sh.e[j]);
+  for (int j = tid; j + 1 < r1; j += GT_TH) sh.w[0][j] = sh.e[j] * sh.e[j];
+  __syncthreads();
+  for (int j = tid; j < r1; j += GT_TH) sh.s[j] = tri_bisect(j, r1, sh, glo, ghi, e2max);
+  __syncthreads();
+
+  // 4. range filter and trace, ascending order
+  if (tid == 0) {
+    const double hi = (1.0 + rho) * g_max;
+    double tr = 0.0;
+    int r2 = 0;
+    for (int j = 0; j < r1; ++j) {
+      const double xi = sh.s[j];
+      if (xi >= 0.0 && xi <= hi) {
+        tr += xi;
+        ++r2;
+      }
+    }
+    dos[i] = tr;
+    if (ranks) {
+      ranks[i] = r1;
+      ranks[rank_stride + i] = r2;
+    }
+  }
+}
+
 }  // namespace
 
 // Threads per point: the Jacobi rounds are latency-bound at one workgroup per CU, so the
@@ -637,13 +1359,32 @@ template <int TH>
 hipError_t launch_trace_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                           double rho, double* dos, int32_t* ranks, double* scratch, int nvh, const double* k_c,
                           const double* trw, double* hscr, const double* s_floor, int rank_stride, size_t lds,
-                          hipStream_t stream) {
+                          hipStream_t stream, int64_t scr_stride, const double* only) {
   hipError_t err = hipFuncSetAttribute((const void*)geneig_trace_kernel<TH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_trace_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho, dos,
-                     ranks, rank_stride, scratch, nvh, k_c, trw, hscr, s_floor);
+                     ranks, rank_stride, scratch, nvh, k_c, trw, hscr, s_floor, scr_stride, only);
   return hipGetLastError();
+}
+
+// The Jacobi kernel for the threads N_v takes.
+hipError_t launch_jacobi_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                               double rho, double* dos, int32_t* ranks, double* scratch, int nvh, const double* k_c,
+                               const double* trw, double* hscr, const double* s_floor, int rank_stride,
+                               hipStream_t stream, int64_t scr_stride, const double* only) {
+  const size_t lds = geneig_lds_bytes(nv);
+  switch (geneig_threads(nv)) {
+    case 256:
+      return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
+                                 s_floor, rank_stride, lds, stream, scr_stride, only);
+    case 512:
+      return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
+                                 s_floor, rank_stride, lds, stream, scr_stride, only);
+    default:
+      return launch_trace_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw,
+                                            hscr, s_floor, rank_stride, lds, stream, scr_stride, only);
+  }
 }
 
 hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
@@ -671,18 +1412,33 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
   if (rank_stride <= 0) rank_stride = ntb;
-  const size_t lds = geneig_lds_bytes(nv);
-  switch (geneig_threads(nv)) {
-    case 256:
-      return launch_trace_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
-                                 s_floor, rank_stride, lds, stream);
-    case 512:
-      return launch_trace_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr,
-                                 s_floor, rank_stride, lds, stream);
-    default:
-      return launch_trace_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw,
-                                            hscr, s_floor, rank_stride, lds, stream);
+  if (!geneig_tri_path(nv, nvh))
+    return launch_jacobi_trace(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, s_floor,
+                               rank_stride, stream, geneig_scratch_doubles(nv), nullptr);
+  // the tridiagonal path, kGeTriChunk points at a time through the same scratch
+  const int64_t stride = geneig_tri_point_doubles(nv);
+  const int64_t nn = (int64_t)nv * nv;
+  const size_t vec_lds = tri_vectors_lds_doubles(nv) * sizeof(double);
+  hipError_t err = hipFuncSetAttribute((const void*)geneig_tri_vectors_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)vec_lds);
+  if (err != hipSuccess) return err;
+  for (int i0 = 0; i0 < ntb; i0 += kGeTriChunk) {
+    const int np = std::min(kGeTriChunk, ntb - i0);
+    const double* kw = k_w + i0 * nn;
+    const double* kz = k_z + i0 * nn;
+    int32_t* rk = ranks ? ranks + i0 : nullptr;
+    const double* sf = s_floor ? s_floor + i0 : nullptr;
+    hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kw, scratch, stride);
+    hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
+    hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream, nv,
+                       np, scratch, stride);
+    hipLaunchKernelGGL(geneig_tri_trace_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, g_max, tau, rho, dos + i0,
+                       rk, rank_stride, scratch, stride, sf);
+    err = launch_jacobi_trace(nv, np, kw, kz, g_max, tau, rho, dos + i0, rk, scratch, 0, nullptr, nullptr, nullptr,
+                              sf, rank_stride, stream, stride, scratch + 6 * nn + 4 * nv);
+    if (err != hipSuccess) return err;
   }
+  return hipGetLastError();
 }
 
 }  // namespace ssm

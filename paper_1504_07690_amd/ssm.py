@@ -347,8 +347,10 @@ def geneig_trace(k_w: torch.Tensor, k_z: torch.Tensor, g_max, tau, rho, dos: tor
                  ranks: torch.Tensor | None = None):
     _require_cuda(k_w, k_z, dos, ranks)
     ntb, nv, _ = k_w.shape
-    per = nv * nv + (0 if nv <= 96 else nv * (nv + 1) if nv <= 128 else 2 * nv * (nv + 1))
-    scratch = torch.empty(ntb * per, dtype=torch.float64, device=k_w.device)
+    size = A.lib.ssm_geneig_trace_scratch_doubles(int(nv), int(ntb))
+    if size < 0:
+        raise ValueError(f"ssm_geneig_trace: unsupported nv={nv}, ntb={ntb}")
+    scratch = torch.empty(size, dtype=torch.float64, device=k_w.device)
     A.check(A.lib.ssm_geneig_trace(int(nv), int(ntb), _ptr(k_w), _ptr(k_z), float(g_max), float(tau), float(rho),
                                    _ptr(dos), _ptr(ranks), _ptr(scratch), _stream()), "ssm_geneig_trace")
     return scratch

@@ -218,6 +218,7 @@ def test_stage_calls_validate(A):
     assert A.lib.ssm_sweep(1, 100, 4, 8, 1, 6, 1, 1, 0, None) == A.SSM_ERR_ARG    # ldc < ntb
     assert A.lib.ssm_gram(1, 100, 260, 4, 1, 1, 1, 1, 1, 1, None) == A.SSM_ERR_UNSUPPORTED
     assert A.lib.ssm_geneig_trace(8, 4, 1, 1, -1.0, 1e-7, 1e-3, 1, None, 1, None) == A.SSM_ERR_ARG
+    assert A.lib.ssm_geneig_trace(300, 4, 1, 1, 1.0, 1e-7, 1e-3, 1, None, 1, None) == A.SSM_ERR_UNSUPPORTED
     assert A.lib.ssm_coefficients(1.0, -1.0, 0.1, 10, 1, 4, 10, 1, None, None) == A.SSM_ERR_ARG
     assert A.lib.ssm_gaussian_block(1, 10, 8, 3, 1, None) == A.SSM_ERR_ARG
     # split sweep: (e, kc, ntb, chi, clo, ldk, y, z, accumulate, k3, stream); every check runs
@@ -379,3 +380,18 @@ def test_box_stencil_workspace(A, nv, precision, lattice, grows):
         assert sizes[1] - sizes[0] >= n * 27 * es and sizes[1] - sizes[0] < n * 27 * es + 512
     else:
         assert sizes[1] == sizes[0]
+
+
+def test_geneig_trace_scratch_sizes(A):
+    """Algorithm 4's scratch: Jacobi matrices per point up to N_v = 128, then the
+    tridiagonal path's 6 n^2 + 8 n + 8 doubles per point for at most 2048 points."""
+    f = A.lib.ssm_geneig_trace_scratch_doubles
+    assert f(80, 10) == 10 * 80 * 80
+    assert f(96, 3) == 3 * 96 * 96
+    assert f(128, 5) == 5 * (128 * 128 + 128 * 129)
+    for nv in (129, 200, 256):
+        per = 6 * nv * nv + 8 * nv + 8
+        assert per >= nv * nv + 2 * nv * (nv + 1)   # the Jacobi redo of a point fits its share
+        assert f(nv, 7) == 7 * per
+        assert f(nv, 2048) == f(nv, 4000) == 2048 * per
+    assert f(0, 4) == f(257, 4) == f(8, 0) == -1

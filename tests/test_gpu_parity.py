@@ -342,6 +342,60 @@ def test_geneig_workload_pencils(S):
     assert np.array_equal(rk[: pts.size], res["r1"]) and np.array_equal(rk[pts.size:], res["r2"])
 
 
+def _theorem3_pencils(rng, count, n, r, nv):
+    """K_W, K_Z of Theorem 3 pencils: exact low-rank PSD P (rank r), W Gaussian."""
+    kws, kzs = [], []
+    for _ in range(count):
+        u, _ = np.linalg.qr(rng.standard_normal((n, r)))
+        s = rng.uniform(0.001, 0.01, r)
+        w = rng.standard_normal((n, nv))
+        kw, kz = O.gram(w, (u * s) @ (u.T @ w))
+        kws.append(kw)
+        kzs.append(kz)
+    return np.array(kws), np.array(kzs)
+
+
+def test_geneig_tridiagonal_path_redoes_a_stopped_point(S):
+    """Above N_v = 128 a point whose QL stops (here: NaN in K_W, so no block ever splits)
+    is redone by the Jacobi kernel, and only that point: its outputs are written (by
+    Jacobi, which stops at once on a NaN norm and proceeds from the unrotated diagonal),
+    the others match the oracle."""
+    kw, kz = _theorem3_pencils(_rng(11), 3, 400, 60, 160)
+    kw[1, 5, 7] = np.nan
+    dos = torch.full((3,), 12345.0, dtype=torch.float64, device=DEV)
+    ranks = torch.full((6,), -7, dtype=torch.int32, device=DEV)
+    S.geneig_trace(torch.tensor(kw, device=DEV), torch.tensor(kz, device=DEV), 0.008, 1e-7, 1e-3, dos, ranks)
+    d, rk = dos.cpu().numpy(), ranks.cpu().numpy()
+    assert d[1] != 12345.0 and rk[1] != -7 and rk[4] != -7
+    for i in (0, 2):
+        ref, r1, r2 = O.geneig_trace(kw[i], kz[i], 0.008, 1e-7, 1e-3)
+        assert abs(d[i] - ref) <= 1e-10 * 0.008
+        assert [rk[i], rk[3 + i]] == [r1, r2]
+
+
+def test_geneig_tridiagonal_path_launch_groups(S):
+    """2100 points at N_v = 136: two launch groups of the tridiagonal path (2048 points
+    each) through one scratch; points on both sides of the boundary against the oracle."""
+    ntb, nv = 2100, 136
+    rng = _rng(12)
+    base_w, base_z = _theorem3_pencils(rng, 4, 300, 40, nv)
+    # every point a distinct pencil: the four bases scaled, so each point's answer is known
+    scale = 1.0 + 0.25 * (np.arange(ntb) % 7)
+    kw = torch.tensor(base_w[np.arange(ntb) % 4] * scale[:, None, None], device=DEV)
+    kz = torch.tensor(base_z[np.arange(ntb) % 4] * scale[:, None, None], device=DEV)
+    dos = torch.empty(ntb, dtype=torch.float64, device=DEV)
+    ranks = torch.empty(2 * ntb, dtype=torch.int32, device=DEV)
+    S.geneig_trace(kw, kz, 0.008, 1e-7, 1e-3, dos, ranks)
+    d, rk = dos.cpu().numpy(), ranks.cpu().numpy()
+    for i in (0, 1, 2046, 2047, 2048, 2049, 2099):
+        ref, r1, r2 = O.geneig_trace(kw[i].cpu().numpy(), kz[i].cpu().numpy(), 0.008, 1e-7, 1e-3)
+        assert abs(d[i] - ref) <= 1e-10 * 0.008, i
+        assert [rk[i], rk[ntb + i]] == [r1, r2], i
+    # a pencil scaled by c has the same generalised eigenvalues: points agree with their base
+    for i in range(ntb):
+        assert abs(d[i] - d[i % 28]) <= 1e-10 * 0.008, i
+
+
 # ----------------------------------------------------------------------------
 # End to end (Algorithm 5 through ssm_create / ssm_dos)
 # ----------------------------------------------------------------------------
