@@ -421,7 +421,7 @@ ssm_status ssm_gram_noalloc(int32_t precision, int64_t n, int32_t nv, int32_t nt
  * (k_w[i] taken as its symmetric part), keep s_j >= tau max_j s_j (nothing if
  * max s <= 0), B = S~^-1/2 U~^T k_z[i] U~ S~^-1/2, eig(B) = xi, dos[i] = sum of xi
  * in [0, (1 + rho) g_max]; ranks[i] = r1, ranks[ntb + i] = r2 (ranks may be NULL).
- * All in FP64: cyclic Jacobi for nv <= 128; above, a Householder reduction to
+ * All in FP64: cyclic Jacobi for nv <= 48; above, a Householder reduction to
  * tridiagonal form, implicit QL for eig(k_w[i]) and bisection for eig(B) (a point
  * whose QL iterations run past their limit is redone by Jacobi).  k_w, k_z: ntb
  * row-major nv x nv FP64 matrices on the device; dos_dev: ntb doubles, ranks_dev:
@@ -432,9 +432,9 @@ ssm_status ssm_gram_noalloc(int32_t precision, int64_t n, int32_t nv, int32_t nt
 ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const double* k_z, double g_max,
                             double tau, double rho, double* dos_dev, int32_t* ranks_dev, double* scratch,
                             void* stream);
-/* Scratch of ssm_geneig_trace in doubles: ntb nv^2 for nv <= 96, ntb (nv^2 + nv(nv+1))
- * for 96 < nv <= 128, min(ntb, 2048) (6 nv^2 + 8 nv + 8) above (the tridiagonal
- * path runs 2048 points at a time).  -1 for nv outside [1, 256] or ntb < 1. */
+/* Scratch of ssm_geneig_trace in doubles: ntb nv^2 for nv <= 48, min(ntb, 2048)
+ * (6 nv^2 + 8 nv + 8) above (the tridiagonal path runs 2048 points at a time).  -1 for
+ * nv outside [1, 256] or ntb < 1. */
 int64_t ssm_geneig_trace_scratch_doubles(int32_t nv, int32_t ntb);
 
 #ifdef __cplusplus

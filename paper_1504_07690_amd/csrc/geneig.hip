@@ -1,18 +1,22 @@
 // Algorithm 4 (truncated generalised eigenvalue problem) and the trace of
-// Algorithm 5 (step 13), one workgroup per sweep point, in FP64:
+// Algorithm 5 (step 13), per sweep point, in FP64:
 //
-//   1. W^T Z = U S U^T                     (cyclic Jacobi, eigenvectors kept)
+//   1. W^T Z = U S U^T                     (eigenvectors kept)
 //   2. keep s_j >= tau max_i s_i            (nothing kept, trace 0, if max s <= 0)
-//   3. B = S~^-1/2 U~^T (Z^T Z) U~ S~^-1/2,  eig(B) = xi   (Jacobi, values only)
+//   3. B = S~^-1/2 U~^T (Z^T Z) U~ S~^-1/2,  eig(B) = xi   (values only)
 //   4. keep xi in [0, (1 + rho) g_max], g_max = 1/(N sqrt(2 pi sigma^2))
 //   trace = sum of kept xi, r1 = |kept s|, r2 = |kept xi|.
 //
-// Jacobi: parallel cyclic sweeps in round-robin (tournament) order, so each round
+// Two eigensolvers.  The trace without the hybrid term, N_v > 48, goes through a
+// tridiagonal matrix (Householder reduction; implicit QL for step 1, bisection for step
+// 3), in four kernels per group of points (see geneig_tri_*).  Below that, with the
+// hybrid term of Algorithm 6, and in the backward kernel, one workgroup per point runs
+// parallel cyclic Jacobi: sweeps in round-robin (tournament) order, so each round
 // rotates N_v/2 disjoint index pairs at once: the pair angles are computed first
 // (Golub & Van Loan, symmetric 2x2 Schur), then the rows of every pair are rotated,
 // then the columns (and the eigenvector columns).  The pivot entries are set to
 // exactly zero.  A sweep starts only while off(A)_F > 1e-14 ||A||_F.
-// The matrix and its eigenvectors live in LDS for N_v <= 96 (2 * 96 * 97 doubles), the
+// Jacobi's matrix and eigenvectors live in LDS for N_v <= 96 (2 * 96 * 97 doubles), the
 // matrix alone up to N_v = 128 (eigenvectors in the point's global scratch), both in
 // global scratch above that (N_v <= 256); the N_v x r1 product
 // Z^T Z U~ S~^-1/2 goes through the same per-point scratch.
@@ -614,21 +618,21 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
 
 
 // ---------------------------------------------------------------------------
-// N_v above GE_TRI_NV, trace only (no hybrid correction): the two symmetric
-// eigenproblems go through a tridiagonal matrix instead of Jacobi sweeps, whose
-// cost there is the traffic of rotating two N_v x N_v matrices in global scratch
-// once per round.
-//   a. Householder reduction Q^T K Q = T (T tridiagonal: d on the diagonal, e[i]
-//      coupling i and i + 1), the reflectors kept in the rows of the reduced matrix;
-//   b. for K_W: Q by backward accumulation of the reflectors, stored transposed, then
-//      implicit QL with Wilkinson shifts on T; each QL iteration's plane rotations
-//      are applied to the rows of Z = Q (one lane per row, the rows of Q^T read
-//      contiguously across lanes), so Z ends as the eigenvectors, row j of the
-//      transposed array being eigenvector j (the layout of the Jacobi path);
-//   c. for B: eigenvalues only, by bisection on the Sturm counts of T, one lane per
-//      eigenvalue index.
-// Scratch per point (geneig_scratch_doubles, all row stride n): Q and then the n x r1
-// product at 0, the matrix being reduced at n^2, Z^T at n^2 + n (n + 1).
+// N_v above 48, trace only (no hybrid term): the two symmetric eigenproblems go through
+// a tridiagonal matrix.  (Jacobi there pays for rotating whole N_v x N_v matrices once
+// per round; the reduction reads the trailing block once per column instead.)
+//   a. geneig_tri_reduce_kernel: Householder reduction Q^T K_W Q = T (T tridiagonal: d
+//      on the diagonal, e[i] coupling i and i + 1), the reflectors kept in the rows of
+//      the reduced matrix;
+//   b. geneig_tri_ql_kernel: implicit QL with Wilkinson shifts on T, one lane per point,
+//      its plane rotations recorded in order (Y = their product: T = Y S Y^T);
+//   c. geneig_tri_vectors_kernel: U = Q Y row by row, 64 rows per workgroup in LDS, from
+//      the reflectors and the record; row j of the transposed array is eigenvector j
+//      (the layout of the Jacobi path);
+//   d. geneig_tri_trace_kernel: truncation, B, its reduction (as in a), its eigenvalues
+//      by bisection on the Sturm counts, one lane per eigenvalue, and the trace.
+// A point whose QL runs past its iteration or record limit is redone by the Jacobi
+// kernel, which skips the others.
 // ---------------------------------------------------------------------------
 constexpr int GT_TH = 256;           // one lane per matrix row or column (n <= 256)
 constexpr int GT_MAX_QL = 30;        // QL iterations allowed per eigenvalue, on average

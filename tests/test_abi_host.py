@@ -383,13 +383,12 @@ def test_box_stencil_workspace(A, nv, precision, lattice, grows):
 
 
 def test_geneig_trace_scratch_sizes(A):
-    """Algorithm 4's scratch: Jacobi matrices per point up to N_v = 128, then the
+    """Algorithm 4's scratch: the Jacobi products per point up to N_v = 48, then the
     tridiagonal path's 6 n^2 + 8 n + 8 doubles per point for at most 2048 points."""
     f = A.lib.ssm_geneig_trace_scratch_doubles
-    assert f(80, 10) == 10 * 80 * 80
-    assert f(96, 3) == 3 * 96 * 96
-    assert f(128, 5) == 5 * (128 * 128 + 128 * 129)
-    for nv in (129, 200, 256):
+    assert f(40, 10) == 10 * 40 * 40
+    assert f(48, 3) == 3 * 48 * 48
+    for nv in (49, 80, 128, 129, 200, 256):
         per = 6 * nv * nv + 8 * nv + 8
         assert per >= nv * nv + 2 * nv * (nv + 1)   # the Jacobi redo of a point fits its share
         assert f(nv, 7) == 7 * per

@@ -356,7 +356,7 @@ def _theorem3_pencils(rng, count, n, r, nv):
 
 
 def test_geneig_tridiagonal_path_redoes_a_stopped_point(S):
-    """Above N_v = 128 a point whose QL stops (here: NaN in K_W, so no block ever splits)
+    """Above N_v = 48 a point whose QL stops (here: NaN in K_W, so no block ever splits)
     is redone by the Jacobi kernel, and only that point: its outputs are written (by
     Jacobi, which stops at once on a NaN norm and proceeds from the unrotated diagonal),
     the others match the oracle."""
