@@ -910,12 +910,25 @@ __global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __res
   int64_t pos = 0;
   int l = 0, iters = 0, nrec = 0;
   bool ok = true;
+  // first m >= from with |e_m| <= eps (|d_m| + |d_m+1|), n - 1 if none (e_{n-1} = 0): the
+  // entries are read GT_U at a time (clamped to the arrays), then tested in order
+  auto split_at = [&](int from) {
+    for (int m0 = from; m0 < n - 1; m0 += GT_U) {
+      double ev[GT_U], dv[GT_U + 1];
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u) ev[u] = e[min(m0 + u, n - 1)];
+#pragma unroll
+      for (int u = 0; u <= GT_U; ++u) dv[u] = d[min(m0 + u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < GT_U; ++u)
+        if (m0 + u >= n - 1 || fabs(ev[u]) <= GT_EPS * (fabs(dv[u]) + fabs(dv[u + 1]))) return min(m0 + u, n - 1);
+    }
+    return n - 1;
+  };
   for (;;) {
     int mm = -1;
     while (l < n) {
-      int m = l;
-      for (; m < n - 1; ++m)
-        if (fabs(e[m]) <= GT_EPS * (fabs(d[m]) + fabs(d[m + 1]))) break;
+      const int m = l < n - 1 ? split_at(l) : l;
       if (m == l) {
         ++l;
         continue;
@@ -936,7 +949,7 @@ __global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __res
     int i = mm - 1;
     double ei = e[i], di = d[i], di1 = d[i + 1];  // entries the step reads, loaded one step ahead
     for (; i >= l; --i) {
-      const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? d[i - 1] : 0.0;
+      const double en = e[i > 0 ? i - 1 : 0], dn = d[i > 0 ? i - 1 : 0];  // unconditional loads
       const double f = s * ei, b = c * ei;
       const double ss = f * f + g * g;
       if (ss == 0.0) {  // the block splits at i + 1: drop the shift and redo the block
