@@ -185,6 +185,44 @@ def machine_rates(torch, dev):
     return out
 
 
+def geneig_scaling(S, torch, dev, cases=((80, 2048), (128, 2048), (256, 2048))):
+    """Algorithm 4 alone (ssm_geneig_trace), N_t = 2048 points (one launch group of the
+    tridiagonal path), on seeded pencils K_W = G^T G, K_Z = 1e-4 H^T H with G, H Gaussian
+    (3 N_v x N_v per point), range bound 1: ms per 1000 points, best of 3 launches."""
+    out = {}
+    gen = torch.Generator(device=dev)
+    for nv, ntb in cases:
+        gen.manual_seed(1000 + nv)
+        kw = torch.empty(ntb, nv, nv, dtype=torch.float64, device=dev)
+        kz = torch.empty_like(kw)
+        for i0 in range(0, ntb, 256):  # in slices, to bound the temporaries
+            k = min(256, ntb - i0)
+            g = torch.randn(k, 3 * nv, nv, dtype=torch.float64, device=dev, generator=gen)
+            kw[i0:i0 + k] = torch.bmm(g.transpose(1, 2).contiguous(), g)
+            h = torch.randn(k, 3 * nv, nv, dtype=torch.float64, device=dev, generator=gen)
+            kz[i0:i0 + k] = 1e-4 * torch.bmm(h.transpose(1, 2).contiguous(), h)
+            del g, h
+        dos = torch.empty(ntb, dtype=torch.float64, device=dev)
+        ranks = torch.empty(2 * ntb, dtype=torch.int32, device=dev)
+        S.geneig_trace(kw, kz, 1.0, 1e-7, 1e-3, dos, ranks)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S.geneig_trace(kw, kz, 1.0, 1e-7, 1e-3, dos, ranks)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[f"nv{nv}"] = {"points": ntb, "ms_per_1000_points": min(ts) * 1000 / ntb,
+                          "path": "tridiagonal" if nv > 48 else "jacobi",
+                          "mean_r1": float(ranks[:ntb].double().mean()), "mean_r2": float(ranks[ntb:].double().mean())}
+        log(f"Algorithm 4, N_v = {nv}: {out[f'nv{nv}']['ms_per_1000_points']:.1f} ms per 1000 points")
+        del kw, kz
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline_small():
     """The oracle's whole SS-DGC on the 32 x 32 random Laplacian (N = 1024, N_v = 40, M = 200,
     N_t = 200) on one host thread, the paper's setting: seconds and the estimate."""
@@ -240,6 +278,8 @@ def main():
     ap.add_argument("--no-ress", action="store_true", help="skip the RESS-DGC runs (Algorithm 7)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the random-graph DOS and the 27-point recurrence rate")
+    ap.add_argument("--only-geneig", action="store_true",
+                    help="time Algorithm 4 alone at N_v = 80, 128, 256 and print that JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -252,7 +292,7 @@ def main():
     # the oracle's baseline first: its process pool forks before anything touches the GPU
     baseline = None
     oracle_small = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_geneig:
         log("timing the oracle on a bounded sample on the host cores ...")
         t0 = time.time()
         baseline = cpu_baseline(2)
@@ -274,6 +314,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
+    if args.only_geneig:
+        print(json.dumps({"geneig": geneig_scaling(S, torch, dev)}), flush=True)
+        return
     t0 = time.time()
     wl = WL.make_workload(2)
     log(f"workload {wl.name}: n={wl.a.n} nnz={wl.a.nnz} nv={wl.nv} M={wl.degree} nt={wl.nt} "
@@ -445,6 +488,7 @@ def main():
     if not args.no_large:
         out["large"] = large_workloads(S, WL, torch, dev, budget_left)
     if not args.no_large:
+        out["geneig"] = geneig_scaling(S, torch, dev)
         out["small"] = small_workload(S, WL, torch, dev, oracle_small)
         out["machine"] = machine_rates(torch, dev)
         log(f"32^2 workload: {out['small']}; machine: {out['machine']}")
