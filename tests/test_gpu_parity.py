@@ -311,6 +311,17 @@ def _geneig_cases():
     # degenerate: negative definite K_W (nothing kept), zero matrices
     cases.append((-np.eye(8), np.eye(8), 0.01))
     cases.append((np.zeros((4, 4)), np.zeros((4, 4)), 0.01))
+    # the same above N_v = 48 (the tridiagonal path), and: K_W = I (every eigenvalue equal, T
+    # already diagonal, no QL iteration) with K_Z diagonal, some entries above the range
+    # bound; a rank-32 K_W of 64 columns (32 duplicated: a cluster of zero eigenvalues)
+    cases.append((-np.eye(64), np.eye(64), 0.01))
+    cases.append((np.zeros((64, 64)), np.zeros((64, 64)), 0.01))
+    cases.append((np.eye(64), np.diag(rng.uniform(0.0, 0.02, 64)), 0.01))
+    w = rng.standard_normal((300, 32))
+    w = np.concatenate([w, w], axis=1)
+    u, _ = np.linalg.qr(rng.standard_normal((300, 20)))
+    kw, kz = O.gram(w, (u * rng.uniform(0.001, 0.01, 20)) @ (u.T @ w))
+    cases.append((kw, kz, 0.008))
     return cases
 
 
