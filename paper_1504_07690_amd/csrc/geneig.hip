@@ -645,8 +645,6 @@ struct TriShared {
   double tau[GE_MAX_NV];
   double v[2][GE_MAX_NV];  // this step's reflector and the next one's
   double w[2][GE_MAX_NV];  // this step's w and the next step's p
-  double cs[GE_MAX_NV];
-  double sn[GE_MAX_NV];
   double s[GE_MAX_NV];
   double scale[GE_MAX_NV];
   double red[GT_TH / 64];
