@@ -280,7 +280,7 @@ __device__ void jacobi_for(const GeShared& sh, double* V, int m, int ld, int nv)
 }
 
 // Point i's scratch starts at scratch + i scr_stride.  With `only` set, point i is
-// skipped unless only[i scr_stride] is nonzero (the points the tridiagonal path gave up).
+// skipped unless only[i scr_stride] is 1 (the points the tridiagonal path gave up).
 // With nvh > 0 (Algorithm 6 / 7 with N~_v = nvh columns of W~) the point also gets the
 // hybrid correction (Tr K_W~ - ||K_C C~||_F^2) / N~_v, C~ = U~ S~^-1/2 Q~ with Q~ the
 // eigenvectors of step 3 that pass step 4: G = K_C U~ S~^-1/2 (N~_v x r1, in hscr) is
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t nn = (int64_t)n * n;
-  if (only && only[i * scr_stride] == 0.0) return;  // a point the tridiagonal path finished
+  if (only && only[i * scr_stride] != 1.0) return;  // a point the tridiagonal path finished
   const double* kw = k_w + i * nn;
   const double* kz = k_z + i * nn;
   double* tmat = scratch + i * scr_stride;
@@ -450,8 +450,9 @@ __global__ void __launch_bounds__(TH) geneig_trace_kernel(int nv, const double* 
 //   dphi/dK_W = U (Gamma o (Kt D P + P D Kt)) U^T      (Daleckii-Krein),
 // Gamma_jk = (F(s_j) - F(s_k)) / (s_j - s_k), Gamma_jj = F'(s_j) = -s_j^-3/2 / 2 on
 // the kept set; kept/kept entries are -1/(sqrt s_j sqrt s_k (sqrt s_j + sqrt s_k)).
-// Both are scaled by phibar[i].  Scratch per point: 3 N_v x N_v doubles
-// (U, Kt, and one product).
+// Both are scaled by phibar[i].  Scratch per point (at scratch + i scr_stride): 3 N_v x N_v
+// doubles (U, Kt, and one product), plus the Jacobi matrices above N_v = 96.  With `only`
+// set, point i is skipped unless only[i scr_stride] is 1.
 template <int TH>
 __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const double* __restrict__ k_w,
                                                                      const double* __restrict__ k_z, double g_max,
@@ -460,16 +461,19 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
                                                                      double* __restrict__ kw_bar,
                                                                      double* __restrict__ kz_bar,
                                                                      double* __restrict__ scratch,
-                                                                     const double* __restrict__ s_floor) {
+                                                                     const double* __restrict__ s_floor,
+                                                                     int64_t scr_stride,
+                                                                     const double* __restrict__ only) {
   extern __shared__ double lds[];
   const int n = nv;
   const int ld = n + 1;
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t nn = (int64_t)n * n;
+  if (only && only[i * scr_stride] != 1.0) return;  // a point the tridiagonal path finished
   const double* kw = k_w + i * nn;
   const double* kz = k_z + i * nn;
-  double* ug = scratch + i * (int64_t)geneig_backward_scratch_doubles(nv);  // U
+  double* ug = scratch + i * scr_stride;  // U
   double* ktg = ug + nn;                                                    // Kt = U^T K_Z U
   double* tg = ug + 2 * nn;                                                 // products
   GeShared sh;
@@ -855,20 +859,23 @@ struct TriPoint {
 constexpr int GT_REC_NN = 4;   // rotation record capacity, in doubles per n^2
 constexpr int GT_REC_IT = 4;   // recorded iterations allowed, per n (about 2 n are taken)
 
-// a. The symmetric part of K_W reduced to tridiagonal form.
+// a. The symmetric part of K_W reduced to tridiagonal form (k_w null: the matrix already in
+// the point's scratch).
 __global__ void __launch_bounds__(GT_TH) geneig_tri_reduce_kernel(int nv, const double* __restrict__ k_w,
                                                                   double* __restrict__ scratch, int64_t stride) {
   __shared__ TriShared sh;
   const int n = nv;
   const int tid = threadIdx.x;
-  const double* kw = k_w + blockIdx.x * (int64_t)n * n;
+  const double* kw = k_w ? k_w + blockIdx.x * (int64_t)n * n : nullptr;
   TriPoint pt(scratch + blockIdx.x * stride, n);
-  for (int idx = tid; idx < n * n; idx += GT_TH) {
-    const int r = idx / n, c = idx - r * n;
-    pt.a[idx] = 0.5 * (kw[idx] + kw[(int64_t)c * n + r]);
+  if (k_w) {  // null: the matrix is already in place (the backward's padded B)
+    for (int idx = tid; idx < n * n; idx += GT_TH) {
+      const int r = idx / n, c = idx - r * n;
+      pt.a[idx] = 0.5 * (kw[idx] + kw[(int64_t)c * n + r]);
+    }
+    __threadfence_block();
+    __syncthreads();
   }
-  __threadfence_block();
-  __syncthreads();
   tri_reduce(pt.a, n, n, sh);
   for (int j = tid; j < n; j += GT_TH) {
     pt.d[j] = sh.d[j];
@@ -1344,6 +1351,243 @@ __global__ void __launch_bounds__(GT_TH) geneig_tri_trace_kernel(int nv, const d
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Backward of Algorithm 4 on the tridiagonal path (N_v > 48), per group of points:
+//   a-c on K_W as in the forward path (U, S);
+//   geneig_tri_bwd_form_kernel: truncation (F(s) = s^-1/2 kept, 0 dropped), U saved,
+//     Kt = U^T K_Z U, and B = D Kt D on the kept set, padded to N_v x N_v with -1 on the
+//     padding's diagonal (outside [0, (1 + rho) g_max], so those eigenpairs never enter
+//     the projector; the padding stays a separate block through the reduction);
+//   a-c on the padded B (reduced in place): its eigenvalues xi and eigenvectors Q;
+//   geneig_tri_bwd_finish_kernel: P = sum over in-range xi of q q^T (U coordinates),
+//     M1 = Gamma o (Kt D P + P D Kt), M2 = D P D, and kw_bar, kz_bar = phibar U M U^T
+//     (the formulas of geneig_backward_kernel).
+// A point whose QL stops in either run is redone by geneig_backward_kernel.
+// Per-point scratch: the forward path's, then U^T, Kt, F(s), s, the kept indices and
+// the point's state (0: on the path, 1: to be redone, 2: done).
+// ---------------------------------------------------------------------------
+struct TriBwd {
+  double* ut;   // U^T: row j = eigenvector j of K_W
+  double* kt;   // Kt
+  double* f;    // F(s_j)
+  double* s;    // s_j
+  int* kidx;    // kept indices, r1 of them
+  double* state;
+  double* r1;
+  __device__ TriBwd(double* base, int n) {
+    const int64_t nn = (int64_t)n * n;
+    ut = base + geneig_tri_point_doubles(n);
+    kt = ut + nn;
+    f = kt + nn;
+    s = f + n;
+    kidx = (int*)(s + n);
+    state = s + 2 * n;
+    r1 = state + 1;
+  }
+};
+
+// R(r, c) = sum_q X(r, q) Y[q][c] for r < rows, c < cols (<= GT_TH), q < kdim: lane c down
+// column c of Y (row-major, contiguous across lanes) against GT_U rows of X at a time,
+// staged in LDS as ub[q][t] and read there by every lane at once.  x_at(r, q) gives X;
+// X_T says X(r, q) sits at q * ld + r (staged with r fastest) rather than r * ld + q.
+template <bool X_T, typename XF, typename OUT>
+__device__ __forceinline__ void gt_gemm(int rows, int cols, int kdim, XF x_at, const double* Y, int64_t ldy,
+                                        double* ub, OUT out) {
+  const int tid = threadIdx.x;
+  for (int r0 = 0; r0 < rows; r0 += GT_U) {
+    __syncthreads();  // the previous group is no longer read
+    for (int idx = tid; idx < GT_U * kdim; idx += GT_TH) {
+      int t, q;
+      if (X_T) {
+        t = idx % GT_U;
+        q = idx / GT_U;
+      } else {
+        t = idx / kdim;
+        q = idx - t * kdim;
+      }
+      ub[q * GT_U + t] = r0 + t < rows ? x_at(r0 + t, q) : 0.0;
+    }
+    __syncthreads();
+    if (tid < cols) {
+      double acc[GT_U] = {};
+#pragma unroll 2
+      for (int q = 0; q < kdim; ++q) {
+        const double y = Y[(int64_t)q * ldy + tid];
+#pragma unroll
+        for (int t = 0; t < GT_U; ++t) acc[t] += ub[q * GT_U + t] * y;
+      }
+#pragma unroll
+      for (int t = 0; t < GT_U; ++t)
+        if (r0 + t < rows) out(r0 + t, tid, acc[t]);
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(GT_TH) geneig_tri_bwd_form_kernel(int nv, const double* __restrict__ k_z,
+                                                                    double tau, const double* __restrict__ phibar,
+                                                                    double* __restrict__ kw_bar,
+                                                                    double* __restrict__ kz_bar,
+                                                                    double* __restrict__ scratch, int64_t stride,
+                                                                    const double* __restrict__ s_floor) {
+  __shared__ double ub[GE_MAX_NV * GT_U];
+  __shared__ int misc[2];
+  const int n = nv;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  const double* kz = k_z + i * nn;
+  TriPoint pt(scratch + i * stride, n);
+  TriBwd bw(scratch + i * stride, n);
+  if (pt.status[0] != 0.0) {  // QL on K_W stopped
+    if (tid == 0) *bw.state = 1.0;
+    return;
+  }
+  // truncation, as in the forward path
+  if (tid == 0) {
+    double smax = -INFINITY;
+    for (int j = 0; j < n; ++j) smax = fmax(smax, pt.eig[j]);
+    const double thr = s_floor ? fmax(tau * smax, s_floor[i]) : tau * smax;
+    int r1 = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = pt.eig[j];
+      const bool keep = smax > 0.0 && sj >= thr;
+      bw.s[j] = sj;
+      bw.f[j] = keep ? 1.0 / sqrt(sj) : 0.0;
+      if (keep) bw.kidx[r1++] = j;
+    }
+    *bw.r1 = r1;
+    misc[0] = r1;
+  }
+  __syncthreads();
+  const int r1 = misc[0];
+  if (r1 == 0 || phibar[i] == 0.0) {
+    for (int idx = tid; idx < n * n; idx += GT_TH) {
+      kw_bar[i * nn + idx] = 0.0;
+      kz_bar[i * nn + idx] = 0.0;
+    }
+    if (tid == 0) *bw.state = 2.0;
+    return;
+  }
+  if (tid == 0) *bw.state = 0.0;
+  for (int idx = tid; idx < n * n; idx += GT_TH) bw.ut[idx] = pt.zt[idx];
+  __threadfence_block();
+  __syncthreads();
+  // S1^T = (U^T K_Z)^T into the record's place: S1[b][q] = sum_p U[p][b] K_Z[p][q]
+  double* s1t = pt.rec;
+  gt_gemm<false>(
+      n, n, n, [&](int b, int p) { return bw.ut[(int64_t)b * n + p]; }, kz, n, ub,
+      [&](int b, int q, double v) { s1t[(int64_t)q * n + b] = v; });
+  // Kt^T[b][a] = sum_r U[r][b] S1[a][r]; stored as it comes (symmetrised next)
+  gt_gemm<false>(
+      n, n, n, [&](int b, int r) { return bw.ut[(int64_t)b * n + r]; }, s1t, n, ub,
+      [&](int b, int a, double v) { bw.kt[(int64_t)b * n + a] = v; });
+  for (int idx = tid; idx < n * n; idx += GT_TH) {
+    const int a = idx / n, b = idx - a * n;
+    if (a < b) {
+      const double m = 0.5 * (bw.kt[(int64_t)a * n + b] + bw.kt[(int64_t)b * n + a]);
+      bw.kt[(int64_t)a * n + b] = m;
+      bw.kt[(int64_t)b * n + a] = m;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // the padded B into the reduction's place
+  for (int idx = tid; idx < n * n; idx += GT_TH) {
+    const int a = idx / n, b = idx - a * n;
+    double v;
+    if (a < r1 && b < r1) {
+      const int ka = bw.kidx[a], kb = bw.kidx[b];
+      v = bw.f[ka] * bw.kt[(int64_t)ka * n + kb] * bw.f[kb];
+    } else {
+      v = a == b ? -1.0 : 0.0;
+    }
+    pt.a[idx] = v;
+  }
+}
+
+__global__ void __launch_bounds__(GT_TH) geneig_tri_bwd_finish_kernel(int nv, double g_max, double rho,
+                                                                      const double* __restrict__ phibar,
+                                                                      double* __restrict__ kw_bar,
+                                                                      double* __restrict__ kz_bar,
+                                                                      double* __restrict__ scratch, int64_t stride) {
+  __shared__ double ub[GE_MAX_NV * GT_U];
+  const int n = nv;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  TriPoint pt(scratch + i * stride, n);
+  TriBwd bw(scratch + i * stride, n);
+  if (*bw.state != 0.0) return;  // redone by Jacobi, or done
+  if (pt.status[0] != 0.0) {     // QL on B stopped
+    if (tid == 0) *bw.state = 1.0;
+    return;
+  }
+  const int r1 = (int)*bw.r1;
+  const double hi = (1.0 + rho) * g_max;
+  const double pb = phibar[i];
+  double* kwb = kw_bar + i * nn;
+  double* kzb = kz_bar + i * nn;
+  const double* q = pt.zt;   // eigenvector j of B in row j (entries a < r1)
+  double* pu = pt.rec;       // P in U coordinates
+  double* m1 = pt.a;         // Kt D P, then M1
+  double* tt = pt.zt;        // M U^T once Q is spent
+  for (int idx = tid; idx < n * n; idx += GT_TH) pu[idx] = 0.0;
+  __threadfence_block();
+  __syncthreads();
+  // P[ka][kb] = sum over in-range j of q_j[a] q_j[b], a, b < r1
+  gt_gemm<true>(
+      r1, r1, n,
+      [&](int a, int j) {
+        const double xi = pt.eig[j];
+        return xi >= 0.0 && xi <= hi ? q[(int64_t)j * n + a] : 0.0;
+      },
+      q, n, ub, [&](int a, int b, double v) { pu[(int64_t)bw.kidx[a] * n + bw.kidx[b]] = v; });
+  // Kt D P
+  gt_gemm<false>(
+      n, n, n, [&](int j, int c) { return bw.kt[(int64_t)j * n + c] * bw.f[c]; }, pu, n, ub,
+      [&](int j, int k, double v) { m1[(int64_t)j * n + k] = v; });
+  // M1 = Gamma o (X + X^T), Gamma the divided differences of F
+  for (int idx = tid; idx < n * n; idx += GT_TH) {
+    const int j = idx / n, k = idx - j * n;
+    if (j > k) continue;
+    const double sj = bw.s[j], sk = bw.s[k], fj = bw.f[j], fk = bw.f[k];
+    const bool kj = fj != 0.0, kk = fk != 0.0;
+    double g;
+    if (j == k) {
+      g = kj ? -0.5 * fj * fj * fj : 0.0;
+    } else if (kj && kk) {
+      const double qj = sqrt(sj), qk = sqrt(sk);
+      g = -1.0 / (qj * qk * (qj + qk));
+    } else if (kj || kk) {
+      g = (fj - fk) / (sj - sk);
+    } else {
+      g = 0.0;
+    }
+    const double h = m1[(int64_t)j * n + k] + m1[(int64_t)k * n + j];
+    m1[(int64_t)j * n + k] = g * h;
+    m1[(int64_t)k * n + j] = g * h;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // kw_bar = phibar U M1 U^T: (M1 U^T)[q][r] = sum_c M1[q][c] U[r][c], then U (M1 U^T)
+  gt_gemm<false>(
+      n, n, n, [&](int r, int c) { return m1[(int64_t)r * n + c]; }, bw.ut, n, ub,
+      [&](int r, int c, double v) { tt[(int64_t)r * n + c] = v; });
+  gt_gemm<true>(
+      n, n, n, [&](int r, int c) { return bw.ut[(int64_t)c * n + r]; }, tt, n, ub,
+      [&](int r, int c, double v) { kwb[(int64_t)r * n + c] = pb * v; });
+  // kz_bar = phibar U M2 U^T, M2 = D P D
+  gt_gemm<false>(
+      n, n, n, [&](int r, int c) { return bw.f[r] * pu[(int64_t)r * n + c] * bw.f[c]; }, bw.ut, n, ub,
+      [&](int r, int c, double v) { tt[(int64_t)r * n + c] = v; });
+  gt_gemm<true>(
+      n, n, n, [&](int r, int c) { return bw.ut[(int64_t)c * n + r]; }, tt, n, ub,
+      [&](int r, int c, double v) { kzb[(int64_t)r * n + c] = pb * v; });
+}
+
 }  // namespace
 
 // Threads per point: the Jacobi rounds are latency-bound at one workgroup per CU, so the
@@ -1361,13 +1605,31 @@ size_t geneig_lds_bytes(int nv) {
 template <int TH>
 hipError_t launch_backward_t(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                              double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
-                             const double* s_floor, size_t lds, hipStream_t stream) {
+                             const double* s_floor, size_t lds, hipStream_t stream, int64_t scr_stride,
+                             const double* only) {
   hipError_t err = hipFuncSetAttribute((const void*)geneig_backward_kernel<TH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(geneig_backward_kernel<TH>, dim3(ntb), dim3(TH), lds, stream, nv, k_w, k_z, g_max, tau, rho,
-                     phibar, kw_bar, kz_bar, scratch, s_floor);
+                     phibar, kw_bar, kz_bar, scratch, s_floor, scr_stride, only);
   return hipGetLastError();
+}
+
+hipError_t launch_jacobi_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
+                                  double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
+                                  const double* s_floor, hipStream_t stream, int64_t scr_stride, const double* only) {
+  const size_t lds = geneig_lds_bytes(nv);
+  switch (geneig_threads(nv)) {
+    case 256:
+      return launch_backward_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
+                                    stream, scr_stride, only);
+    case 512:
+      return launch_backward_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
+                                    stream, scr_stride, only);
+    default:
+      return launch_backward_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch,
+                                               s_floor, lds, stream, scr_stride, only);
+  }
 }
 
 template <int TH>
@@ -1406,18 +1668,43 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
                                   double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
                                   hipStream_t stream, const double* s_floor) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
-  const size_t lds = geneig_lds_bytes(nv);
-  switch (geneig_threads(nv)) {
-    case 256:
-      return launch_backward_t<256>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
-                                    stream);
-    case 512:
-      return launch_backward_t<512>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor, lds,
-                                    stream);
-    default:
-      return launch_backward_t<GE_MAX_THREADS>(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch,
-                                               s_floor, lds, stream);
+  if (!geneig_tri_path(nv, 0))
+    return launch_jacobi_backward(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor,
+                                  stream, geneig_backward_scratch_doubles(nv), nullptr);
+  // the tridiagonal path on K_W, then on the padded B, kGeTriChunk points at a time
+  const int64_t stride = geneig_tri_bwd_point_doubles(nv);
+  const int64_t nn = (int64_t)nv * nv;
+  const int64_t state_off = geneig_tri_point_doubles(nv) + 2 * nn + 3 * (int64_t)nv;  // TriBwd::state
+  const size_t vec_lds = tri_vectors_lds_doubles(nv) * sizeof(double);
+  hipError_t err = hipFuncSetAttribute((const void*)geneig_tri_vectors_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)vec_lds);
+  if (err != hipSuccess) return err;
+  for (int i0 = 0; i0 < ntb; i0 += kGeTriChunk) {
+    const int np = std::min(kGeTriChunk, ntb - i0);
+    const double* kw = k_w + i0 * nn;
+    const double* kz = k_z + i0 * nn;
+    const double* pb = phibar + i0;
+    double* kwb = kw_bar + i0 * nn;
+    double* kzb = kz_bar + i0 * nn;
+    const double* sf = s_floor ? s_floor + i0 : nullptr;
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, pass ? nullptr : kw,
+                         scratch, stride);
+      hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
+      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream,
+                         nv, np, scratch, stride);
+      if (pass == 0)
+        hipLaunchKernelGGL(geneig_tri_bwd_form_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, tau, pb, kwb, kzb,
+                           scratch, stride, sf);
+      else
+        hipLaunchKernelGGL(geneig_tri_bwd_finish_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, g_max, rho, pb, kwb,
+                           kzb, scratch, stride);
+    }
+    err = launch_jacobi_backward(nv, np, kw, kz, g_max, tau, rho, pb, kwb, kzb, scratch, sf, stream, stride,
+                                 scratch + state_off);
+    if (err != hipSuccess) return err;
   }
+  return hipGetLastError();
 }
 
 hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,

@@ -1083,7 +1083,7 @@ BackwardLayout backward_layout(const ssm_ctx* c) {
   L.phibar = take(p.nt * 8);
   L.kwb = take(p.nt * nn * 8);
   L.kzb = take(p.nt * nn * 8);
-  L.gescr = take((size_t)p.nt * ssm::geneig_backward_scratch_doubles(p.nv) * 8);
+  L.gescr = take((size_t)ssm::geneig_backward_scratch_total(p.nv, p.nt) * 8);
   L.ct64 = take(p.precision == SSM_FP64 ? (size_t)p.nt * L.ldct * 8 : 0);
   L.ct32 = take(p.precision == SSM_FP32 || p.precision == SSM_FP32_BF16SWEEP ? (size_t)p.nt * L.ldct * 4 : 0);
   L.chit = take(p.precision == SSM_FP32_BF16X3 ? (size_t)m1 * L.ldkt * 2 : 0);

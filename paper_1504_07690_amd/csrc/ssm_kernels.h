@@ -155,6 +155,18 @@ __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
   const int64_t n = nv;
   return 3 * n * n + (2 - geneig_lds_matrices(nv)) * n * (n + 1);
 }
+// The backward on the tridiagonal path: the forward path's per-point scratch, then U^T and
+// Kt (N_v^2 each), F(s), s, the kept indices and the point's state.
+__host__ __device__ inline int64_t geneig_tri_bwd_point_doubles(int nv) {
+  const int64_t n = nv;
+  return geneig_tri_point_doubles(nv) + 2 * n * n + 4 * n + 8;
+}
+// FP64 scratch of launch_geneig_backward for ntb points
+__host__ __device__ inline int64_t geneig_backward_scratch_total(int nv, int ntb) {
+  if (geneig_tri_path(nv, 0))
+    return (int64_t)(ntb < kGeTriChunk ? ntb : kGeTriChunk) * geneig_tri_bwd_point_doubles(nv);
+  return (int64_t)ntb * geneig_backward_scratch_doubles(nv);
+}
 // nvh > 0 adds the hybrid correction of Algorithm 6 from k_c (ntb x nvh x nv), trw (ntb)
 // with hscr (ntb * nvh * nv doubles) as scratch.
 // s_floor (ntb doubles, may be null): Algorithm 4 step 2 also drops s_j < s_floor[i].
@@ -176,7 +188,7 @@ hipError_t launch_ress_floor(int nv, int nvp, int h, const double* x, const doub
 size_t geneig_lds_bytes(int nv);
 // Backward of Algorithm 4 (geneig.hip): kw_bar[i], kz_bar[i] = phibar[i] * d trace / d K_W, K_Z,
 // the kept sets taken as in the forward kernel (s_floor as there, may be null).
-// scratch: 3 * ntb * nv * nv doubles.
+// scratch: geneig_backward_scratch_total(nv, ntb) doubles.
 hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const double* k_z, double g_max, double tau,
                                   double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
                                   hipStream_t stream, const double* s_floor = nullptr);
