@@ -7,11 +7,11 @@
 //   4. keep xi in [0, (1 + rho) g_max], g_max = 1/(N sqrt(2 pi sigma^2))
 //   trace = sum of kept xi, r1 = |kept s|, r2 = |kept xi|.
 //
-// Two eigensolvers.  The trace without the hybrid term, N_v > 48, goes through a
-// tridiagonal matrix (Householder reduction; implicit QL for step 1, bisection for step
-// 3), in four kernels per group of points (see geneig_tri_*).  Below that, with the
-// hybrid term of Algorithm 6, and in the backward kernel, one workgroup per point runs
-// parallel cyclic Jacobi: sweeps in round-robin (tournament) order, so each round
+// Two eigensolvers.  Above N_v = 48 the trace (with or without the hybrid term of
+// Algorithm 6) and its backward go through a tridiagonal matrix (Householder reduction;
+// implicit QL for step 1, bisection or QL for step 3), in kernels per group of points
+// (see geneig_tri_*).  At or below 48, and for points the QL gives up, one workgroup per
+// point runs parallel cyclic Jacobi: sweeps in round-robin (tournament) order, so each round
 // rotates N_v/2 disjoint index pairs at once: the pair angles are computed first
 // (Golub & Van Loan, symmetric 2x2 Schur), then the rows of every pair are rotated,
 // then the columns (and the eigenvector columns).  The pivot entries are set to
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
 
 
 // ---------------------------------------------------------------------------
-// N_v above 48, trace only (no hybrid term): the two symmetric eigenproblems go through
+// N_v above 48, the trace without the hybrid term: the two symmetric eigenproblems go through
 // a tridiagonal matrix.  (Jacobi there pays for rotating whole N_v x N_v matrices once
 // per round; the reduction reads the trailing block once per column instead.)
 //   a. geneig_tri_reduce_kernel: Householder reduction Q^T K_W Q = T (T tridiagonal: d
@@ -1588,6 +1588,152 @@ __global__ void __launch_bounds__(GT_TH) geneig_tri_bwd_finish_kernel(int nv, do
       [&](int r, int c, double v) { kzb[(int64_t)r * n + c] = pb * v; });
 }
 
+
+// ---------------------------------------------------------------------------
+// The trace with RESS-DGC's hybrid term (Algorithm 6, N~_v = nvh columns of W~), N_v > 48:
+//   a-c on K_W (U, S);
+//   geneig_tri_hyb_form_kernel: truncation, U~ = U~ S~^-1/2 (N_v x r1), G^T = (K_C U~)^T,
+//     B = U~^T K_Z U~ padded to N_v x N_v with -1 on the padding's diagonal;
+//   a-c on the padded B (its eigenvalues xi, eigenvectors Q);
+//   geneig_tri_hyb_finish_kernel: the trace of the in-range xi and the correction
+//     (Tr K_W~ - ||G Q~||_F^2) / N~_v, Q~ the in-range eigenvectors (the padding's
+//     eigenvalues, -1, are never in range).
+// status[3] of a point holds r1, status[4] its state (0: on the path, 1: redone by
+// Jacobi, 2: done); U~ and K_Z U~ go through the record's place, G^T through hscr.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(GT_TH) geneig_tri_hyb_form_kernel(int nv, int nvh, const double* __restrict__ k_z,
+                                                                    const double* __restrict__ k_c, double tau,
+                                                                    const double* __restrict__ trw,
+                                                                    double* __restrict__ dos,
+                                                                    int32_t* __restrict__ ranks, int rank_stride,
+                                                                    double* __restrict__ scratch, int64_t stride,
+                                                                    double* __restrict__ hscr,
+                                                                    const double* __restrict__ s_floor) {
+  __shared__ double ub[GE_MAX_NV * GT_U];
+  __shared__ double scale[GE_MAX_NV];
+  __shared__ int kidx[GE_MAX_NV];
+  __shared__ int misc[1];
+  const int n = nv;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  const double* kz = k_z + i * nn;
+  const double* kc = k_c + (int64_t)i * nvh * n;
+  double* gt = hscr + (int64_t)i * nvh * n;
+  TriPoint pt(scratch + i * stride, n);
+  if (pt.status[0] != 0.0) {  // QL on K_W stopped
+    if (tid == 0) pt.status[4] = 1.0;
+    return;
+  }
+  if (tid == 0) {
+    double smax = -INFINITY;
+    for (int j = 0; j < n; ++j) smax = fmax(smax, pt.eig[j]);
+    int r1 = 0;
+    if (smax > 0.0) {
+      const double thr = s_floor ? fmax(tau * smax, s_floor[i]) : tau * smax;
+      for (int j = 0; j < n; ++j)
+        if (pt.eig[j] >= thr) {
+          kidx[r1] = j;
+          scale[r1] = 1.0 / sqrt(pt.eig[j]);
+          ++r1;
+        }
+    }
+    misc[0] = r1;
+    pt.status[3] = r1;
+    pt.status[4] = r1 == 0 ? 2.0 : 0.0;
+    if (r1 == 0) {  // C~ is empty: only Tr K_W~ / N~_v remains
+      dos[i] = trw[i] / nvh;
+      if (ranks) {
+        ranks[i] = 0;
+        ranks[rank_stride + i] = 0;
+      }
+    }
+  }
+  __syncthreads();
+  const int r1 = misc[0];
+  if (r1 == 0) return;
+  double* ut = pt.rec;                   // U~ S~^-1/2, N_v x r1
+  double* tz = pt.rec + (int64_t)n * r1;  // K_Z^T U~ S~^-1/2, N_v x r1
+  for (int idx = tid; idx < n * r1; idx += GT_TH) {
+    const int c = idx / r1, b = idx - c * r1;
+    ut[idx] = pt.zt[(int64_t)kidx[b] * n + c] * scale[b];
+  }
+  __threadfence_block();
+  __syncthreads();
+  // G^T[b][a] = sum_c K_C[a][c] U~[c][b]
+  gt_gemm<false>(
+      nvh, r1, n, [&](int a, int c) { return kc[(int64_t)a * n + c]; }, ut, r1, ub,
+      [&](int a, int b, double v) { gt[(int64_t)b * nvh + a] = v; });
+  // K_Z^T U~ (K_Z^T for K_Z: B becomes B^T, which the symmetrisation takes to the same matrix)
+  gt_gemm<true>(
+      n, r1, n, [&](int r, int c) { return kz[(int64_t)c * n + r]; }, ut, r1, ub,
+      [&](int r, int b, double v) { tz[(int64_t)r * r1 + b] = v; });
+  // B = U~^T (K_Z^T U~) into the reduction's place
+  gt_gemm<true>(
+      r1, r1, n, [&](int a, int c) { return ut[(int64_t)c * r1 + a]; }, tz, r1, ub,
+      [&](int a, int b, double v) { pt.a[(int64_t)a * n + b] = v; });
+  for (int idx = tid; idx < n * n; idx += GT_TH) {
+    const int a = idx / n, b = idx - a * n;
+    if (a < r1 && b < r1) {
+      if (a < b) {
+        const double m = 0.5 * (pt.a[(int64_t)a * n + b] + pt.a[(int64_t)b * n + a]);
+        pt.a[(int64_t)a * n + b] = m;
+        pt.a[(int64_t)b * n + a] = m;
+      }
+    } else {
+      pt.a[idx] = a == b ? -1.0 : 0.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(GT_TH) geneig_tri_hyb_finish_kernel(int nv, int nvh, double g_max, double rho,
+                                                                      const double* __restrict__ trw,
+                                                                      double* __restrict__ dos,
+                                                                      int32_t* __restrict__ ranks, int rank_stride,
+                                                                      double* __restrict__ scratch, int64_t stride,
+                                                                      const double* __restrict__ hscr) {
+  __shared__ double ub[GE_MAX_NV * GT_U];
+  __shared__ double red[GT_TH / 64];
+  const int n = nv;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  TriPoint pt(scratch + i * stride, n);
+  if (pt.status[4] != 0.0) return;  // redone by Jacobi, or done
+  if (pt.status[0] != 0.0) {        // QL on B stopped
+    if (tid == 0) pt.status[4] = 1.0;
+    return;
+  }
+  const int r1 = (int)pt.status[3];
+  const double hi = (1.0 + rho) * g_max;
+  const double* gt = hscr + (int64_t)i * nvh * n;
+  // ||G Q~||_F^2: row j of H^T = Q~^T G^T is sum_b q_j[b] G^T[b][.], lane a summing squares
+  double part = 0.0;
+  gt_gemm<false>(
+      n, nvh, r1,
+      [&](int j, int b) {
+        const double xi = pt.eig[j];
+        return xi >= 0.0 && xi <= hi ? pt.zt[(int64_t)j * n + b] : 0.0;
+      },
+      gt, nvh, ub, [&](int, int, double v) { part += v * v; });
+  const double hs = gt_sum(part, red);
+  if (tid == 0) {
+    double tr = 0.0;
+    int r2 = 0;
+    for (int j = 0; j < n; ++j) {
+      const double xi = pt.eig[j];
+      if (xi >= 0.0 && xi <= hi) {
+        tr += xi;
+        ++r2;
+      }
+    }
+    dos[i] = tr + (trw[i] - hs) / nvh;
+    if (ranks) {
+      ranks[i] = r1;
+      ranks[rank_stride + i] = r2;
+    }
+  }
+}
+
 }  // namespace
 
 // Threads per point: the Jacobi rounds are latency-bound at one workgroup per CU, so the
@@ -1668,7 +1814,7 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
                                   double rho, const double* phibar, double* kw_bar, double* kz_bar, double* scratch,
                                   hipStream_t stream, const double* s_floor) {
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
-  if (!geneig_tri_path(nv, 0))
+  if (!geneig_tri_path(nv))
     return launch_jacobi_backward(nv, ntb, k_w, k_z, g_max, tau, rho, phibar, kw_bar, kz_bar, scratch, s_floor,
                                   stream, geneig_backward_scratch_doubles(nv), nullptr);
   // the tridiagonal path on K_W, then on the padded B, kGeTriChunk points at a time
@@ -1714,7 +1860,7 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
   if (nv < 1 || nv > GE_MAX_NV) return hipErrorInvalidValue;
   if (nvh < 0 || (nvh > 0 && (!k_c || !trw || !hscr))) return hipErrorInvalidValue;
   if (rank_stride <= 0) rank_stride = ntb;
-  if (!geneig_tri_path(nv, nvh))
+  if (!geneig_tri_path(nv))
     return launch_jacobi_trace(nv, ntb, k_w, k_z, g_max, tau, rho, dos, ranks, scratch, nvh, k_c, trw, hscr, s_floor,
                                rank_stride, stream, geneig_scratch_doubles(nv), nullptr);
   // the tridiagonal path, kGeTriChunk points at a time through the same scratch
@@ -1734,10 +1880,26 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
     hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
     hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream, nv,
                        np, scratch, stride);
-    hipLaunchKernelGGL(geneig_tri_trace_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, g_max, tau, rho, dos + i0,
-                       rk, rank_stride, scratch, stride, sf);
-    err = launch_jacobi_trace(nv, np, kw, kz, g_max, tau, rho, dos + i0, rk, scratch, 0, nullptr, nullptr, nullptr,
-                              sf, rank_stride, stream, stride, scratch + 6 * nn + 4 * nv);
+    if (nvh == 0) {
+      hipLaunchKernelGGL(geneig_tri_trace_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, g_max, tau, rho,
+                         dos + i0, rk, rank_stride, scratch, stride, sf);
+      err = launch_jacobi_trace(nv, np, kw, kz, g_max, tau, rho, dos + i0, rk, scratch, 0, nullptr, nullptr, nullptr,
+                                sf, rank_stride, stream, stride, scratch + 6 * nn + 4 * nv);
+    } else {  // B through the same kernels, then the trace and the hybrid term
+      const double* kc = k_c + (int64_t)i0 * nvh * nv;
+      double* hs = hscr + (int64_t)i0 * nvh * nv;
+      hipLaunchKernelGGL(geneig_tri_hyb_form_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, nvh, kz, kc, tau,
+                         trw + i0, dos + i0, rk, rank_stride, scratch, stride, hs, sf);
+      hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, (const double*)nullptr,
+                         scratch, stride);
+      hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
+      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream,
+                         nv, np, scratch, stride);
+      hipLaunchKernelGGL(geneig_tri_hyb_finish_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, nvh, g_max, rho,
+                         trw + i0, dos + i0, rk, rank_stride, scratch, stride, hs);
+      err = launch_jacobi_trace(nv, np, kw, kz, g_max, tau, rho, dos + i0, rk, scratch, nvh, kc, trw + i0, hs, sf,
+                                rank_stride, stream, stride, scratch + 6 * nn + 4 * nv + 4);
+    }
     if (err != hipSuccess) return err;
   }
   return hipGetLastError();

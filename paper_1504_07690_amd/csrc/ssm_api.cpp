@@ -257,7 +257,7 @@ void layout(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_w = take(own_w ? e * es : 0);
   pl.off_kw = take((size_t)p->nt * nn * 8);
   pl.off_kz = take((size_t)p->nt * nn * 8);
-  pl.off_escr = take((size_t)ssm::geneig_trace_scratch_doubles(p->nv, p->nt, 0) * 8);
+  pl.off_escr = take((size_t)ssm::geneig_trace_scratch_doubles(p->nv, p->nt) * 8);
   pl.off_dos = take(p->nt * 8);
   pl.off_ranks = take(2 * (size_t)p->nt * 4);
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
@@ -305,7 +305,7 @@ void layout_ress(Plan& pl, const ssm_csr* a, const ssm_params* p, bool own_w) {
   pl.off_kc = take((size_t)p->nt * p->nv_hybrid * p->nv * 8);
   pl.off_trw = take((size_t)p->nt * 8);
   pl.off_hscr = take((size_t)p->nt * p->nv_hybrid * p->nv * 8);
-  pl.off_escr = take((size_t)ssm::geneig_trace_scratch_doubles(p->nv, p->nt, p->nv_hybrid) * 8);
+  pl.off_escr = take((size_t)ssm::geneig_trace_scratch_doubles(p->nv, p->nt) * 8);
   pl.off_dos = take(p->nt * 8);
   pl.off_ranks = take(2 * (size_t)p->nt * 4);
   pl.off_norm = take((size_t)(ssm::reduce_partials() + 8) * 8);
@@ -1621,7 +1621,7 @@ ssm_status ssm_geneig_trace(int32_t nv, int32_t ntb, const double* k_w, const do
 
 int64_t ssm_geneig_trace_scratch_doubles(int32_t nv, int32_t ntb) {
   if (nv < 1 || nv > kMaxNv || ntb < 1) return -1;
-  return ssm::geneig_trace_scratch_doubles(nv, ntb, 0);
+  return ssm::geneig_trace_scratch_doubles(nv, ntb);
 }
 
 }  // extern "C"

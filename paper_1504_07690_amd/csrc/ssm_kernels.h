@@ -135,20 +135,20 @@ __host__ __device__ inline int64_t geneig_scratch_doubles(int nv) {
   const int64_t n = nv;
   return n * n + (2 - geneig_lds_matrices(nv)) * n * (n + 1);
 }
-// Above N_v = 48 the trace without the hybrid term goes through a tridiagonal matrix
+// Above N_v = 48 the trace (with or without the hybrid term) goes through a tridiagonal matrix
 // (Householder reduction, QL for eig(K_W) with the eigenvectors built in LDS from a record
 // of its rotations, bisection for eig(B)), kGeTriChunk points per launch group through
 // geneig_tri_point_doubles of scratch each: 6 n^2 + 8 n + 8 (the reduced matrix, U^T, the
 // rotation record of 4 n^2, the tridiagonal matrix and status).
 constexpr int kGeTriChunk = 2048;
-__host__ __device__ inline bool geneig_tri_path(int nv, int nvh) { return nvh == 0 && nv > 48; }
+__host__ __device__ inline bool geneig_tri_path(int nv) { return nv > 48; }
 __host__ __device__ inline int64_t geneig_tri_point_doubles(int nv) {
   const int64_t n = nv;
   return 6 * n * n + 8 * n + 8;
 }
-// FP64 scratch of launch_geneig_trace for ntb points (nvh: the hybrid term's N~_v)
-__host__ __device__ inline int64_t geneig_trace_scratch_doubles(int nv, int ntb, int nvh) {
-  if (geneig_tri_path(nv, nvh)) return (int64_t)(ntb < kGeTriChunk ? ntb : kGeTriChunk) * geneig_tri_point_doubles(nv);
+// FP64 scratch of launch_geneig_trace for ntb points
+__host__ __device__ inline int64_t geneig_trace_scratch_doubles(int nv, int ntb) {
+  if (geneig_tri_path(nv)) return (int64_t)(ntb < kGeTriChunk ? ntb : kGeTriChunk) * geneig_tri_point_doubles(nv);
   return (int64_t)ntb * geneig_scratch_doubles(nv);
 }
 __host__ __device__ inline int64_t geneig_backward_scratch_doubles(int nv) {
@@ -163,7 +163,7 @@ __host__ __device__ inline int64_t geneig_tri_bwd_point_doubles(int nv) {
 }
 // FP64 scratch of launch_geneig_backward for ntb points
 __host__ __device__ inline int64_t geneig_backward_scratch_total(int nv, int ntb) {
-  if (geneig_tri_path(nv, 0))
+  if (geneig_tri_path(nv))
     return (int64_t)(ntb < kGeTriChunk ? ntb : kGeTriChunk) * geneig_tri_bwd_point_doubles(nv);
   return (int64_t)ntb * geneig_backward_scratch_doubles(nv);
 }

@@ -126,7 +126,7 @@ def test_ress_degrees_and_ragged_block(S, degree, nv, nvh):
     _check(dos, ref["dos"], f"ragged M={degree} N_v={nv} N~_v={nvh}")
 
 
-@pytest.mark.parametrize("nv,nvh", [(96, 32), (128, 0), (160, 96)])
+@pytest.mark.parametrize("nv,nvh", [(64, 16), (96, 32), (128, 0), (160, 96)])
 def test_ress_large_blocks(S, nv, nvh):
     """N_v' above 96 (tiled pair Gram) and N_v above 96 (Algorithm 4 in global scratch)."""
     rng = np.random.default_rng(nv + nvh)
