@@ -1008,33 +1008,48 @@ __global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __res
   }
 }
 
-// c. Rows of U = Q Y, 64 per workgroup, one per lane of wave 0 (in LDS as L[j][lane], so
-// the wave's accesses are contiguous): row r starts as e_r, takes x <- x H_k for
-// k = 0..n-3 (x - tau (x.v) v^T), then the recorded rotations, and is written to
-// Z^T[.][r].  Wave 1 feeds wave 0 through two LDS slots per kind: the reflectors one per
-// step, the rotation record in blocks of GT_BLK (an iteration may span blocks; wave 0
-// carries its state across).  Its loads are issued GT_VD (GT_RD) steps before their
-// data is due, in rotating register sets, so a step waits for none of them; each step
-// ends at a barrier.  The workgroups of one point's row chunks run on one XCD (blockIdx
+// c. Rows of U = Q Y, 64 per workgroup, one per lane (in LDS as L[j][lane], so a wave's
+// accesses are contiguous): row r starts as e_r, takes x <- x H_k for k = 0..n-3
+// (x - tau (x.v) v^T), then the recorded rotations, and is written to Z^T[.][r].  The
+// reflector steps are shared by waves 0..GT_VW-1, each owning the entries j of every row in
+// the 8-entry blocks j / 8 = w mod GT_VW: a step's partial products x.v meet in LDS at the
+// step's barrier, and each wave then updates its own entries.  The rotations run along a
+// row, so wave 0 alone applies them.  Wave GT_VW feeds the others: the reflectors one per
+// step through three LDS slots, the rotation record in blocks of GT_BLK through two (an
+// iteration may span blocks; wave 0 carries its state across).  Its loads are issued
+// GT_VD (GT_RD) steps before their data is due, in rotating register sets, so a step
+// waits for none of them; each step ends at a barrier.  The workgroups of one point's row chunks run on one XCD (blockIdx
 // modulo 8 picks the XCD), so the record streams from that XCD's L2 after the first.
 constexpr int GT_BLK = 512;  // rotations per staged block
 constexpr int GT_VD = 3;     // reflector loads in flight
 constexpr int GT_RD = 2;     // rotation block loads in flight
+constexpr int GT_VW = 3;     // waves sharing the reflector steps (one more feeds them)
 
 __host__ __device__ constexpr size_t tri_vectors_lds_doubles(int n) {
   return (size_t)n * 64 + 2 * GE_MAX_NV + 2 * 2 * GT_BLK + GE_MAX_NV + GT_REC_IT * GE_MAX_NV;
 }
 __host__ __device__ inline int tri_vectors_groups(int np, int nv) { return (np + 7) / 8 * 8 * ((nv + 63) / 64); }
 
-__global__ void __launch_bounds__(128) geneig_tri_vectors_kernel(int nv, int np, double* __restrict__ scratch,
-                                                                 int64_t stride) {
+__global__ void __launch_bounds__(64 * (GT_VW + 1)) geneig_tri_vectors_kernel(int nv, int np,
+                                                                              double* __restrict__ scratch,
+                                                                              int64_t stride) {
   extern __shared__ double lds[];
   const int n = nv;
   double* L = lds;
-  double* vslot = L + n * 64;                  // 2 reflectors
+  double* vslot = L + n * 64;                  // reflector slots 0 and 1
   double* rslot = vslot + 2 * GE_MAX_NV;       // 2 blocks of rotations
   double* taus = rslot + 2 * 2 * GT_BLK;
   int* hdr = (int*)(taus + GE_MAX_NV);         // 2 GT_REC_IT GE_MAX_NV ints
+  // Until the rotation phase, the second rotation block holds reflector slot 2 and the
+  // partial products of two steps (GT_VW x 64 each); the feeding wave writes that block
+  // only after the barrier that ends the reflector phase.
+  double* vslot2 = rslot + 2 * GT_BLK;
+  double* part = vslot2 + GE_MAX_NV;
+  static_assert(GE_MAX_NV + 2 * GT_VW * 64 <= 2 * GT_BLK, "reflector slot 2 and the partial products");
+  auto vref = [&](int k) -> double* {  // reflector k's slot
+    const int q = k % 3;
+    return q == 2 ? vslot2 : vslot + q * GE_MAX_NV;
+  };
   const int nch = (n + 63) / 64;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int point = (slot / nch) * 8 + xcd, ch = slot % nch;
@@ -1062,7 +1077,7 @@ __global__ void __launch_bounds__(128) geneig_tri_vectors_kernel(int nv, int np,
   };
   auto put_v = [&](int k, const double (&x)[VQ]) {
     const int m = k < nrefl ? n - k - 1 : 0;
-    double* dst = vslot + (k & 1) * GE_MAX_NV;
+    double* dst = vref(k);
 #pragma unroll
     for (int q = 0; q < VQ; ++q) dst[lane + 64 * q] = lane + 64 * q < m ? x[q] : 0.0;
   };
@@ -1080,40 +1095,52 @@ __global__ void __launch_bounds__(128) geneig_tri_vectors_kernel(int nv, int np,
     for (int q = 0; q < RQ; ++q) dst[lane + 64 * q] = blk * 2 * GT_BLK + lane + 64 * q <= last ? x[q] : 0.0;
   };
 
-  // wave 0's step k of the reflector phase: x <- x H_k
-  auto reflect = [&](int k) {
-    const int m = n - k - 1;
-    const double tau = taus[k];
-    const double* v = vslot + (k & 1) * GE_MAX_NV;
-    if (tau == 0.0) return;
-    double* x = L + (k + 1) * 64 + lane;
+  // Step k of the reflector phase on this wave's entries j > k of the row: x.v over them,
+  // and x_j <- x_j - y v_j, with v_j at index j - k - 1 of the slot.  Blocks of 8 entries;
+  // the block that holds entry k + 1 is cut at it.
+  auto refl_first = [&](int k) {  // wave w's first block at or after entry k + 1
+    const int b = (k + 1) >> 3;
+    return b + (wave - b % GT_VW + GT_VW) % GT_VW;
+  };
+  auto refl_dot = [&](int k) {
+    const double* v = vref(k);
     double acc[4] = {};
-    int t = 0;
-    for (; t + GT_U <= m; t += GT_U) {
-      double xv[GT_U];
+    for (int b = refl_first(k); 8 * b < n; b += GT_VW) {
+      const int j0 = 8 * b;
+      if (j0 > k && j0 + 8 <= n) {
+        double xv[8];
 #pragma unroll
-      for (int u = 0; u < GT_U; ++u) xv[u] = x[(t + u) * 64];
+        for (int u = 0; u < 8; ++u) xv[u] = L[(j0 + u) * 64 + lane];
 #pragma unroll
-      for (int u = 0; u < GT_U; ++u) acc[u & 3] += xv[u] * v[t + u];
-    }
-    for (; t < m; ++t) acc[0] += x[t * 64] * v[t];
-    const double y = tau * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
-    for (t = 0; t + GT_U <= m; t += GT_U) {  // reads of a batch before its writes
-      double xv[GT_U], vv[GT_U];
-#pragma unroll
-      for (int u = 0; u < GT_U; ++u) {
-        xv[u] = x[(t + u) * 64];
-        vv[u] = v[t + u];
+        for (int u = 0; u < 8; ++u) acc[u & 3] += xv[u] * v[j0 + u - k - 1];
+      } else {
+        for (int j = j0 > k ? j0 : k + 1; j < j0 + 8 && j < n; ++j) acc[j & 3] += L[j * 64 + lane] * v[j - k - 1];
       }
-#pragma unroll
-      for (int u = 0; u < GT_U; ++u) x[(t + u) * 64] = xv[u] - y * vv[u];
     }
-    for (; t < m; ++t) x[t * 64] -= y * v[t];
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  };
+  auto refl_update = [&](int k, double y) {  // reads of a block before its writes
+    const double* v = vref(k);
+    for (int b = refl_first(k); 8 * b < n; b += GT_VW) {
+      const int j0 = 8 * b;
+      if (j0 > k && j0 + 8 <= n) {
+        double xv[8], vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xv[u] = L[(j0 + u) * 64 + lane];
+          vv[u] = v[j0 + u - k - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) L[(j0 + u) * 64 + lane] = xv[u] - y * vv[u];
+      } else {
+        for (int j = j0 > k ? j0 : k + 1; j < j0 + 8 && j < n; ++j) L[j * 64 + lane] -= y * v[j - k - 1];
+      }
+    }
   };
 
-  // the two waves run separate loops with the same barriers: 1 + nrefl + 1 + nblk
+  // every wave passes the same barriers: 1 + nrefl + 1 + nblk
   const int64_t nblk = (nrot + GT_BLK - 1) / GT_BLK;
-  if (wave == 1) {
+  if (wave == GT_VW) {
     double vs[GT_VD][VQ];  // reflectors in flight, v_j in set j % GT_VD
     for (int j = lane; j < n; j += 64) taus[j] = pt.tau[j];
     for (int j = lane; j < 2 * nit; j += 64) hdr[j] = pt.hdr[j];
@@ -1152,69 +1179,80 @@ __global__ void __launch_bounds__(128) geneig_tri_vectors_kernel(int nv, int np,
       }
     }
   } else {
-    for (int j = 0; j < n; ++j) L[j * 64 + lane] = j == r ? 1.0 : 0.0;
+    for (int j = wave; j < n; j += GT_VW) L[j * 64 + lane] = j == r ? 1.0 : 0.0;
     __syncthreads();
     for (int k = 0; k < nrefl; ++k) {
-      reflect(k);
+      const double tau = taus[k];
+      double* pk = part + (k & 1) * GT_VW * 64;
+      pk[wave * 64 + lane] = tau != 0.0 ? refl_dot(k) : 0.0;
       __syncthreads();
+      if (tau != 0.0) {
+        double y = pk[lane];
+        for (int w = 1; w < GT_VW; ++w) y += pk[w * 64 + lane];
+        refl_update(k, tau * y);
+      }
     }
     __syncthreads();
-    int it = 0, t = 0, mm = 0, i0 = 0, cnt = 0;  // the iteration and rotation reached
-    double hold = 0.0;
-    if (nit > 0) {
-      mm = hdr[0];
-      i0 = hdr[1];
-      cnt = mm - i0;
-    }
-    for (int64_t blk = 0; blk < nblk; ++blk) {
-      const double* rb = rslot + (blk & 1) * 2 * GT_BLK;
-      int64_t p = blk * GT_BLK;
-      const int64_t pend = p + GT_BLK < nrot ? p + GT_BLK : nrot;
-      while (p < pend) {
-        if (t == 0) hold = L[mm * 64 + lane];
-        const int nh = (int)(cnt - t < pend - p ? cnt - t : pend - p);
-        const double* rc = rb + 2 * (p - blk * GT_BLK);
-        const int top = mm - 1 - t;  // rotation j of this run is i = top - j
-        int j = 0;
-        // every LDS read of a batch is issued before its first write: the compiler cannot
-        // tell the rows written from the rotations read, so it would not move them
-        for (; j + GT_U <= nh; j += GT_U) {
-          double z[GT_U], c[GT_U], sn[GT_U];
-#pragma unroll
-          for (int u = 0; u < GT_U; ++u) {
-            z[u] = L[(top - j - u) * 64 + lane];
-            c[u] = rc[2 * (j + u)];
-            sn[u] = rc[2 * (j + u) + 1];
-          }
-#pragma unroll
-          for (int u = 0; u < GT_U; ++u) {
-            L[(top - j - u + 1) * 64 + lane] = sn[u] * z[u] + c[u] * hold;
-            hold = c[u] * z[u] - sn[u] * hold;
-          }
-        }
-        for (; j < nh; ++j) {
-          const double z = L[(top - j) * 64 + lane];
-          const double c = rc[2 * j], sn = rc[2 * j + 1];
-          L[(top - j + 1) * 64 + lane] = sn * z + c * hold;
-          hold = c * z - sn * hold;
-        }
-        t += nh;
-        p += nh;
-        if (t == cnt) {
-          L[i0 * 64 + lane] = hold;
-          t = 0;
-          if (++it < nit) {
-            mm = hdr[2 * it];
-            i0 = hdr[2 * it + 1];
-            cnt = mm - i0;
-          }
-        }
+    if (wave != 0) {  // the rotations are wave 0's
+      for (int64_t blk = 0; blk < nblk; ++blk) __syncthreads();
+    } else {
+      int it = 0, t = 0, mm = 0, i0 = 0, cnt = 0;  // the iteration and rotation reached
+      double hold = 0.0;
+      if (nit > 0) {
+        mm = hdr[0];
+        i0 = hdr[1];
+        cnt = mm - i0;
       }
-      __syncthreads();
+      for (int64_t blk = 0; blk < nblk; ++blk) {
+        const double* rb = rslot + (blk & 1) * 2 * GT_BLK;
+        int64_t p = blk * GT_BLK;
+        const int64_t pend = p + GT_BLK < nrot ? p + GT_BLK : nrot;
+        while (p < pend) {
+          if (t == 0) hold = L[mm * 64 + lane];
+          const int nh = (int)(cnt - t < pend - p ? cnt - t : pend - p);
+          const double* rc = rb + 2 * (p - blk * GT_BLK);
+          const int top = mm - 1 - t;  // rotation j of this run is i = top - j
+          int j = 0;
+          // every LDS read of a batch is issued before its first write: the compiler cannot
+          // tell the rows written from the rotations read, so it would not move them
+          for (; j + GT_U <= nh; j += GT_U) {
+            double z[GT_U], c[GT_U], sn[GT_U];
+#pragma unroll
+            for (int u = 0; u < GT_U; ++u) {
+              z[u] = L[(top - j - u) * 64 + lane];
+              c[u] = rc[2 * (j + u)];
+              sn[u] = rc[2 * (j + u) + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < GT_U; ++u) {
+              L[(top - j - u + 1) * 64 + lane] = sn[u] * z[u] + c[u] * hold;
+              hold = c[u] * z[u] - sn[u] * hold;
+            }
+          }
+          for (; j < nh; ++j) {
+            const double z = L[(top - j) * 64 + lane];
+            const double c = rc[2 * j], sn = rc[2 * j + 1];
+            L[(top - j + 1) * 64 + lane] = sn * z + c * hold;
+            hold = c * z - sn * hold;
+          }
+          t += nh;
+          p += nh;
+          if (t == cnt) {
+            L[i0 * 64 + lane] = hold;
+            t = 0;
+            if (++it < nit) {
+              mm = hdr[2 * it];
+              i0 = hdr[2 * it + 1];
+              cnt = mm - i0;
+            }
+          }
+        }
+        __syncthreads();
+      }
     }
   }
   if (r < n)
-    for (int j = wave; j < n; j += 2) pt.zt[(int64_t)j * n + r] = L[j * 64 + lane];
+    for (int j = wave; j < n; j += GT_VW + 1) pt.zt[(int64_t)j * n + r] = L[j * 64 + lane];
 }
 
 // d. Algorithm 4 steps 2-4 from U, S: truncation, B, its eigenvalues (reduction, then
@@ -1848,7 +1886,7 @@ hipError_t launch_geneig_backward(int nv, int ntb, const double* k_w, const doub
       hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, pass ? nullptr : kw,
                          scratch, stride);
       hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
-      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream,
+      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(64 * (GT_VW + 1)), vec_lds, stream,
                          nv, np, scratch, stride);
       if (pass == 0)
         hipLaunchKernelGGL(geneig_tri_bwd_form_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, tau, pb, kwb, kzb,
@@ -1889,7 +1927,7 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
     const double* sf = s_floor ? s_floor + i0 : nullptr;
     hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kw, scratch, stride);
     hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
-    hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream, nv,
+    hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(64 * (GT_VW + 1)), vec_lds, stream, nv,
                        np, scratch, stride);
     if (nvh == 0) {
       hipLaunchKernelGGL(geneig_tri_trace_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, kz, g_max, tau, rho,
@@ -1904,7 +1942,7 @@ hipError_t launch_geneig_trace(int nv, int ntb, const double* k_w, const double*
       hipLaunchKernelGGL(geneig_tri_reduce_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, (const double*)nullptr,
                          scratch, stride);
       hipLaunchKernelGGL(geneig_tri_ql_kernel, dim3(np), dim3(64), 0, stream, nv, scratch, stride);
-      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(128), vec_lds, stream,
+      hipLaunchKernelGGL(geneig_tri_vectors_kernel, dim3(tri_vectors_groups(np, nv)), dim3(64 * (GT_VW + 1)), vec_lds, stream,
                          nv, np, scratch, stride);
       hipLaunchKernelGGL(geneig_tri_hyb_finish_kernel, dim3(np), dim3(GT_TH), 0, stream, nv, nvh, g_max, rho,
                          trw + i0, dos + i0, rk, rank_stride, scratch, stride, hs);
