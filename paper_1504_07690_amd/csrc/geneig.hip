@@ -20,6 +20,8 @@
 // matrix alone up to N_v = 128 (eigenvectors in the point's global scratch), both in
 // global scratch above that (N_v <= 256); the N_v x r1 product
 // Z^T Z U~ S~^-1/2 goes through the same per-point scratch.
+#include <type_traits>
+
 #include "ssm_kernels.h"
 
 namespace ssm {
@@ -907,6 +909,7 @@ __device__ __forceinline__ double gt_rsqrt(double x) {
 // wave's 64 lanes active.
 __global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __restrict__ scratch, int64_t stride) {
   __shared__ double d[GE_MAX_NV], e[GE_MAX_NV];
+  __shared__ double d0[GE_MAX_NV], e0[GE_MAX_NV];  // the block's entries before an iteration
   const int n = nv;
   const bool lead = threadIdx.x == 0;
   TriPoint pt(scratch + blockIdx.x * stride, n);
@@ -954,38 +957,66 @@ __global__ void __launch_bounds__(64) geneig_tri_ql_kernel(int nv, double* __res
     // shift: the eigenvalue of the leading 2 x 2 block nearer d_l
     double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
     double r = sqrt(g * g + 1.0);
-    g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-    double s = 1.0, c = 1.0, p = 0.0;
-    int i = mm - 1;
-    double ei = e[i], di = d[i], di1 = d[i + 1];  // entries the step reads, loaded one step ahead
-    for (; i >= l; --i) {
-      const double en = e[i > 0 ? i - 1 : 0], dn = d[i > 0 ? i - 1 : 0];  // unconditional loads
-      const double f = s * ei, b = c * ei;
-      const double ss = f * f + g * g;
-      if (ss == 0.0) {  // the block splits at i + 1: drop the shift and redo the block
-        e[i + 1] = 0.0;
-        d[i + 1] = di1 - p;
-        e[mm] = 0.0;
-        break;
+    const double gs = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+    // The iteration's rotations run without the split test (ss = 0: the block splits at
+    // i + 1), which as a branch in the chain cost a fifth of the kernel's time.  A split
+    // leaves NaN in the chain from there on, so a NaN g at the end sends the iteration back
+    // to the block's entries as they were and through the loop that tests every step.
+    for (int j = l + (int)threadIdx.x; j <= mm; j += 64) {
+      d0[j] = d[j];
+      e0[j] = e[j];
+    }
+    const int64_t pos0 = pos;
+    double s, c, p;
+    int i;
+    auto iterate = [&](auto tested) {
+      constexpr bool TESTED = decltype(tested)::value;
+      g = gs;
+      s = 1.0;
+      c = 1.0;
+      p = 0.0;
+      pos = pos0;
+      i = mm - 1;
+      double ei = e[i], di = d[i], di1 = d[i + 1];  // entries the step reads, loaded one step ahead
+      for (; i >= l; --i) {
+        const double en = e[i > 0 ? i - 1 : 0], dn = d[i > 0 ? i - 1 : 0];  // unconditional loads
+        const double f = s * ei, b = c * ei;
+        const double ss = f * f + g * g;
+        if (TESTED && ss == 0.0) {  // the block splits at i + 1: drop the shift and redo the block
+          e[i + 1] = 0.0;
+          d[i + 1] = di1 - p;
+          e[mm] = 0.0;
+          break;
+        }
+        const double inv = gt_rsqrt(ss);
+        r = ss * inv;
+        e[i + 1] = r;
+        s = f * inv;
+        c = g * inv;
+        g = di1 - p;
+        r = (di - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        if (lead) {
+          rec[pos] = c;
+          rec[pos + 1] = s;
+        }
+        pos += 2;
+        ei = en;
+        di1 = di;
+        di = dn;
       }
-      const double inv = gt_rsqrt(ss);
-      r = ss * inv;
-      e[i + 1] = r;
-      s = f * inv;
-      c = g * inv;
-      g = di1 - p;
-      r = (di - g) * s + 2.0 * c * b;
-      p = s * r;
-      d[i + 1] = g + p;
-      g = c * r - b;
-      if (lead) {
-        rec[pos] = c;
-        rec[pos + 1] = s;
+    };
+    iterate(std::false_type{});
+    if (__builtin_amdgcn_readfirstlane(g != g ? 1 : 0)) {  // every lane holds the same g
+      __syncthreads();
+      for (int j = l + (int)threadIdx.x; j <= mm; j += 64) {
+        d[j] = d0[j];
+        e[j] = e0[j];
       }
-      pos += 2;
-      ei = en;
-      di1 = di;
-      di = dn;
+      __syncthreads();
+      iterate(std::true_type{});
     }
     if (i + 1 < mm) {
       if (lead) {
