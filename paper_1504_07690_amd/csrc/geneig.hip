@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(TH) geneig_backward_kernel(int nv, const doubl
 //   a. geneig_tri_reduce_kernel: Householder reduction Q^T K_W Q = T (T tridiagonal: d
 //      on the diagonal, e[i] coupling i and i + 1), the reflectors kept in the rows of
 //      the reduced matrix;
-//   b. geneig_tri_ql_kernel: implicit QL with Wilkinson shifts on T, one lane per point,
+//   b. geneig_tri_ql_kernel: implicit QL with Wilkinson shifts on T, one wave per point,
 //      its plane rotations recorded in order (Y = their product: T = Y S Y^T);
 //   c. geneig_tri_vectors_kernel: U = Q Y row by row, 64 rows per workgroup in LDS, from
 //      the reflectors and the record; row j of the transposed array is eigenvector j
