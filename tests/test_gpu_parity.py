@@ -366,6 +366,22 @@ def _theorem3_pencils(rng, count, n, r, nv):
     return np.array(kws), np.array(kzs)
 
 
+@pytest.mark.parametrize("nv", [49, 77, 131, 250])
+def test_geneig_tridiagonal_path_odd_sizes(S, nv):
+    """N_v not a multiple of 8 on the tridiagonal path: the last 8-entry block of each row
+    in the reflector steps is partial, and the last 64-row group of U is partial (for
+    77, 131 and 250); three Theorem 3 pencils against the oracle."""
+    kw, kz = _theorem3_pencils(_rng(13 + nv), 3, 2 * nv + 50, nv // 3, nv)
+    dos = torch.empty(3, dtype=torch.float64, device=DEV)
+    ranks = torch.empty(6, dtype=torch.int32, device=DEV)
+    S.geneig_trace(torch.tensor(kw, device=DEV), torch.tensor(kz, device=DEV), 0.008, 1e-7, 1e-3, dos, ranks)
+    d, rk = dos.cpu().numpy(), ranks.cpu().numpy()
+    for i in range(3):
+        ref, r1, r2 = O.geneig_trace(kw[i], kz[i], 0.008, 1e-7, 1e-3)
+        assert abs(d[i] - ref) <= 1e-10 * 0.008, i
+        assert [rk[i], rk[3 + i]] == [r1, r2], i
+
+
 def test_geneig_tridiagonal_path_redoes_a_stopped_point(S):
     """Above N_v = 48 a point whose QL stops (here: NaN in K_W, so no block ever splits)
     is redone by the Jacobi kernel, and only that point: its outputs are written (by
