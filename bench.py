@@ -280,6 +280,9 @@ def main():
                     help="skip the random-graph DOS and the 27-point recurrence rate")
     ap.add_argument("--only-geneig", action="store_true",
                     help="time Algorithm 4 alone at N_v = 80, 128, 256 and print that JSON only")
+    ap.add_argument("--only-stencil27", action="store_true",
+                    help="time the 27-point lattice's recurrence alone (degree 400, 8 points) and print "
+                         "that JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with a plain 1 GiB device-to-device copy (a known-size kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -292,7 +295,7 @@ def main():
     # the oracle's baseline first: its process pool forks before anything touches the GPU
     baseline = None
     oracle_small = None
-    if not args.no_cpu_baseline and not args.only_geneig:
+    if not args.no_cpu_baseline and not args.only_geneig and not args.only_stencil27:
         log("timing the oracle on a bounded sample on the host cores ...")
         t0 = time.time()
         baseline = cpu_baseline(2)
@@ -316,6 +319,11 @@ def main():
         torch.cuda.empty_cache()
     if args.only_geneig:
         print(json.dumps({"geneig": geneig_scaling(S, torch, dev)}), flush=True)
+        return
+    if args.only_stencil27:
+        free, _ = torch.cuda.mem_get_info()
+        print(json.dumps({"stencil27_recurrence": stencil27_recurrence(S, WL, torch, dev,
+                                                                        int(free - 12 * (1 << 30)))}), flush=True)
         return
     t0 = time.time()
     wl = WL.make_workload(2)
@@ -497,6 +505,31 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def stencil27_recurrence(S, WL, torch, dev, budget):
+    """The 27-point 128^3 lattice (N_v = 256) at degree 400 and eight sweep points: two ssm_dos
+    calls, the second's recurrence timed (us per step, GB/s on compulsory bytes)."""
+    wl = WL.make_workload(5, degree=400)
+    t = wl.t[wl.nt // 16::wl.nt // 8]
+    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
+    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=t, precision="bf16x3",
+                seed=wl.seed, budget=budget, lattice=wl.lattice, device=dev)
+    ctx.dos()
+    ctx.dos()
+    st = ctx.stats()
+    ctx.close()
+    del ctx, csr
+    torch.cuda.empty_cache()
+    comp, _ = spmm_bytes_models(wl.a.n, wl.a.nnz, wl.nv, 4)
+    us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
+    out = {"workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv,
+           "kernel": "box_step_kernel" if st["box_stencil"] else "cheb_step_kernel",
+           "steps": st["spmm_launches"], "us_per_step": us, "bytes_compulsory": comp,
+           "GBps_compulsory": comp / (us * 1e-6) / 1e9,
+           "frac_hbm": comp / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+    log(f"27-point recurrence: {us:.0f} us per step, {out['GBps_compulsory']:.0f} GB/s")
+    return out
+
+
 def large_workloads(S, WL, torch, dev, budget_left):
     """The random-graph workload's whole DOS (split-BF16 sweep, sweep-point batches as
     planned in the free memory; its DOS against the stored oracle values when present), and
@@ -552,25 +585,7 @@ def large_workloads(S, WL, torch, dev, budget_left):
                       "moments_and_sums": st["ms_sweep"], "geneig": st["ms_geneig"]}}
     log(f"random graph, RESS-DGC FP32: {s_res:.2f} s per DOS")
 
-    wl = WL.make_workload(5, degree=400)
-    t = wl.t[wl.nt // 16::wl.nt // 8]
-    csr = S.DeviceCSR.from_csr(wl.a, dtype=torch.float32, device=dev)
-    ctx = S.SSM(csr, lo=wl.lo, hi=wl.hi, sigma=wl.sigma, nv=wl.nv, degree=wl.degree, t=t, precision="bf16x3",
-                seed=wl.seed, budget=budget_left(12), lattice=wl.lattice, device=dev)
-    ctx.dos()
-    ctx.dos()
-    st = ctx.stats()
-    ctx.close()
-    del ctx, csr
-    torch.cuda.empty_cache()
-    comp, _ = spmm_bytes_models(wl.a.n, wl.a.nnz, wl.nv, 4)
-    us = st["ms_recurrence"] * 1e3 / st["spmm_launches"]
-    res["stencil27_recurrence"] = {"workload": wl.name, "n": wl.a.n, "nnz": wl.a.nnz, "nv": wl.nv,
-                                   "kernel": "box_step_kernel" if st["box_stencil"] else "cheb_step_kernel",
-                                   "steps": st["spmm_launches"], "us_per_step": us,
-                                   "GBps_compulsory": comp / (us * 1e-6) / 1e9,
-                                   "frac_hbm": comp / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
-    log(f"27-point recurrence: {us:.0f} us per step, {res['stencil27_recurrence']['GBps_compulsory']:.0f} GB/s")
+    res["stencil27_recurrence"] = stencil27_recurrence(S, WL, torch, dev, budget_left(12))
     # its whole DOS (M = 4000, N_t = 4000) by RESS-DGC with an FP32 recurrence: SS-DGC would
     # need about 36 sweep-point batches, each replaying the 4000 steps
     wl = WL.make_workload(5)
